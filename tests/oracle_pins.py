@@ -1,0 +1,449 @@
+"""Pins of the FP64 oracle against facts fixed outside the oracle.
+
+Each ``pin_*`` function takes an ``oracle.Oracle`` and raises
+``AssertionError`` when the oracle disagrees with a closed form, an exact
+rational evaluation, a hand-worked fixture (``tests/golden``) or an invariant
+that the paper's mathematics fixes.  ``test_oracle_pins.py`` runs them on the
+real oracle; ``test_oracle_mutants.py`` runs them on copies of the oracle with
+a planted mistake and requires that some pin fails.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+import exact
+from oracle import pack_bits, unpack_bits
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name: str) -> dict:
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _rng(salt):
+    return np.random.default_rng(1234 + salt)
+
+
+def small_int_convex(rng, n, scale=20):
+    """Convex polygon with small-integer vertices (CCW): a random convex hull."""
+    for _ in range(1000):
+        pts = rng.integers(-scale, scale + 1, size=(4 * n, 2))
+        hull = _hull(pts)
+        if len(hull) >= 3:
+            return np.array(hull[:], dtype=np.float64)
+    raise RuntimeError("no hull")
+
+
+def _hull(pts):
+    pts = sorted(set(map(tuple, pts.tolist())))
+    if len(pts) < 3:
+        return pts
+
+    def cross(o, a, b):
+        return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+    lower, upper = [], []
+    for p in pts:
+        while len(lower) >= 2 and cross(lower[-2], lower[-1], p) <= 0:
+            lower.pop()
+        lower.append(p)
+    for p in reversed(pts):
+        while len(upper) >= 2 and cross(upper[-2], upper[-1], p) <= 0:
+            upper.pop()
+        upper.append(p)
+    return lower[:-1] + upper[:-1]
+
+
+# ---------------------------------------------------------------------------
+# Section 3: centroid and generators
+# ---------------------------------------------------------------------------
+def pin_square_and_triangle(o):
+    sq = golden("unit_square.json")
+    V = np.array(sq["vertices_ccw"], dtype=float)
+    g0, area, rc = o.centroid(V)
+    assert rc == 0 and area == sq["area_ccw"] and list(g0) == sq["centroid"]
+    P, rc = o.generators(V)
+    assert rc == 0 and P.tolist() == sq["generators_ccw"], P
+    g0, area, _ = o.centroid(V[::-1])
+    assert area == -1.0 and list(g0) == sq["centroid"]          # CW: signed area
+    tri = golden("triangle.json")
+    V = np.array(tri["vertices"], dtype=float)
+    g0, area, _ = o.centroid(V)
+    assert area == tri["area"] and list(g0) == tri["centroid"]
+    P, _ = o.generators(V)
+    assert P.tolist() == tri["generators"], P
+
+
+def pin_regular_ngon(o):
+    """Regular n-gon of radius R: area (n/2) R^2 sin(2 pi/n), centroid at the
+    centre, generator of edge j at distance 2 R cos(pi/n) from the centre at
+    the mid-angle of the edge."""
+    for n in (3, 5, 8, 13, 64):
+        R = 2.5
+        th = 2 * math.pi * np.arange(n) / n
+        V = np.stack([R * np.cos(th), R * np.sin(th)], 1)
+        g0, area, _ = o.centroid(V)
+        assert abs(area - 0.5 * n * R * R * math.sin(2 * math.pi / n)) < 1e-12 * R * R
+        assert np.all(np.abs(g0) < 1e-14 * R)
+        P, _ = o.generators(V)
+        for j in range(n):
+            mid = th[j] - math.pi / n          # edge j runs v_{j-1} -> v_j
+            want = 2 * R * math.cos(math.pi / n) * np.array([math.cos(mid), math.sin(mid)])
+            assert np.allclose(P[1 + j], want, rtol=0, atol=1e-13 * R), (n, j)
+
+
+def pin_generators_exact_rational(o):
+    """Random small-integer convex polygons: float64 centroid and generators
+    agree with exact rationals to a few units in the last place."""
+    rng = _rng(1)
+    for t in range(30):
+        V = small_int_convex(rng, 6 + t % 5)
+        if t % 3 == 2:
+            V = V[::-1].copy()
+        Pe = exact.generators(V.tolist())
+        P, rc = o.generators(V)
+        assert rc == 0
+        scale = np.abs(V).max() + 1
+        for (ex, ey), (fx, fy) in zip(Pe, P):
+            assert abs(float(ex) - fx) <= 1e-13 * scale and abs(float(ey) - fy) <= 1e-13 * scale
+
+
+def pin_generator_invariants(o):
+    """Eq. 2: every point of edge i is equidistant from p_0 and p_i; Eq. 6:
+    the midpoint of p_0 p_i lies on edge line i and p_i - p_0 is
+    perpendicular to it; |p_i - p_0| = 2 dist(p_0, line i)."""
+    rng = _rng(2)
+    for t in range(20):
+        n = int(rng.integers(3, 20))
+        c = rng.uniform(-5, 5, 2)
+        V = W.circle_polygon(n, float(rng.uniform(0.1, 10)), c, rng)
+        P, _ = o.generators(V)
+        g0 = P[0]
+        for i in range(n):
+            a, b = V[i - 1], V[i]
+            e = b - a
+            gi = P[1 + i]
+            h = gi - g0
+            L = np.hypot(*e)
+            scale = np.abs(V).max() ** 2 + 1
+            for s in (0.0, 0.25, 0.5, 1.0):
+                x = a + s * e
+                d0 = np.sum((x - g0) ** 2)
+                di = np.sum((x - gi) ** 2)
+                assert abs(d0 - di) <= 1e-12 * scale
+            mid = 0.5 * (g0 + gi)
+            assert abs(e[0] * (mid[1] - a[1]) - e[1] * (mid[0] - a[0])) <= 1e-12 * scale
+            assert abs(np.dot(h, e)) <= 1e-12 * scale
+            dist = abs(e[0] * (g0[1] - a[1]) - e[1] * (g0[0] - a[0])) / L
+            assert abs(np.hypot(*h) - 2 * dist) <= 1e-12 * math.sqrt(scale)
+
+
+def pin_degenerate_status(o):
+    _, rc = o.generators(np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]]))
+    assert rc == -1                       # zero area
+    _, rc = o.generators(np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 0.0], [0.0, 1.0]]))
+    assert rc == -2                       # zero-length edge
+
+
+# ---------------------------------------------------------------------------
+# Algorithms 1, 2, 5 on exact inputs
+# ---------------------------------------------------------------------------
+def pin_unit_square_grid(o):
+    sq = golden("unit_square.json")
+    G = W.dyadic_grid(sq["grid"]["lo"], sq["grid"]["hi"], sq["grid"]["k"])
+    V = np.array(sq["vertices_ccw"], dtype=float)
+    want = sq["grid_inside_counts"]
+    for orient, VV in (("ccw", V), ("cw", V[::-1].copy())):
+        assert int(o.voronoi(VV, G).sum()) == want["voronoi"][orient]
+        assert int(o.sign_of_offset(VV, G).sum()) == want["sign_of_offset"][orient]
+        assert int(o.ray_crossing(VV, G).sum()) == want["ray_crossing"][orient]
+    # the 81 Voronoi points are exactly the closed square, the 64 ray
+    # crossing points exactly [0,1)^2
+    vin = o.voronoi(V, G)
+    closed = (G[:, 0] >= 0) & (G[:, 0] <= 1) & (G[:, 1] >= 0) & (G[:, 1] <= 1)
+    assert np.array_equal(vin, closed)
+    half = (G[:, 0] >= 0) & (G[:, 0] < 1) & (G[:, 1] >= 0) & (G[:, 1] < 1)
+    assert np.array_equal(o.ray_crossing(V, G), half)
+
+
+def pin_exact_rational_labels(o):
+    """Small-integer polygons, dyadic points: all three float64 tests equal
+    the exact-rational evaluation of the same algorithm, and the exact
+    Voronoi predicate equals the closed half-plane definition of the convex
+    polygon (brute force), whenever the point is not within float64 reach of
+    the boundary.  Points exactly on a vertex or edge are included: the exact
+    Voronoi answer there is 'inside'."""
+    rng = _rng(3)
+    checked = 0
+    for t in range(12):
+        V = small_int_convex(rng, 5 + t % 4, scale=8)
+        if t % 2:
+            V = V[::-1].copy()
+        Pe = exact.generators(V.tolist())
+        pts = rng.integers(-40, 41, size=(150, 2)) / 4.0
+        pts = np.concatenate([pts, V, 0.5 * (V + np.roll(V, 1, 0))])
+        vor = o.voronoi(V, pts)
+        soo = o.sign_of_offset(V, pts)
+        ray = o.ray_crossing(V, pts)
+        P, _ = o.generators(V)
+        Pf = [(float(x), float(y)) for x, y in Pe]
+        for k, p in enumerate(pts.tolist()):
+            ve = exact.voronoi(V.tolist(), p, Pe)
+            assert ve == exact.convex_contains(V.tolist(), p)
+            margins = exact.voronoi_margins(Pe, p)
+            mmax = max(margins)
+            # float64 error of the oracle's squared distances, generously
+            r2 = max((p[0] - gx) ** 2 + (p[1] - gy) ** 2 for gx, gy in Pf)
+            gen_err = 1e-12 * (np.abs(V).max() + abs(p[0]) + abs(p[1]) + 1) ** 2
+            if abs(float(mmax)) > 1e-13 * r2 + gen_err:
+                assert bool(vor[k]) == ve, (t, p)
+            assert bool(soo[k]) == exact.sign_of_offset(V.tolist(), p), (t, p)
+            assert bool(ray[k]) == exact.ray_crossing(V.tolist(), p), (t, p)
+            checked += 1
+        # generators in float64 match the exact ones closely
+        assert np.allclose(P, np.array(Pf), rtol=0, atol=1e-12 * (np.abs(V).max() + 1))
+    assert checked > 1000
+
+
+def pin_three_tests_agree_away_from_edges(o):
+    """The paper's own correctness experiment (Section 6.1): on random points
+    around a polygon the Voronoi labels equal sign-of-offset labels; ray
+    crossing agrees too.  Points within 1e-9 of an edge line are skipped
+    (boundary conventions differ there by design)."""
+    rng = _rng(4)
+    for t in range(6):
+        n = int(rng.integers(3, 16))
+        V = W.circle_polygon(n, 1.0, rng.uniform(-0.1, 0.1, 2), rng)
+        if t % 2:
+            V = V[::-1].copy()
+        Q = rng.uniform(-1.5, 1.5, size=(20000, 2))
+        Wv = np.roll(V, 1, 0)
+        e = V - Wv
+        L = np.hypot(e[:, 0], e[:, 1])
+        d = np.abs((e[None, :, 0] * (Q[:, None, 1] - Wv[None, :, 1]) -
+                    e[None, :, 1] * (Q[:, None, 0] - Wv[None, :, 0])) / L[None, :])
+        far = d.min(axis=1) > 1e-9
+        a, b, c = o.voronoi(V, Q), o.sign_of_offset(V, Q), o.ray_crossing(V, Q)
+        assert np.array_equal(a[far], b[far]) and np.array_equal(a[far], c[far])
+        assert 0.1 < a.mean() < 0.6
+
+
+def pin_label_invariants(o):
+    """Labels are invariant under translation and 90-degree rotation for
+    points off the edge lines, convex combinations of vertices with
+    weights >= 1e-3 are inside, and reflecting an interior point across an
+    edge line (landing >= 1e-9 from it) gives an outside point."""
+    rng = _rng(5)
+    for t in range(8):
+        V = small_int_convex(rng, 7, scale=16)
+        Q = rng.integers(-80, 81, size=(2000, 2)) / 4.0
+        base = o.voronoi(V, Q)
+        # the centroid divides by 6A, so generators are rounded: points on an
+        # edge line may flip under a motion; compare the rest
+        far = _min_edge_dist(V, Q) > 1e-9
+        sh = np.array([64.0, -32.0])
+        assert np.array_equal(base[far], o.voronoi(V + sh, Q + sh)[far])
+        rot = lambda A: np.stack([-A[:, 1], A[:, 0]], 1)
+        assert np.array_equal(base[far], o.voronoi(rot(V), rot(Q))[far])
+        wts = rng.uniform(1e-3, 1.0, size=(500, len(V)))
+        wts /= wts.sum(1, keepdims=True)
+        inner = wts @ V
+        for test in (o.voronoi, o.sign_of_offset, o.ray_crossing):
+            assert test(V, inner).all()
+        i = int(rng.integers(len(V)))
+        a, b = V[i - 1], V[i]
+        e = (b - a) / np.hypot(*(b - a))
+        nrm = np.array([e[1], -e[0]])
+        dist = (inner - a) @ nrm
+        refl = inner - 2 * dist[:, None] * nrm[None, :]
+        keep = np.abs(dist) > 1e-9
+        assert not o.voronoi(V, refl[keep]).any()
+        assert not o.sign_of_offset(V, refl[keep]).any()
+        assert not o.ray_crossing(V, refl[keep]).any()
+
+
+def pin_nonfinite_points(o):
+    V = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], dtype=float)
+    Q = np.array([[np.nan, 0.5], [0.5, np.inf], [-np.inf, 0.5], [0.5, 0.5]])
+    assert o.voronoi(V, Q).tolist() == [False, False, False, True]
+
+
+def pin_max_margin(o):
+    """The largest margin is <= 0 exactly for the inside points and equals
+    the exact rational max margin on dyadic data."""
+    rng = _rng(6)
+    V = small_int_convex(rng, 6, scale=8)
+    Q = rng.integers(-40, 41, size=(300, 2)) / 4.0
+    mm = o.voronoi_max_margin(V, Q)
+    assert np.array_equal(mm <= 0, o.voronoi(V, Q))
+    Pe = exact.generators(V.tolist())
+    for k, p in enumerate(Q.tolist()):
+        want = float(max(exact.voronoi_margins(Pe, p)))
+        assert abs(want - mm[k]) <= 1e-11 * (1 + abs(p[0]) + abs(p[1])) ** 2 * 64
+
+
+# ---------------------------------------------------------------------------
+# poses, all pairs
+# ---------------------------------------------------------------------------
+def pin_pose_polygon(o):
+    F = W.car_footprint()
+    Wp = o.pose_polygon(F, 3.0, -2.0, 0.0, 1.0)            # theta = pi/2
+    assert np.array_equal(Wp, np.stack([-F[:, 1] + 3.0, F[:, 0] - 2.0], 1))
+    Wp = o.pose_polygon(F, 0.5, 0.25, 1.0, 0.0)
+    assert np.array_equal(Wp, F + np.array([0.5, 0.25]))
+
+
+def pin_allpairs(o):
+    F = W.car_footprint()
+    rng = _rng(7)
+    K = 6
+    xy = rng.uniform(-3, 3, size=(K, 2))
+    th = rng.uniform(-math.pi, math.pi, K)
+    cs = np.stack([np.cos(th), np.sin(th)], 1)
+    Q = rng.uniform(-6, 6, size=(1000, 2))
+    bits, counts = o.allpairs(F, xy, cs, Q)
+    for k in range(K):
+        # inside the rotated, shifted footprint == inside the footprint after
+        # undoing the motion (brute force half-plane test, away from edges)
+        d = Q - xy[k]
+        body = np.stack([cs[k, 0] * d[:, 0] + cs[k, 1] * d[:, 1],
+                         -cs[k, 1] * d[:, 0] + cs[k, 0] * d[:, 1]], 1)
+        lab = unpack_bits(bits[k], len(Q))
+        inside = np.array([exact.convex_contains(F.tolist(), p) for p in body.tolist()])
+        ok = _min_edge_dist(F, body) > 1e-9
+        assert np.array_equal(lab[ok], inside[ok])
+        assert counts[k] == lab.sum()
+        assert np.array_equal(bits[k], pack_bits(lab))
+
+
+def _min_edge_dist(V, Q):
+    Wv = np.roll(V, 1, 0)
+    e = V - Wv
+    L = np.hypot(e[:, 0], e[:, 1])
+    d = np.abs((e[None, :, 0] * (Q[:, None, 1] - Wv[None, :, 1]) -
+                e[None, :, 1] * (Q[:, None, 0] - Wv[None, :, 0])) / L[None, :])
+    return d.min(axis=1)
+
+
+# ---------------------------------------------------------------------------
+# collision cost and its gradient
+# ---------------------------------------------------------------------------
+def _footprint(spec):
+    return W.car_footprint() if spec == "car" else np.array(spec, dtype=float)
+
+
+def pin_cost_fixtures(o):
+    for case in golden("collision_cost.json")["cases"]:
+        F = _footprint(case["footprint"])
+        c = o.cost(F, np.array([case["pose"]]), np.array(case["points"], dtype=float))
+        assert abs(c[0] - case["cost"]) < 1e-12, (case, c)
+
+
+def pin_cost_rigid_invariance(o):
+    """Moving the points and the pose by the same rigid motion leaves the
+    cost unchanged."""
+    rng = _rng(8)
+    F = W.car_footprint()
+    Q = rng.uniform(-4, 4, size=(3000, 2))
+    pose = np.array([[0.3, -0.2, 0.4]])
+    c0 = o.cost(F, pose, Q)[0]
+    a = 0.7
+    R = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+    t = np.array([5.0, -3.0])
+    Q2 = Q @ R.T + t
+    p2 = np.array([[*(R @ pose[0, :2] + t), pose[0, 2] + a]])
+    c1 = o.cost(F, p2, Q2)[0]
+    assert c0 > 0 and abs(c0 - c1) < 1e-10 * max(1.0, c0)
+
+
+def _fd_cost(o, F, poses, Q, h=1e-6):
+    """Central differences of the oracle cost; entries whose (active,
+    argmin) state changes between +h and -h are marked invalid."""
+    K = len(poses)
+    gp = np.zeros((K, 3))
+    okp = np.ones((K, 3), dtype=bool)
+    for k in range(K):
+        for d in range(3):
+            pp = poses[k].copy()
+            pm = poses[k].copy()
+            pp[d] += h
+            pm[d] -= h
+            cp = o.cost(F, pp[None], Q)[0]
+            cm = o.cost(F, pm[None], Q)[0]
+            gp[k, d] = (cp - cm) / (2 * h)
+            okp[k, d] = np.array_equal(o.cost_state(F, pp, Q), o.cost_state(F, pm, Q))
+    gF = np.zeros_like(F)
+    okF = np.ones(F.shape, dtype=bool)
+    for i in range(len(F)):
+        for d in range(2):
+            Fp = F.copy()
+            Fm = F.copy()
+            Fp[i, d] += h
+            Fm[i, d] -= h
+            gF[i, d] = (o.cost(Fp, poses, Q).sum() - o.cost(Fm, poses, Q).sum()) / (2 * h)
+            okF[i, d] = all(np.array_equal(o.cost_state(Fp, poses[k], Q),
+                                           o.cost_state(Fm, poses[k], Q)) for k in range(K))
+    return gp, okp, gF, okF
+
+
+def pin_cost_gradient_fd(o):
+    """The closed-form reference gradient matches float64 central finite
+    differences (h = 1e-6) of the cost to pose and to footprint vertices."""
+    rng = _rng(9)
+    F = W.car_footprint()
+    Q = rng.uniform(-3, 3, size=(400, 2))
+    poses = np.stack([rng.uniform(-0.5, 0.5, 4), rng.uniform(-0.5, 0.5, 4),
+                      rng.uniform(-math.pi, math.pi, 4)], 1)
+    gp, gF = o.cost_grad(F, poses, Q)
+    fp, okp, fF, okF = _fd_cost(o, F, poses, Q)
+    assert okp.sum() >= 10 and okF.sum() >= 12
+    assert np.all(np.abs(gp - fp)[okp] <= 1e-5 * (1 + np.abs(fp)[okp]))
+    assert np.all(np.abs(gF - fF)[okF] <= 1e-5 * (1 + np.abs(fF)[okF]))
+    # weighted form: w scales pose rows and the footprint sum
+    w = rng.uniform(0.5, 2.0, len(poses))
+    gpw, gFw = o.cost_grad(F, poses, Q, w)
+    assert np.allclose(gpw, gp * w[:, None], rtol=1e-12, atol=1e-12)
+    gF_sum = sum(o.cost_grad(F, poses[k:k + 1], Q, w[k:k + 1])[1] for k in range(len(poses)))
+    assert np.allclose(gFw, gF_sum, rtol=1e-10, atol=1e-10)
+
+
+def pin_cost_gradient_cw(o):
+    """A clockwise footprint describes the same set: same cost, same pose
+    gradient, and the vertex gradient permuted with the vertex order."""
+    rng = _rng(10)
+    F = W.car_footprint()
+    Fcw = F[::-1].copy()
+    Q = rng.uniform(-3, 3, size=(500, 2))
+    poses = np.array([[0.1, 0.2, 0.3], [-0.2, 0.1, -1.0]])
+    assert np.allclose(o.cost(F, poses, Q), o.cost(Fcw, poses, Q), rtol=1e-12, atol=1e-12)
+    gp, gF = o.cost_grad(F, poses, Q)
+    gp2, gF2 = o.cost_grad(Fcw, poses, Q)
+    assert np.allclose(gp, gp2, rtol=1e-9, atol=1e-9)
+    assert np.allclose(gF, gF2[::-1], rtol=1e-9, atol=1e-9)
+
+
+ALL_PINS = [
+    pin_square_and_triangle,
+    pin_regular_ngon,
+    pin_generators_exact_rational,
+    pin_generator_invariants,
+    pin_degenerate_status,
+    pin_unit_square_grid,
+    pin_exact_rational_labels,
+    pin_three_tests_agree_away_from_edges,
+    pin_label_invariants,
+    pin_nonfinite_points,
+    pin_max_margin,
+    pin_pose_polygon,
+    pin_allpairs,
+    pin_cost_fixtures,
+    pin_cost_rigid_invariance,
+    pin_cost_gradient_fd,
+    pin_cost_gradient_cw,
+]
