@@ -1,0 +1,237 @@
+"""Throughput of the Voronoi point-inclusion path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--points M]
+
+Workload (one "step"): the streaming sweep -- six convex polygons with 3, 4,
+8, 16, 32 and 64 vertices on a circle of radius 1, each tested against its
+own 2^28 float32 points uniform in [-1.5, 1.5]^2 of which 1% lie within 1e-6
+of an edge.  Each polygon is one call of the C ABI's pip_voronoi (binary64
+generator derivation, float32 screen with proven band, binary64 recheck,
+packed labels), all on one stream with the inputs resident in HBM.
+
+Prints one JSON line: whole-step throughput in G point-polygon tests/s, the
+roofline of the dominant kernel (measured with HIP events on the launch
+stream), per-polygon figures, sign-of-offset and float32-only kernels for
+comparison, label mismatches against the FP64 oracle on a sample, and the
+oracle's own throughput on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (dense)
+BYTES_PER_TEST = 8.125         # float2 point in + 1 label bit out
+NS = (3, 4, 8, 16, 32, 64)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2007_15385_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    e = d.get("kernels", {}).get(kernel_key)
+    return None if e is None else float(e["bytes_per_launch"])
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--points", type=int, default=1 << 28, help="points per polygon")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 26,
+                    help="points per polygon for the oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
+              "multi-GPU form in this build", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2007_15385_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.load_library()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m = int(args.points)
+
+    # ---- inputs, resident in HBM -----------------------------------------
+    t0 = time.time()
+    polys, pts, labels = {}, {}, {}
+    host_q = {}
+    for n in NS:
+        V = W.streaming_polygon(n)
+        Q = W.streaming_points(V, m)
+        polys[n] = torch.from_numpy(V).to(dev)
+        pts[n] = torch.from_numpy(Q).to(dev)
+        labels[n] = torch.empty((m + 31) // 32, dtype=torch.int32, device=dev)
+        host_q[n] = (V, Q[: args.cpu_sample].copy())
+        del Q
+        print(f"[bench] inputs n={n} ready ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    def step():
+        for n in NS:
+            P.pip_voronoi(polys[n], pts[n], labels[n])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- timed region: K steps, per-launch HIP events on the launch stream --
+    stream = torch.cuda.current_stream(dev)
+    ev = {n: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)] for n in NS}
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for k in range(args.steps):
+        for n in NS:
+            a, b = ev[n][k]
+            a.record(stream)
+            P.pip_voronoi(polys[n], pts[n], labels[n])
+            b.record(stream)
+    end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    ms_per_step = total_ms / args.steps
+    per_n_ms = {n: float(np.mean([a.elapsed_time(b) for a, b in ev[n]])) for n in NS}
+    tests_per_step = m * len(NS)
+    value = tests_per_step / (ms_per_step * 1e-3) / 1e9
+    print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
+
+    kernels = []
+    for n in NS:
+        t = per_n_ms[n] * 1e-3
+        gbs = BYTES_PER_TEST * m / t / 1e9
+        tfl = 4.0 * n * m / t / 1e12
+        kernels.append({"n": n, "ms": round(per_n_ms[n], 4), "gtests_per_s": round(m / t / 1e9, 2),
+                        "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                        "fp32_tflops": round(tfl, 2),
+                        "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)})
+    dom = max(kernels, key=lambda r: r["ms"])
+    # binding roofline of the dominant launch: bytes vs flops at peak
+    t_hbm = BYTES_PER_TEST * m / (HBM_PEAK_GBS * 1e9)
+    t_alu = 4.0 * dom["n"] * m / (FP32_VALU_PEAK_TFLOPS * 1e12)
+    if t_alu > t_hbm:
+        roof = {"bound": "alu", "achieved": dom["fp32_tflops"], "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": dom["fp32_frac"]}
+    else:
+        roof = {"bound": "hbm", "achieved": dom["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["hbm_frac"]}
+    roof["kernel"] = f"k_stream<voronoi,float32> n={dom['n']}"
+    roof["traffic"] = traffic_for(f"voronoi_f32_n{dom['n']}")
+    roof["algorithmic_per_launch"] = ({"flop": 4.0 * dom["n"] * m} if roof["bound"] == "alu"
+                                      else {"bytes": BYTES_PER_TEST * m})
+
+    # ---- comparison kernels (outside the timed step) -----------------------
+    def time_fn(fn, n, reps=3):
+        fn(polys[n], pts[n], labels[n])
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn(polys[n], pts[n], labels[n])
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    soo = {n: time_fn(P.pip_sign_of_offset, n) for n in NS}
+    plain = {n: time_fn(P.pip_voronoi_fp32_plain, n) for n in NS}
+    comparisons = {
+        "sign_of_offset_gtests_per_s": round(tests_per_step / (sum(soo.values()) * 1e-3) / 1e9, 2),
+        "sign_of_offset_ms": {str(n): round(v, 4) for n, v in soo.items()},
+        "fp32_plain_gtests_per_s": round(tests_per_step / (sum(plain.values()) * 1e-3) / 1e9, 2),
+        "fp32_plain_ms": {str(n): round(v, 4) for n, v in plain.items()},
+    }
+
+    # ---- parity on a sample + oracle baseline ------------------------------
+    mismatches = None
+    plain_mismatches = None
+    cpu = None
+    if not args.no_cpu:
+        from oracle import Oracle, pack_bits
+        o = Oracle()
+        S = int(args.cpu_sample)
+        cpu_t = 0.0
+        mismatches = 0
+        plain_mismatches = 0
+        for n in NS:
+            V, Qs = host_q[n]
+            Q64 = Qs.astype(np.float64)
+            c0 = time.perf_counter()
+            want = o.voronoi(V, Q64)
+            cpu_t += time.perf_counter() - c0
+            P.pip_voronoi(polys[n], pts[n], labels[n])
+            got = labels[n][: (S + 31) // 32].cpu().numpy().view(np.uint32)
+            mismatches += int(np.unpackbits((got ^ pack_bits(want)).view(np.uint8)).sum())
+            P.pip_voronoi_fp32_plain(polys[n], pts[n], labels[n])
+            got = labels[n][: (S + 31) // 32].cpu().numpy().view(np.uint32)
+            plain_mismatches += int(np.unpackbits((got ^ pack_bits(want)).view(np.uint8)).sum())
+        cpu = {"value": round(S * len(NS) / cpu_t / 1e9, 5), "unit": "G tests/s",
+               "cores": o.num_threads(), "kind": "oracle",
+               "sample": f"first {S} points of each of the 6 polygons' arrays "
+                         f"({S * len(NS)} tests), FP64 C oracle, OpenMP over points",
+               "seconds": round(cpu_t, 2)}
+        comparisons["fp32_plain_mismatches_on_sample"] = plain_mismatches
+
+    out = {
+        "metric": "G point-polygon tests/s (Voronoi, certified float32 screen + binary64 "
+                  "recheck, labels bit-identical to the FP64 oracle)",
+        "value": round(value, 2),
+        "unit": "G tests/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "streaming sweep: convex polygons with n = 3,4,8,16,32,64 "
+                               "vertices (radius 1, centre in [-0.1,0.1]^2), each against "
+                               f"{m} float32 points in [-1.5,1.5]^2, 1% within 1e-6 of an edge",
+                   "points_per_polygon": m, "polygons": list(NS), "point_dtype": "float32"},
+        "mismatches_on_sample": mismatches,
+        "roofline": roof,
+        "kernels": kernels,
+        "comparisons": comparisons,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

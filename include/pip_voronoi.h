@@ -1,0 +1,147 @@
+/*
+ * pip_voronoi.h -- C ABI of the MI355X (gfx950) point-inclusion library.
+ *
+ * The library implements the point-in-convex-polygon test of R. S. Zengin and
+ * V. Sezer, "A Novel Point Inclusion Test for Convex Polygons Based on
+ * Voronoi Tessellations" (arXiv:2007.15385), and the two reference tests the
+ * paper compares it with:
+ *   - Voronoi inclusion (Section 4, Eq. 1 and 9-11, Algorithm 5): the polygon
+ *     is converted once into an inner generator p_0 (its centroid, Section 3,
+ *     Eq. 3-4, Algorithm 3) and one outer generator per edge (p_0 mirrored
+ *     across the edge line, Section 3, Eq. 5-8, Algorithm 4); a point is
+ *     inside iff it is no farther from p_0 than from every outer generator;
+ *   - sign of offset (Section 2.2, Algorithm 2), convex polygons;
+ *   - ray crossing (Section 2.1, Algorithm 1), any simple polygon.
+ *
+ * Conventions shared by every entry point
+ *   - Polygons: binary64 vertices v_0..v_{n-1}, interleaved x,y ([n][2]), in
+ *     cyclic order, either orientation.  Edge i runs from v_{i-1} to v_i
+ *     (v_{-1} = v_{n-1}), the paper's rolled vertex matrix.  3 <= n <= 64.
+ *   - Query points: interleaved x,y ([m][2]) as float32 (PIP_F32, 8-byte
+ *     aligned) or binary64 (PIP_F64, 16-byte aligned).
+ *   - Labels: ceil(m/32) little-endian 32-bit words, 4-byte aligned; bit
+ *     (k mod 32) of word floor(k/32) is point k, 1 = inside.  Bits past m are
+ *     written as 0.  A point with a non-finite coordinate is outside.
+ *   - Exactness: every label equals the result of the paper's algorithm
+ *     evaluated in IEEE binary64 in the order written (no fused
+ *     multiply-add), with float32 query points widened exactly.  The
+ *     Voronoi test keeps the closed boundary of Eq. 1, sign of offset the
+ *     strict comparison of Algorithm 2, ray crossing the half-open rule of
+ *     Algorithm 1 with odd parity meaning inside.
+ *   - Memory: every pointer argument is a DEVICE pointer unless stated; the
+ *     caller allocates and owns all buffers; the library frees nothing it did
+ *     not allocate.
+ *   - Streams: every compute call only enqueues work on `stream` (a
+ *     hipStream_t; NULL is the default stream) and returns; results are ready
+ *     when the stream has reached that point.
+ *   - Errors: argument errors are detected on the host before anything is
+ *     enqueued and returned as a pip_status; pip_last_error() then holds a
+ *     sentence naming the argument.  Data-dependent problems of a polygon
+ *     (non-finite vertex, zero area, zero-length edge, non-convex input) are
+ *     written as a pip_status value to the optional device `status` word; the
+ *     labels are still those of the binary64 algorithm for that input.
+ *   - Threads: a pip_ctx may be used from several host threads; calls that
+ *     share no output buffer may run concurrently on different streams.
+ */
+#ifndef PIP_VORONOI_H
+#define PIP_VORONOI_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PIP_OK = 0,
+    PIP_EINVAL = 1,        /* bad argument (host check) or non-finite vertex (device) */
+    PIP_EDEGENERATE = 2,   /* zero area or zero-length edge (device) */
+    PIP_ENONCONVEX = 3,    /* turn directions of the vertices are mixed (device) */
+    PIP_EHIP = 4,          /* a HIP runtime call failed; see pip_last_error() */
+    PIP_ENOMEM = 5,        /* device allocation failed */
+    PIP_EUNSUPPORTED = 6   /* valid request outside the compiled limits (n > 64) */
+} pip_status;
+
+typedef enum { PIP_F32 = 0, PIP_F64 = 1 } pip_dtype;
+
+#define PIP_MAX_EDGES 64
+
+typedef struct pip_ctx_s *pip_ctx;
+
+/* Create a context bound to HIP device `hip_device` (made current for the
+ * call).  *out receives the handle.  Returns PIP_EINVAL for a bad device
+ * index, PIP_EHIP if the device cannot be queried. */
+pip_status pip_create(int hip_device, pip_ctx *out);
+
+/* Destroy a context created by pip_create (NULL is ignored).  Work already
+ * enqueued is not waited for; callers synchronise their streams first. */
+void pip_destroy(pip_ctx ctx);
+
+/* Static English name of a status code. */
+const char *pip_status_str(pip_status s);
+
+/* Detail of the last error returned on this host thread (never NULL). */
+const char *pip_last_error(pip_ctx ctx);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int pip_version(void);
+
+/*
+ * Generators of one convex polygon (Section 3, Eq. 3-8, Algorithms 3-4).
+ *   V       [n][2] binary64 vertices.
+ *   P       [n+1][2] binary64 output: P[0] = p_0 (centroid, Eq. 4), P[1+i] =
+ *           outer generator of edge i (p_0 mirrored across the line through
+ *           v_{i-1} and v_i, Eq. 8).
+ *   status  optional [1] int32: PIP_OK / PIP_EINVAL / PIP_EDEGENERATE /
+ *           PIP_ENONCONVEX for this polygon.
+ * Bit-identical to the plain binary64 evaluation of Algorithms 3-4.
+ */
+pip_status polygon_to_generators(pip_ctx ctx, const double *V, int32_t n, double *P,
+                                 int32_t *status, hipStream_t stream);
+
+/*
+ * Voronoi point-inclusion test (Section 4, Algorithm 5) of m points against
+ * one convex polygon.  Q is [m][2] of type qdt; labels [ceil(m/32)] words;
+ * status optional [1].  The polygon's generators are derived on the device
+ * in binary64; margins are screened in float32 with a proven error band and
+ * the undecided points are re-decided in binary64.
+ */
+pip_status pip_voronoi(pip_ctx ctx, const double *V, int32_t n, const void *Q, pip_dtype qdt,
+                       int64_t m, uint32_t *labels, int32_t *status, hipStream_t stream);
+
+/* Sign-of-offset test (Section 2.2, Algorithm 2): inside iff every edge gives
+ * the same answer to LHS < RHS.  Same arguments and guarantees as
+ * pip_voronoi; status reports non-convex input. */
+pip_status pip_sign_of_offset(pip_ctx ctx, const double *V, int32_t n, const void *Q,
+                              pip_dtype qdt, int64_t m, uint32_t *labels, int32_t *status,
+                              hipStream_t stream);
+
+/* Ray-crossing test (Section 2.1, Algorithm 1) with a ray towards +x; the
+ * polygon may be any simple polygon (convexity is not required or checked).
+ * Evaluated directly in binary64. */
+pip_status pip_ray_crossing(pip_ctx ctx, const double *V, int32_t n, const void *Q,
+                            pip_dtype qdt, int64_t m, uint32_t *labels, int32_t *status,
+                            hipStream_t stream);
+
+/* The same Voronoi test evaluated entirely in float32 (generators derived in
+ * float32 in the global frame, label = largest margin <= 0), with no error
+ * band and no binary64 recheck.  A speed reference: its labels are NOT
+ * guaranteed to equal the binary64 algorithm near the boundary. */
+pip_status pip_voronoi_fp32_plain(pip_ctx ctx, const double *V, int32_t n, const void *Q,
+                                  pip_dtype qdt, int64_t m, uint32_t *labels, int32_t *status,
+                                  hipStream_t stream);
+
+/* Largest Voronoi margin per point, max_i (|p - p_0|^2 - |p - p_i|^2)
+ * (Eq. 11 rearranged; <= 0 inside), evaluated in float32 from the binary64
+ * generators in the polygon-local frame.  max_margin is [m] float32. */
+pip_status pip_voronoi_max_margin(pip_ctx ctx, const double *V, int32_t n, const void *Q,
+                                  pip_dtype qdt, int64_t m, float *max_margin, int32_t *status,
+                                  hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIP_VORONOI_H */

@@ -1,0 +1,25 @@
+"""Python binding of the MI355X point-inclusion library (``libpip_voronoi.so``).
+
+Argument marshalling only: every function takes torch tensors that already
+live on a ROCm device, checks their dtype/shape/contiguity, and passes the
+raw device pointers plus the current HIP stream to the C ABI declared in
+``include/pip_voronoi.h``.  Every step of every test runs in the library's
+HIP kernels; there is no CPU fallback.  If the library has not been built,
+or no GPU is present, the calls raise.
+
+The functions carry the C names: :func:`polygon_to_generators`,
+:func:`pip_voronoi`, :func:`pip_sign_of_offset`, :func:`pip_ray_crossing`,
+:func:`pip_voronoi_fp32_plain`, :func:`pip_voronoi_max_margin`.
+"""
+from __future__ import annotations
+
+from ._lib import (PIP_F32, PIP_F64, PipError, lib_path, load_library, num_label_words,
+                   status_name)
+from .api import (pip_ray_crossing, pip_sign_of_offset, pip_voronoi, pip_voronoi_fp32_plain,
+                  pip_voronoi_max_margin, polygon_to_generators, unpack_labels)
+
+__all__ = [
+    "PIP_F32", "PIP_F64", "PipError", "lib_path", "load_library", "num_label_words",
+    "status_name", "polygon_to_generators", "pip_voronoi", "pip_sign_of_offset",
+    "pip_ray_crossing", "pip_voronoi_fp32_plain", "pip_voronoi_max_margin", "unpack_labels",
+]

@@ -1,0 +1,82 @@
+"""ctypes loader for ``libpip_voronoi.so`` (no torch types cross this layer)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_NAME = "libpip_voronoi.so"
+
+PIP_F32 = 0
+PIP_F64 = 1
+
+STATUS_NAMES = {
+    0: "PIP_OK", 1: "PIP_EINVAL", 2: "PIP_EDEGENERATE", 3: "PIP_ENONCONVEX", 4: "PIP_EHIP",
+    5: "PIP_ENOMEM", 6: "PIP_EUNSUPPORTED",
+}
+
+
+def status_name(s: int) -> str:
+    return STATUS_NAMES.get(int(s), f"PIP_UNKNOWN({int(s)})")
+
+
+class PipError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = int(status)
+        super().__init__(f"{where}: {status_name(status)}: {detail}")
+
+
+def lib_path() -> str:
+    return os.environ.get("PIP_VORONOI_LIB", os.path.join(HERE, LIB_NAME))
+
+
+_c = ctypes
+_vp = _c.c_void_p
+_i32 = _c.c_int32
+_i64 = _c.c_int64
+_int = _c.c_int
+
+# name -> (restype, argtypes); pointers are passed as plain integers
+SIGNATURES = {
+    "pip_version": (_int, []),
+    "pip_create": (_int, [_int, _c.POINTER(_vp)]),
+    "pip_destroy": (None, [_vp]),
+    "pip_status_str": (_c.c_char_p, [_int]),
+    "pip_last_error": (_c.c_char_p, [_vp]),
+    "polygon_to_generators": (_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "pip_voronoi": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
+    "pip_sign_of_offset": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
+    "pip_ray_crossing": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
+    "pip_voronoi_fp32_plain": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
+    "pip_voronoi_max_margin": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
+}
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load_library(path: str | None = None) -> ctypes.CDLL:
+    """Load the HIP library (import torch first so that its HIP runtime is
+    the one the library binds to).  Raises if the library is missing."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or lib_path()
+        if not os.path.exists(p):
+            raise ImportError(
+                f"{p} not found: build the HIP library first "
+                "(python -m paper_2007_15385_amd.build); there is no CPU fallback")
+        lib = ctypes.CDLL(p)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def num_label_words(m: int) -> int:
+    return (int(m) + 31) // 32

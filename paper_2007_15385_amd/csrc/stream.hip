@@ -1,0 +1,387 @@
+// Single-polygon streaming kernels: one polygon, a very large point array.
+//
+// Each workgroup first derives the polygon's generators (Section 3) into LDS,
+// then every wave walks its own chunks of 256 points (4 per lane, lane l
+// holding points l, l+64, l+128, l+192 of the chunk, so each 8- or 16-byte
+// load of a wave covers one contiguous span of memory).  Results are packed
+// with wave ballots: the mask of slot j covers points [64 j, 64 j + 64) of
+// the chunk, i.e. two consecutive little-endian label words.
+//
+// Voronoi and sign of offset decide a point in float32 only when the margin
+// clears the proven band; the remaining points are queued per wave in LDS
+// and re-decided in binary64 (all 64 lanes busy) when the queue fills and at
+// the end.  A queued point's label bit is left 0 by the chunk's store and set
+// afterwards with an atomic OR by the same wave, after a fence.
+#include "device.hpp"
+#include "kernels.hpp"
+
+using namespace pipdev;
+
+namespace {
+
+template <typename PT>
+struct PointIO;
+
+template <>
+struct PointIO<float> {
+    using V2 = float2;
+    __device__ static float2 load(const void* Q, int64_t i) {
+        return static_cast<const float2*>(Q)[i];
+    }
+};
+
+template <>
+struct PointIO<double> {
+    using V2 = double2;
+    __device__ static double2 load(const void* Q, int64_t i) {
+        return static_cast<const double2*>(Q)[i];
+    }
+};
+
+// Loads of one chunk.  The loads are unconditional (indices past the end
+// are clamped to the last point, m >= 1), so the compiler can wait for
+// exactly the previous chunk's loads and keep this chunk's in flight while
+// the previous one is processed; out-of-range slots are masked later.
+template <typename PT>
+__device__ __forceinline__ void load_chunk(const void* Q, int64_t m, int64_t chunk, int lane,
+                                           PT (&x)[kPPL], PT (&y)[kPPL]) {
+    const int64_t last = m - 1;
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        int64_t idx = chunk * kChunk + lane + kWave * j;
+        idx = idx < last ? idx : last;
+        const auto p = PointIO<PT>::load(Q, idx);
+        x[j] = p.x;
+        y[j] = p.y;
+    }
+}
+
+// Local float32 coordinate: fl32(p - o).  For float32 input this is one
+// rounded float32 subtraction; for binary64 input the difference is taken
+// in binary64 and rounded once more to float32.
+__device__ __forceinline__ float to_local(float p, float o) { return p - o; }
+__device__ __forceinline__ float to_local(double p, float o) { return (float)(p - (double)o); }
+
+// Lane k (k < 8) stores label word k of the chunk.  The masks are
+// wave-uniform; a select tree on the lane's bits picks the word (plain
+// selects between scalar values, no per-lane array indexing).
+__device__ __forceinline__ void store_words(uint32_t* labels, int64_t base, int64_t nwords, int lane,
+                                            const uint64_t (&mask)[kPPL]) {
+    const uint32_t lo0 = (uint32_t)mask[0], hi0 = (uint32_t)(mask[0] >> 32);
+    const uint32_t lo1 = (uint32_t)mask[1], hi1 = (uint32_t)(mask[1] >> 32);
+    const uint32_t lo2 = (uint32_t)mask[2], hi2 = (uint32_t)(mask[2] >> 32);
+    const uint32_t lo3 = (uint32_t)mask[3], hi3 = (uint32_t)(mask[3] >> 32);
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    const uint32_t w0 = b0 ? hi0 : lo0, w1 = b0 ? hi1 : lo1;
+    const uint32_t w2 = b0 ? hi2 : lo2, w3 = b0 ? hi3 : lo3;
+    const uint32_t w01 = b1 ? w1 : w0, w23 = b1 ? w3 : w2;
+    const uint32_t w = b2 ? w23 : w01;
+    const int64_t widx = base / 32 + lane;
+    if (lane < kWordsPerChunk && widx < nwords) labels[widx] = w;
+}
+
+// Re-decide the queued points in binary64 and set the inside bits.
+//
+// Only the wave that owns a chunk ever writes its label words: first the
+// chunk store (undecided bits 0), later these ORs.  `s_waitcnt 0` makes the
+// wave wait until all of its own earlier stores are acknowledged by the L2
+// of its XCD, where the (workgroup-scope) atomics are then performed, so no
+// OR can be overtaken by the store it modifies; the LDS queue writes of the
+// wave are complete too.  An agent-scope fence would also order them but
+// writes back and invalidates the whole L2 of the XCD, which stalls every
+// other wave's stream.
+template <int KIND, typename PT>
+__device__ void flush_queue(const PolyLds& S, const int64_t* q, int count, const void* Q,
+                            uint32_t* labels, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < count; e += kWave) {
+        const int64_t idx = q[e];
+        const auto p = PointIO<PT>::load(Q, idx);
+        const double x = (double)p.x, y = (double)p.y;
+        bool in;
+        if constexpr (KIND == K_VORONOI)
+            in = voronoi64(x, y, S.gen, S.n);
+        else
+            in = sign_of_offset64(x, y, S.vtx, S.n);
+        if (in)
+            __hip_atomic_fetch_or(&labels[idx >> 5], 1u << (uint32_t)(idx & 31), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+// float32, binary64-free preparation (Algorithms 3-4 evaluated in float32 in
+// the global frame) for the plain reference kernel.
+__device__ void prepare_plain(PolyLds& S, int lane) {
+    const int n = S.n;
+    float Ss = 0.f, Sx = 0.f, Sy = 0.f;
+    for (int i = 0; i < n; ++i) {
+        const int j = prev_edge(i, n);
+        const float vx = (float)S.vtx[i].x, vy = (float)S.vtx[i].y;
+        const float wx = (float)S.vtx[j].x, wy = (float)S.vtx[j].y;
+        const float Ai = wx * vy - vx * wy;
+        Ss += Ai;
+        Sx += (vx + wx) * Ai;
+        Sy += (vy + wy) * Ai;
+    }
+    const float a = 0.5f * Ss;
+    const float cx = Sx / (6.f * a), cy = Sy / (6.f * a);
+    const int i = lane < n ? lane : 0;
+    const int j = prev_edge(i, n);
+    const float vx = (float)S.vtx[i].x, vy = (float)S.vtx[i].y;
+    const float wx = (float)S.vtx[j].x, wy = (float)S.vtx[j].y;
+    const float ea = vy - wy, eb = wx - vx;
+    const float ec = -(ea * vx + eb * vy);
+    const float den = ea * ea + eb * eb;
+    const float gx = ((eb * eb - ea * ea) * cx + (-2.f * ea) * eb * cy + (-2.f * ec) * ea) / den;
+    const float gy = ((-2.f * ea) * eb * cx + (ea * ea - eb * eb) * cy + (-2.f * ec) * eb) / den;
+    const float A = 2.f * (gx - cx), B = 2.f * (gy - cy);
+    const float C = (gx * gx + gy * gy) - (cx * cx + cy * cy);
+    S.coef[lane] = make_float4(A, B, -C, 0.f);
+    if (lane == 0) {
+        S.ox = 0.f;
+        S.oy = 0.f;
+        S.n4 = (n + 3) & ~3;
+        S.status = ST_OK;
+    }
+}
+
+template <int KIND, typename PT>
+__global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V, int n,
+                                                  const void* __restrict__ Q, int64_t m,
+                                                  uint32_t* __restrict__ labels,
+                                                  float* __restrict__ margin,
+                                                  int32_t* __restrict__ status) {
+    constexpr bool kQueue = (KIND == K_VORONOI || KIND == K_SOO);
+    __shared__ PolyLds S;
+    __shared__ int64_t queue[kWavesPerBlock][kQueue ? kQueueCap : 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = tid / kWave;
+    const int64_t nchunks = (m + kChunk - 1) / kChunk;
+    const int64_t nwords = (m + 31) / 32;
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    int64_t chunk = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+
+    double2 vt = make_double2(0.0, 0.0);
+    if (tid < n) vt = make_double2(V[2 * tid], V[2 * tid + 1]);
+    PT px[kPPL], py[kPPL];
+    if (m > 0) load_chunk<PT>(Q, m, chunk, lane, px, py);  // in flight during preparation
+
+    if (tid < n) S.vtx[tid] = vt;
+    if (tid == 0) S.n = n;
+    __syncthreads();
+    if (wv == 0) {
+        if constexpr (KIND == K_PLAIN)
+            prepare_plain(S, lane);
+        else
+            prepare_polygon(S, KIND, lane);
+    }
+    __syncthreads();
+    if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
+
+    const float ox = S.ox, oy = S.oy;
+    const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC;
+    const int n4 = __builtin_amdgcn_readfirstlane(S.n4);
+    const int nv = __builtin_amdgcn_readfirstlane(S.n);
+    int qcount = 0;
+
+    for (; chunk < nchunks; chunk += stride) {
+        PT nx[kPPL], ny[kPPL];
+        load_chunk<PT>(Q, m, chunk + stride, lane, nx, ny);
+        const int64_t base = chunk * kChunk;
+        uint64_t inm[kPPL];
+
+        if constexpr (KIND == K_RAY) {
+            // Algorithm 1 in binary64 directly (exact replay, no band).
+            double x[kPPL], y[kPPL];
+            bool cross[kPPL];
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                x[j] = (double)px[j];
+                y[j] = (double)py[j];
+                cross[j] = false;
+            }
+            for (int e = 0; e < nv; ++e) {
+                const double4 r = S.ray[e];  // (V'_y, V_y, dV_x, dV_y)
+                const double R = S.rhs[e];
+                const bool up = r.y > r.x;
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    const bool inr = (r.y > y[j]) != (r.x > y[j]);
+                    const double L = y[j] * r.z - x[j] * r.w;
+                    const bool left = up ? (L > R) : (L < R);
+                    cross[j] = cross[j] != (inr && left);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                const int64_t idx = base + lane + kWave * j;
+                const bool fin = isfinite(x[j]) && isfinite(y[j]);
+                inm[j] = __ballot(idx < m && fin && cross[j]);
+            }
+        } else {
+            float X[kPPL], Y[kPPL], Mx[kPPL], Mn[kPPL];
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                X[j] = to_local(px[j], ox);
+                Y[j] = to_local(py[j], oy);
+                Mx[j] = -__builtin_huge_valf();
+                Mn[j] = __builtin_huge_valf();
+            }
+            for (int e = 0; e < n4; e += 4) {
+                const float4 c0 = S.coef[e + 0], c1 = S.coef[e + 1];
+                const float4 c2 = S.coef[e + 2], c3 = S.coef[e + 3];
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                    const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                    const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+                    const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);  // v_max3_f32
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
+                    if constexpr (KIND == K_SOO) {
+                        Mn[j] = fminf(fminf(Mn[j], m0), m1);  // v_min3_f32
+                        Mn[j] = fminf(fminf(Mn[j], m2), m3);
+                    }
+                }
+            }
+            if constexpr (KIND == K_MARGIN) {
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    const int64_t idx = base + lane + kWave * j;
+                    if (idx < m) margin[idx] = Mx[j];
+                }
+                px[0] = nx[0]; px[1] = nx[1]; px[2] = nx[2]; px[3] = nx[3];
+                py[0] = ny[0]; py[1] = ny[1]; py[2] = ny[2]; py[3] = ny[3];
+                continue;
+            } else if constexpr (KIND == K_PLAIN) {
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    const int64_t idx = base + lane + kWave * j;
+                    inm[j] = __ballot(idx < m && Mx[j] <= 0.0f);
+                }
+            } else {
+                uint64_t unc[kPPL];
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    const int64_t idx = base + lane + kWave * j;
+                    const bool valid = idx < m;
+                    const float ax = fabsf(X[j]), ay = fabsf(Y[j]);
+                    const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+                    const float E = fmaf(KQ, r2, fmaf(KA, ax, fmaf(KB, ay, KC)));
+                    bool ins, outs;
+                    if constexpr (KIND == K_VORONOI) {
+                        ins = Mx[j] < -E;
+                        outs = Mx[j] > E;
+                    } else {
+                        ins = (Mx[j] < -E) || (Mn[j] > E);
+                        outs = (Mx[j] > E) && (Mn[j] < -E);
+                    }
+                    inm[j] = __ballot(valid && ins);
+                    unc[j] = __ballot(valid && !ins && !outs);
+                }
+                const uint64_t lt = lanemask_lt();
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    if (unc[j]) {
+                        if ((unc[j] >> lane) & 1ull)
+                            queue[wv][qcount + __popcll(unc[j] & lt)] = base + lane + kWave * j;
+                        qcount += __popcll(unc[j]);
+                    }
+                }
+            }
+        }
+        store_words(labels, base, nwords, lane, inm);
+        if constexpr (kQueue) {
+            if (qcount > kQueueCap - kChunk) {
+                flush_queue<KIND, PT>(S, queue[wv], qcount, Q, labels, lane);
+                qcount = 0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            px[j] = nx[j];
+            py[j] = ny[j];
+        }
+    }
+    if constexpr (kQueue) {
+        if (qcount > 0) flush_queue<KIND, PT>(S, queue[wv], qcount, Q, labels, lane);
+    }
+}
+
+// polygon_to_generators: one wave derives p_0 and the n outer generators.
+__global__ __launch_bounds__(kWave) void k_generators_one(const double* __restrict__ V, int n,
+                                                         double* __restrict__ P,
+                                                         int32_t* __restrict__ status) {
+    __shared__ PolyLds S;
+    const int lane = threadIdx.x;
+    if (lane < n) S.vtx[lane] = make_double2(V[2 * lane], V[2 * lane + 1]);
+    if (lane == 0) S.n = n;
+    __syncthreads();
+    prepare_polygon(S, K_VORONOI, lane);
+    __syncthreads();
+    for (int k = lane; k <= n; k += kWave) {
+        P[2 * k] = S.gen[k].x;
+        P[2 * k + 1] = S.gen[k].y;
+    }
+    if (status && lane == 0) *status = S.status;
+}
+
+template <int KIND, typename PT>
+hipError_t launch_stream_t(const StreamLaunch& L) {
+    const int64_t nchunks = (L.m + kChunk - 1) / kChunk;
+    const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
+    int grid = (int)(want < L.max_blocks ? want : L.max_blocks);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_stream<KIND, PT>), dim3(grid), dim3(kBlock), 0, L.stream, L.V, L.n, L.Q,
+                       L.m, L.labels, L.margin, L.status);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+namespace pipdev {
+
+hipError_t launch_stream(const StreamLaunch& L) {
+    const bool f64 = L.qdt == 1;
+    switch (L.kind) {
+        case K_VORONOI:
+            return f64 ? launch_stream_t<K_VORONOI, double>(L) : launch_stream_t<K_VORONOI, float>(L);
+        case K_SOO:
+            return f64 ? launch_stream_t<K_SOO, double>(L) : launch_stream_t<K_SOO, float>(L);
+        case K_RAY:
+            return f64 ? launch_stream_t<K_RAY, double>(L) : launch_stream_t<K_RAY, float>(L);
+        case K_PLAIN:
+            return f64 ? launch_stream_t<K_PLAIN, double>(L) : launch_stream_t<K_PLAIN, float>(L);
+        case K_MARGIN:
+            return f64 ? launch_stream_t<K_MARGIN, double>(L) : launch_stream_t<K_MARGIN, float>(L);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_generators_one(const double* V, int n, double* P, int32_t* status,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(k_generators_one, dim3(1), dim3(kWave), 0, stream, V, n, P, status);
+    return hipGetLastError();
+}
+
+hipError_t stream_max_blocks_per_cu(int kind, int qdt, int* out) {
+    const void* f = nullptr;
+    const bool f64 = qdt == 1;
+    switch (kind) {
+        case K_VORONOI: f = f64 ? (const void*)k_stream<K_VORONOI, double> : (const void*)k_stream<K_VORONOI, float>; break;
+        case K_SOO: f = f64 ? (const void*)k_stream<K_SOO, double> : (const void*)k_stream<K_SOO, float>; break;
+        case K_RAY: f = f64 ? (const void*)k_stream<K_RAY, double> : (const void*)k_stream<K_RAY, float>; break;
+        case K_PLAIN: f = f64 ? (const void*)k_stream<K_PLAIN, double> : (const void*)k_stream<K_PLAIN, float>; break;
+        case K_MARGIN: f = f64 ? (const void*)k_stream<K_MARGIN, double> : (const void*)k_stream<K_MARGIN, float>; break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, f, kBlock, 0);
+}
+
+}  // namespace pipdev
