@@ -140,6 +140,85 @@ pip_status pip_voronoi_max_margin(pip_ctx ctx, const double *V, int32_t n, const
                                   pip_dtype qdt, int64_t m, float *max_margin, int32_t *status,
                                   hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched Voronoi inclusion: P convex polygons, each against its own point
+ * set, in one persistent launch (Section 4, Algorithm 5 per polygon; the
+ * generators of every polygon are derived once and stored beside it, the
+ * precomputation Section 7 suggests for static polygons).
+ *
+ *   vtx_off       [P+1] int64, non-decreasing; polygon k has vertices
+ *                 V[vtx_off[k] .. vtx_off[k+1]) of V ([total_vertices][2]
+ *                 binary64).
+ *   pt_off        [P+1] int64, non-decreasing; polygon k is tested against
+ *                 points Q[pt_off[k] .. pt_off[k+1]) of Q ([total_points][2]
+ *                 float32, 8-byte aligned).
+ *   lbl_word_off  [P+1] int64; the labels of polygon k start at word
+ *                 lbl_word_off[k] of `labels` (every set starts on a fresh
+ *                 32-bit word; bit j of the set's words is its point j;
+ *                 words must not overlap: lbl_word_off[k+1] - lbl_word_off[k]
+ *                 >= ceil(set size / 32)).  Bits past a set's last point in its
+ *                 last word are written as 0.
+ *   status        optional [P] int32 device status per polygon; a polygon
+ *                 with n < 3 gets PIP_EINVAL, n > 64 PIP_EUNSUPPORTED, and its
+ *                 points are all labelled 0; offsets outside
+ *                 [0, total_vertices] / [0, total_points] give PIP_EINVAL and
+ *                 leave that polygon's labels untouched.
+ *   workspace     device buffer of pip_voronoi_batched_workspace_bytes(P,
+ *                 total_vertices, total_points) bytes, 256-byte aligned, owned
+ *                 by the caller, not shared by calls that may overlap.
+ *   config        tile shape; NULL for the default.  Labels do not depend on it.
+ */
+typedef struct {
+    int32_t chunks_per_tile; /* a wave walks tiles of this many 256-point chunks */
+    int32_t blocks_per_cu;   /* persistent workgroups (256 threads) per CU */
+} pip_batched_config;
+
+size_t pip_voronoi_batched_workspace_bytes(int32_t P, int64_t total_vertices,
+                                           int64_t total_points);
+
+pip_status pip_voronoi_batched(pip_ctx ctx, int32_t P, const int64_t *vtx_off, const double *V,
+                               int64_t total_vertices, const int64_t *pt_off, const float *Q,
+                               int64_t total_points, const int64_t *lbl_word_off,
+                               uint32_t *labels, int32_t *status, void *workspace,
+                               size_t workspace_bytes, const pip_batched_config *config,
+                               hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Plans: a batched request bound to its buffers, with a workspace the plan
+ * allocates (pip_plan_create_batched is the only call that allocates device
+ * memory, besides pip_plan_autotune's comparison buffers), a tile shape
+ * chosen by timing candidates on the real data, and the whole launch
+ * sequence captured in a hipGraph.
+ *
+ *   pip_plan_create_batched  arguments as pip_voronoi_batched; reads
+ *                            lbl_word_off[P] from the device (synchronous).
+ *   pip_plan_autotune        runs every candidate tile shape (chunks per tile
+ *                            1, 4, 16, 64, whole range; three grid sizes) `reps`
+ *                            times on `stream`, requires bitwise-identical
+ *                            labels from all of them (PIP_EHIP otherwise),
+ *                            keeps the fastest and captures the hipGraph.
+ *                            Synchronises `stream`.
+ *   pip_plan_launch          replays the graph on `stream` (captures the
+ *                            default shape first if the plan was never tuned).
+ *   pip_plan_config          the chosen shape and its measured time (ms, -1 if
+ *                            not tuned).
+ *   pip_plan_set_config      force a shape (recaptures the graph).
+ *   pip_plan_destroy         frees the plan; destroy plans before their ctx.
+ * The buffers bound at creation must stay valid while the plan is used.
+ */
+typedef struct pip_plan_s *pip_plan;
+
+pip_status pip_plan_create_batched(pip_ctx ctx, int32_t P, const int64_t *vtx_off,
+                                   const double *V, int64_t total_vertices,
+                                   const int64_t *pt_off, const float *Q, int64_t total_points,
+                                   const int64_t *lbl_word_off, uint32_t *labels,
+                                   int32_t *status, pip_plan *out);
+pip_status pip_plan_autotune(pip_plan plan, int32_t reps, hipStream_t stream);
+pip_status pip_plan_launch(pip_plan plan, hipStream_t stream);
+pip_status pip_plan_config(pip_plan plan, pip_batched_config *config, float *best_ms);
+pip_status pip_plan_set_config(pip_plan plan, const pip_batched_config *config);
+void pip_plan_destroy(pip_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -50,7 +50,21 @@ SIGNATURES = {
     "pip_ray_crossing": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_voronoi_fp32_plain": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_voronoi_max_margin": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
+    "pip_voronoi_batched_workspace_bytes": (_c.c_size_t, [_i32, _i64, _i64]),
+    "pip_voronoi_batched": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+                                   _c.c_size_t, _vp, _vp]),
+    "pip_plan_create_batched": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp,
+                                       _c.POINTER(_vp)]),
+    "pip_plan_autotune": (_int, [_vp, _i32, _vp]),
+    "pip_plan_launch": (_int, [_vp, _vp]),
+    "pip_plan_config": (_int, [_vp, _vp, _c.POINTER(_c.c_float)]),
+    "pip_plan_set_config": (_int, [_vp, _vp]),
+    "pip_plan_destroy": (None, [_vp]),
 }
+
+
+class BatchedConfig(ctypes.Structure):
+    _fields_ = [("chunks_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 _lock = threading.Lock()
 _lib = None

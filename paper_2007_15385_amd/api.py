@@ -6,7 +6,7 @@ import threading
 
 import torch
 
-from ._lib import PIP_F32, PIP_F64, PipError, load_library, num_label_words
+from ._lib import PIP_F32, PIP_F64, BatchedConfig, PipError, load_library, num_label_words
 
 _ctx_lock = threading.Lock()
 _ctx: dict[int, int] = {}
@@ -150,3 +150,130 @@ def unpack_labels(words: torch.Tensor, m: int) -> torch.Tensor:
     w = words.contiguous().view(torch.uint8)
     bits = (w.unsqueeze(-1) >> torch.arange(8, device=w.device, dtype=torch.uint8)) & 1
     return bits.reshape(-1)[:m].bool()
+
+
+# ---------------------------------------------------------------------------
+# batched
+# ---------------------------------------------------------------------------
+def _i64(t, name):
+    if t.dtype != torch.int64 or t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D int64 tensor")
+    return t
+
+
+def label_word_offsets(pt_off: torch.Tensor) -> torch.Tensor:
+    """Word offsets that start every set on a fresh 32-bit word."""
+    sizes = pt_off[1:] - pt_off[:-1]
+    words = (sizes + 31) // 32
+    return torch.cat([torch.zeros(1, dtype=torch.int64, device=pt_off.device),
+                      torch.cumsum(words, 0)])
+
+
+def batched_workspace_bytes(P: int, total_vertices: int, total_points: int) -> int:
+    return int(_lib().pip_voronoi_batched_workspace_bytes(int(P), int(total_vertices),
+                                                          int(total_points)))
+
+
+class _BatchedArgs:
+    def __init__(self, vtx_off, V, pt_off, Q, lbl_word_off, labels, status):
+        self.vtx_off = _i64(vtx_off, "vtx_off")
+        self.pt_off = _i64(pt_off, "pt_off")
+        self.V = _polygon(V)
+        if Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != 2 or not Q.is_contiguous():
+            raise ValueError("Q must be a contiguous float32 tensor of shape [m, 2]")
+        self.Q = Q
+        self.P = self.vtx_off.numel() - 1
+        if self.pt_off.numel() != self.P + 1:
+            raise ValueError("vtx_off and pt_off must both have P+1 entries")
+        self.device = _dev(self.V)
+        self.lbl = _i64(lbl_word_off, "lbl_word_off") if lbl_word_off is not None else \
+            label_word_offsets(self.pt_off)
+        nwords = int(self.lbl[-1].item()) if self.P > 0 else 0
+        if labels is None:
+            labels = torch.zeros(max(nwords, 1), dtype=torch.int32, device=self.V.device)
+        self.labels = labels
+        self.status = status if status is not None else \
+            torch.zeros(max(self.P, 1), dtype=torch.int32, device=self.V.device)
+        self.TV = self.V.shape[0]
+        self.TP = self.Q.shape[0]
+
+    def ptrs(self):
+        return (self.P, self.vtx_off.data_ptr(), self.V.data_ptr() if self.TV else None, self.TV,
+                self.pt_off.data_ptr(), self.Q.data_ptr() if self.TP else None, self.TP,
+                self.lbl.data_ptr(), self.labels.data_ptr(), self.status.data_ptr())
+
+
+def pip_voronoi_batched(vtx_off, V, pt_off, Q, lbl_word_off=None, labels=None, status=None,
+                        workspace=None, config=None):
+    """Labels of P polygons against their own point sets; returns
+    (labels, lbl_word_off, status)."""
+    a = _BatchedArgs(vtx_off, V, pt_off, Q, lbl_word_off, labels, status)
+    need = batched_workspace_bytes(a.P, a.TV, a.TP)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=a.V.device)
+    cfg = None
+    if config is not None:
+        cfg = BatchedConfig(int(config[0]), int(config[1]))
+    ctx = context(a.device)
+    s = _lib().pip_voronoi_batched(ctx, *a.ptrs(), workspace.data_ptr(), workspace.numel(),
+                                   ctypes.byref(cfg) if cfg is not None else None,
+                                   _stream(a.device))
+    _check(s, "pip_voronoi_batched", ctx)
+    return a.labels, a.lbl, a.status
+
+
+class BatchedPlan:
+    """Autotuned, graph-captured batched launch bound to fixed buffers."""
+
+    def __init__(self, vtx_off, V, pt_off, Q, lbl_word_off=None, labels=None, status=None):
+        self.args = _BatchedArgs(vtx_off, V, pt_off, Q, lbl_word_off, labels, status)
+        self.ctx = context(self.args.device)
+        h = ctypes.c_void_p()
+        s = _lib().pip_plan_create_batched(self.ctx, *self.args.ptrs(), ctypes.byref(h))
+        _check(s, "pip_plan_create_batched", self.ctx)
+        self.handle = h.value
+
+    @property
+    def labels(self):
+        return self.args.labels
+
+    @property
+    def status(self):
+        return self.args.status
+
+    @property
+    def lbl_word_off(self):
+        return self.args.lbl
+
+    def autotune(self, reps: int = 3):
+        s = _lib().pip_plan_autotune(self.handle, int(reps), _stream(self.args.device))
+        _check(s, "pip_plan_autotune", self.ctx)
+        return self.config()
+
+    def launch(self):
+        s = _lib().pip_plan_launch(self.handle, _stream(self.args.device))
+        _check(s, "pip_plan_launch", self.ctx)
+        return self.args.labels
+
+    def config(self):
+        cfg = BatchedConfig()
+        ms = ctypes.c_float()
+        s = _lib().pip_plan_config(self.handle, ctypes.byref(cfg), ctypes.byref(ms))
+        _check(s, "pip_plan_config", self.ctx)
+        return (cfg.chunks_per_tile, cfg.blocks_per_cu), float(ms.value)
+
+    def set_config(self, chunks_per_tile: int, blocks_per_cu: int):
+        cfg = BatchedConfig(int(chunks_per_tile), int(blocks_per_cu))
+        s = _lib().pip_plan_set_config(self.handle, ctypes.byref(cfg))
+        _check(s, "pip_plan_set_config", self.ctx)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().pip_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,6 +14,24 @@ struct pip_ctx_s {
     int cu_count = 0;
     std::mutex mu;
     int stream_blocks[8][2] = {};  // cached persistent grid per (kind, dtype); 0 = unknown
+    int batched_blocks_per_cu = 0;
+};
+
+// A plan: one batched request bound to its buffers, its own workspace, the
+// tile shape chosen by the autotuner and the captured hipGraph.
+struct pip_plan_s {
+    pip_ctx ctx = nullptr;
+    pipdev::BatchedDev D{};
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    pip_batched_config cfg{};
+    float best_ms = -1.f;
+    int64_t label_words = 0;
+    uint32_t* ref_labels = nullptr;
+    unsigned long long* d_diff = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -205,6 +223,328 @@ pip_status pip_voronoi_max_margin(pip_ctx ctx, const double* V, int32_t n, const
                                   pip_dtype qdt, int64_t m, float* max_margin, int32_t* status,
                                   hipStream_t stream) {
     return run_stream(ctx, pipdev::K_MARGIN, V, n, Q, qdt, m, nullptr, max_margin, status, stream);
+}
+
+
+// ---------------------------------------------------------------------------
+// batched
+// ---------------------------------------------------------------------------
+size_t pip_voronoi_batched_workspace_bytes(int32_t P, int64_t total_vertices,
+                                           int64_t total_points) {
+    if (P < 0 || total_vertices < 0 || total_points < 0) return 0;
+    pipdev::BatchedLayout L;
+    return pipdev::batched_workspace_layout(P, total_vertices, total_points, &L);
+}
+
+}  // extern "C"
+
+namespace {
+
+pip_status check_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_off, const double* V,
+                         int64_t total_vertices, const int64_t* pt_off, const float* Q,
+                         int64_t total_points, const int64_t* lbl_word_off, uint32_t* labels,
+                         int32_t* status) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (P < 0) return fail(PIP_EINVAL, "P = %d is negative", (int)P);
+    if (total_vertices < 0 || total_points < 0)
+        return fail(PIP_EINVAL, "total_vertices / total_points must be >= 0");
+    if (P > 0 && (!vtx_off || !pt_off || !lbl_word_off))
+        return fail(PIP_EINVAL, "vtx_off, pt_off and lbl_word_off must not be NULL");
+    if (P > 0 && (!aligned(vtx_off, 8) || !aligned(pt_off, 8) || !aligned(lbl_word_off, 8)))
+        return fail(PIP_EINVAL, "offset arrays must be 8-byte aligned");
+    if (total_vertices > 0 && (!V || !aligned(V, 8))) return fail(PIP_EINVAL, "V is NULL or misaligned");
+    if (total_points > 0 && (!Q || !aligned(Q, 8))) return fail(PIP_EINVAL, "Q is NULL or not 8-byte aligned");
+    if (total_points > 0 && (!labels || !aligned(labels, 4)))
+        return fail(PIP_EINVAL, "labels is NULL or not 4-byte aligned");
+    if (status && !aligned(status, 4)) return fail(PIP_EINVAL, "status is not 4-byte aligned");
+    if (total_points > (int64_t(1) << 46)) return fail(PIP_EUNSUPPORTED, "too many points");
+    return PIP_OK;
+}
+
+pipdev::BatchedDev make_dev(int32_t P, const int64_t* vtx_off, const double* V,
+                            int64_t total_vertices, const int64_t* pt_off, const float* Q,
+                            int64_t total_points, const int64_t* lbl_word_off, uint32_t* labels,
+                            int32_t* status, void* ws) {
+    pipdev::BatchedLayout L;
+    pipdev::batched_workspace_layout(P, total_vertices, total_points, &L);
+    char* b = static_cast<char*>(ws);
+    pipdev::BatchedDev D{};
+    D.P = P;
+    D.vtx_off = vtx_off;
+    D.V = V;
+    D.total_vertices = total_vertices;
+    D.pt_off = pt_off;
+    D.Q = Q;
+    D.total_points = total_points;
+    D.lbl_word_off = lbl_word_off;
+    D.labels = labels;
+    D.status = status;
+    D.hdr = reinterpret_cast<pipdev::PolyHdr*>(b + L.hdr);
+    D.coef = reinterpret_cast<float4*>(b + L.coef);
+    D.gen = reinterpret_cast<double2*>(b + L.gen);
+    D.chunk_cnt = reinterpret_cast<int64_t*>(b + L.chunk_cnt);
+    D.chunk_off = reinterpret_cast<int64_t*>(b + L.chunk_off);
+    D.desc = b + L.desc;
+    D.misc = reinterpret_cast<int64_t*>(b + L.misc);
+    D.max_chunks = L.max_chunks;
+    return D;
+}
+
+int batched_blocks_per_cu(pip_ctx ctx) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->batched_blocks_per_cu == 0) {
+        int b = 0;
+        if (pipdev::batched_max_blocks_per_cu(&b) != hipSuccess || b < 1) b = 1;
+        ctx->batched_blocks_per_cu = b;
+    }
+    return ctx->batched_blocks_per_cu;
+}
+
+pip_status resolve_config(pip_ctx ctx, const pip_batched_config* in, pip_batched_config* out) {
+    const int occ = batched_blocks_per_cu(ctx);
+    pip_batched_config c;
+    c.chunks_per_tile = 16;
+    c.blocks_per_cu = occ;
+    if (in) {
+        if (in->chunks_per_tile < 1) return fail(PIP_EINVAL, "chunks_per_tile must be >= 1");
+        if (in->blocks_per_cu < 1 || in->blocks_per_cu > 64)
+            return fail(PIP_EINVAL, "blocks_per_cu must be in [1, 64]");
+        c = *in;
+    }
+    *out = c;
+    return PIP_OK;
+}
+
+pip_status launch_batched_cfg(pip_ctx ctx, const pipdev::BatchedDev& D,
+                              const pip_batched_config& c, hipStream_t stream) {
+    hipError_t e = pipdev::launch_batched(D, c.chunks_per_tile, c.blocks_per_cu * ctx->cu_count, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pip_status pip_voronoi_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_off, const double* V,
+                               int64_t total_vertices, const int64_t* pt_off, const float* Q,
+                               int64_t total_points, const int64_t* lbl_word_off,
+                               uint32_t* labels, int32_t* status, void* workspace,
+                               size_t workspace_bytes, const pip_batched_config* config,
+                               hipStream_t stream) {
+    pip_status s = check_batched(ctx, P, vtx_off, V, total_vertices, pt_off, Q, total_points,
+                                 lbl_word_off, labels, status);
+    if (s != PIP_OK) return s;
+    if (P == 0) return PIP_OK;
+    const size_t need = pip_voronoi_batched_workspace_bytes(P, total_vertices, total_points);
+    if (!workspace || workspace_bytes < need)
+        return fail(PIP_EINVAL, "workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
+    if (!aligned(workspace, 256)) return fail(PIP_EINVAL, "workspace is not 256-byte aligned");
+    pip_batched_config c;
+    if ((s = resolve_config(ctx, config, &c)) != PIP_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const pipdev::BatchedDev D = make_dev(P, vtx_off, V, total_vertices, pt_off, Q, total_points,
+                                          lbl_word_off, labels, status, workspace);
+    return launch_batched_cfg(ctx, D, c, stream);
+}
+
+// ---------------------------------------------------------------------------
+// plans: autotuned tile shape + captured hipGraph
+// ---------------------------------------------------------------------------
+void pip_plan_destroy(pip_plan p) {
+    if (!p) return;
+    DeviceGuard g(p->ctx->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->ref_labels) (void)hipFree(p->ref_labels);
+    if (p->d_diff) (void)hipFree(p->d_diff);
+    delete p;
+}
+
+pip_status pip_plan_create_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_off,
+                                   const double* V, int64_t total_vertices,
+                                   const int64_t* pt_off, const float* Q, int64_t total_points,
+                                   const int64_t* lbl_word_off, uint32_t* labels,
+                                   int32_t* status, pip_plan* out) {
+    if (!out) return fail(PIP_EINVAL, "out is NULL");
+    *out = nullptr;
+    pip_status s = check_batched(ctx, P, vtx_off, V, total_vertices, pt_off, Q, total_points,
+                                 lbl_word_off, labels, status);
+    if (s != PIP_OK) return s;
+    if (P < 1) return fail(PIP_EINVAL, "a plan needs P >= 1");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    pip_plan p = new (std::nothrow) pip_plan_s();
+    if (!p) return fail(PIP_ENOMEM, "out of host memory");
+    p->ctx = ctx;
+    p->ws_bytes = pip_voronoi_batched_workspace_bytes(P, total_vertices, total_points);
+    hipError_t e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+        pip_plan_destroy(p);
+        return fail(PIP_ENOMEM, "hipMalloc of %zu workspace bytes failed", p->ws_bytes);
+    }
+    int64_t words = 0;
+    e = hipMemcpy(&words, lbl_word_off + P, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        pip_plan_destroy(p);
+        return hip_fail(e, "reading lbl_word_off[P]");
+    }
+    if (words < 0 || words > total_points / 32 + P + 1) {
+        pip_plan_destroy(p);
+        return fail(PIP_EINVAL, "lbl_word_off[P] = %lld is inconsistent with the point count",
+                    (long long)words);
+    }
+    p->label_words = words;
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        pip_plan_destroy(p);
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    p->D = make_dev(P, vtx_off, V, total_vertices, pt_off, Q, total_points, lbl_word_off, labels,
+                    status, p->ws);
+    resolve_config(ctx, nullptr, &p->cfg);
+    *out = p;
+    return PIP_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+pip_status capture_plan(pip_plan p) {
+    if (p->exec) {
+        (void)hipGraphExecDestroy(p->exec);
+        p->exec = nullptr;
+    }
+    if (p->graph) {
+        (void)hipGraphDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = pipdev::launch_batched(p->D, p->cfg.chunks_per_tile,
+                                           p->cfg.blocks_per_cu * p->ctx->cu_count, p->cap);
+    e = hipStreamEndCapture(p->cap, &p->graph);
+    if (le != hipSuccess) return hip_fail(le, "kernel launch during capture");
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    return PIP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pip_status pip_plan_autotune(pip_plan p, int32_t reps, hipStream_t stream) {
+    if (!p) return fail(PIP_EINVAL, "plan is NULL");
+    if (reps < 1) reps = 3;
+    DeviceGuard g(p->ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e;
+    if (!p->ref_labels && p->label_words > 0) {
+        if ((e = hipMalloc(&p->ref_labels, sizeof(uint32_t) * p->label_words)) != hipSuccess)
+            return fail(PIP_ENOMEM, "hipMalloc of the reference labels failed");
+    }
+    if (!p->d_diff && (e = hipMalloc(&p->d_diff, sizeof(unsigned long long))) != hipSuccess)
+        return fail(PIP_ENOMEM, "hipMalloc failed");
+    const int occ = batched_blocks_per_cu(p->ctx);
+    const int tiles[] = {1, 4, 16, 64, 1 << 30};  // 1 << 30: one contiguous range per wave
+    int bpcs[3] = {occ, occ > 2 ? occ - 2 : occ, occ > 1 ? occ / 2 : occ};
+    hipEvent_t a, b;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "hipEventCreate");
+    }
+    pip_status st = PIP_OK;
+    float best = -1.f;
+    pip_batched_config best_cfg = p->cfg;
+    bool have_ref = false;
+    for (int ti = 0; ti < 5 && st == PIP_OK; ++ti) {
+        for (int bi = 0; bi < 3 && st == PIP_OK; ++bi) {
+            if (bi > 0 && bpcs[bi] == bpcs[bi - 1]) continue;
+            pip_batched_config c;
+            c.chunks_per_tile = tiles[ti];
+            c.blocks_per_cu = bpcs[bi];
+            if ((st = launch_batched_cfg(p->ctx, p->D, c, stream)) != PIP_OK) break;  // warm-up
+            if (p->label_words > 0) {
+                if (!have_ref) {
+                    e = hipMemcpyAsync(p->ref_labels, p->D.labels, sizeof(uint32_t) * p->label_words,
+                                       hipMemcpyDeviceToDevice, stream);
+                    if (e != hipSuccess) { st = hip_fail(e, "hipMemcpyAsync"); break; }
+                    have_ref = true;
+                } else {
+                    unsigned long long diff = 0;
+                    e = hipMemsetAsync(p->d_diff, 0, sizeof(unsigned long long), stream);
+                    if (e == hipSuccess)
+                        e = pipdev::launch_count_diff(p->ref_labels, p->D.labels, p->label_words,
+                                                      p->d_diff, stream);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(&diff, p->d_diff, sizeof diff, hipMemcpyDeviceToHost, stream);
+                    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+                    if (e != hipSuccess) { st = hip_fail(e, "label comparison"); break; }
+                    if (diff != 0) {
+                        st = fail(PIP_EHIP, "autotune: tile shape (%d chunks, %d blocks/CU) changed %llu label words",
+                                  c.chunks_per_tile, c.blocks_per_cu, diff);
+                        break;
+                    }
+                }
+            }
+            (void)hipEventRecord(a, stream);
+            for (int r = 0; r < reps; ++r)
+                if ((st = launch_batched_cfg(p->ctx, p->D, c, stream)) != PIP_OK) break;
+            (void)hipEventRecord(b, stream);
+            if ((e = hipEventSynchronize(b)) != hipSuccess) { st = hip_fail(e, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, a, b);
+            ms /= reps;
+            if (best < 0.f || ms < best) {
+                best = ms;
+                best_cfg = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != PIP_OK) return st;
+    p->cfg = best_cfg;
+    p->best_ms = best;
+    return capture_plan(p);
+}
+
+pip_status pip_plan_launch(pip_plan p, hipStream_t stream) {
+    if (!p) return fail(PIP_EINVAL, "plan is NULL");
+    DeviceGuard g(p->ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    if (!p->exec) {
+        pip_status s = capture_plan(p);
+        if (s != PIP_OK) return s;
+    }
+    hipError_t e = hipGraphLaunch(p->exec, stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return PIP_OK;
+}
+
+pip_status pip_plan_config(pip_plan p, pip_batched_config* cfg, float* best_ms) {
+    if (!p) return fail(PIP_EINVAL, "plan is NULL");
+    if (cfg) *cfg = p->cfg;
+    if (best_ms) *best_ms = p->best_ms;
+    return PIP_OK;
+}
+
+pip_status pip_plan_set_config(pip_plan p, const pip_batched_config* cfg) {
+    if (!p || !cfg) return fail(PIP_EINVAL, "plan or cfg is NULL");
+    pip_batched_config c;
+    pip_status s = resolve_config(p->ctx, cfg, &c);
+    if (s != PIP_OK) return s;
+    DeviceGuard g(p->ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    p->cfg = c;
+    return capture_plan(p);
 }
 
 }  // extern "C"

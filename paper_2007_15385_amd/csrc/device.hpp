@@ -34,7 +34,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kPPL = 4;                     // points per lane per chunk
 constexpr int kChunk = kWave * kPPL;        // 256 points per wave iteration
 constexpr int kWordsPerChunk = kChunk / 32; // 8 label words
-constexpr int kQueueCap = 512;              // per-wave queue of undecided points
+constexpr int kQueueCap = 256;              // per-wave queue of undecided points
 
 // Device status codes (same numbering as the C-ABI's pip_status).
 constexpr int ST_OK = 0;
@@ -298,6 +298,105 @@ __device__ inline bool sign_of_offset64(double px, double py, const double2* vtx
         if (LHS < RHS) count += 1;
     }
     return ((count % n) == 0) && isfinite(px) && isfinite(py);
+}
+
+// ----------------------------------------------------------------------------
+// Per-polygon table in global memory (batched and all-pairs work): written by
+// a preparation kernel, read by the screening kernels.
+// ----------------------------------------------------------------------------
+static_assert(sizeof(PolyHdr) == 64, "PolyHdr is 64 bytes");
+
+// Offsets of polygon k's rows in the coefficient and generator arrays,
+// derived from the vertex offsets alone (no scan): n_k + 3 padded float4
+// coefficients and n_k + 1 generators per polygon.
+__device__ __forceinline__ int64_t coef_base(const int64_t* vtx_off, int64_t k) {
+    return vtx_off[k] + 3 * k;
+}
+__device__ __forceinline__ int64_t gen_base(const int64_t* vtx_off, int64_t k) {
+    return vtx_off[k] + k;
+}
+
+// ----------------------------------------------------------------------------
+// The float32 screen of one chunk (kPPL points per lane) against n4 padded
+// edges whose coefficients are in LDS.  Voronoi: Mx = max margin.  Sign of
+// offset: Mx, Mn = max and min offsets.  Classification against the band E:
+// see prepare_polygon.  valid[j] false -> neither inside nor undecided.
+// ----------------------------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ void screen_chunk(const float4* coef, int n4, float KQ, float KA, float KB,
+                                             float KC, const float (&X)[kPPL],
+                                             const float (&Y)[kPPL], const bool (&valid)[kPPL],
+                                             uint64_t (&inm)[kPPL], uint64_t (&unc)[kPPL]) {
+    float Mx[kPPL], Mn[kPPL];
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        Mx[j] = -__builtin_huge_valf();
+        Mn[j] = __builtin_huge_valf();
+    }
+    for (int e = 0; e < n4; e += 4) {
+        const float4 c0 = coef[e + 0], c1 = coef[e + 1];
+        const float4 c2 = coef[e + 2], c3 = coef[e + 3];
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+            const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+            const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+            const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+            Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);  // v_max3_f32
+            Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
+            if constexpr (KIND == K_SOO) {
+                Mn[j] = fminf(fminf(Mn[j], m0), m1);  // v_min3_f32
+                Mn[j] = fminf(fminf(Mn[j], m2), m3);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        const float ax = fabsf(X[j]), ay = fabsf(Y[j]);
+        const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+        const float E = fmaf(KQ, r2, fmaf(KA, ax, fmaf(KB, ay, KC)));
+        bool ins, outs;
+        if constexpr (KIND == K_SOO) {
+            ins = (Mx[j] < -E) || (Mn[j] > E);
+            outs = (Mx[j] > E) && (Mn[j] < -E);
+        } else {
+            ins = Mx[j] < -E;
+            outs = Mx[j] > E;
+        }
+        inm[j] = __ballot(valid[j] && ins);
+        unc[j] = __ballot(valid[j] && !ins && !outs);
+    }
+}
+
+// Lane k (k < 8) stores label word k of a chunk whose first word is `wbase`
+// (nwords words exist from wbase on).  The masks are wave-uniform; a select
+// tree on the lane's bits picks the word (no per-lane array indexing).
+__device__ __forceinline__ void store_chunk_words(uint32_t* labels, int64_t wbase, int64_t nwords,
+                                                  int lane, const uint64_t (&mask)[kPPL]) {
+    const uint32_t lo0 = (uint32_t)mask[0], hi0 = (uint32_t)(mask[0] >> 32);
+    const uint32_t lo1 = (uint32_t)mask[1], hi1 = (uint32_t)(mask[1] >> 32);
+    const uint32_t lo2 = (uint32_t)mask[2], hi2 = (uint32_t)(mask[2] >> 32);
+    const uint32_t lo3 = (uint32_t)mask[3], hi3 = (uint32_t)(mask[3] >> 32);
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
+    const uint32_t w0 = b0 ? hi0 : lo0, w1 = b0 ? hi1 : lo1;
+    const uint32_t w2 = b0 ? hi2 : lo2, w3 = b0 ? hi3 : lo3;
+    const uint32_t w01 = b1 ? w1 : w0, w23 = b1 ? w3 : w2;
+    const uint32_t w = b2 ? w23 : w01;
+    if (lane < kWordsPerChunk && lane < nwords) labels[wbase + lane] = w;
+}
+
+// Wait for every outstanding memory operation of this wave (its label
+// stores are then acknowledged by the L2 of its XCD, where the
+// workgroup-scope atomics that patch them are performed).  Cheaper than an
+// agent-scope fence, which writes back and invalidates the XCD's whole L2.
+__device__ __forceinline__ void wave_drain() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void or_label_bit(uint32_t* labels, int64_t word, uint32_t bit) {
+    __hip_atomic_fetch_or(&labels[word], 1u << bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 }  // namespace pipdev

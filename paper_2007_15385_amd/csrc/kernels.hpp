@@ -1,6 +1,6 @@
 // Host-side launchers of the HIP kernels (private to the library).
 #pragma once
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace pipdev {
@@ -22,6 +22,49 @@ struct StreamLaunch {
 };
 
 hipError_t launch_stream(const StreamLaunch& L);
+
+// Per-polygon table row of the batched and all-pairs paths.
+struct alignas(16) PolyHdr {
+    float ox, oy;          // float32 local origin (p_0 rounded)
+    float KQ, KA, KB, KC;  // band constants
+    int n, n4;             // edges (0 for an invalid polygon), padded to 4
+    int status;            // pip_status of this polygon
+    int pad[7];
+};
+
+// Device view of a batched request plus its workspace.
+struct BatchedDev {
+    int64_t P;
+    const int64_t* vtx_off;
+    const double* V;
+    int64_t total_vertices;
+    const int64_t* pt_off;
+    const void* Q;
+    int64_t total_points;
+    const int64_t* lbl_word_off;
+    uint32_t* labels;
+    int32_t* status;
+    PolyHdr* hdr;
+    float4* coef;
+    double2* gen;
+    int64_t* chunk_cnt;
+    int64_t* chunk_off;
+    void* desc;
+    int64_t* misc;
+    int64_t max_chunks;
+};
+
+struct BatchedLayout {
+    size_t hdr, coef, gen, chunk_cnt, chunk_off, desc, misc;
+    int64_t max_chunks;
+};
+
+size_t batched_workspace_layout(int64_t P, int64_t total_vertices, int64_t total_points,
+                                BatchedLayout* L);
+hipError_t launch_batched(const BatchedDev& D, int chunks_per_tile, int blocks, hipStream_t stream);
+hipError_t batched_max_blocks_per_cu(int* out);
+hipError_t launch_count_diff(const uint32_t* a, const uint32_t* b, int64_t nwords,
+                             unsigned long long* out, hipStream_t stream);
 hipError_t launch_generators_one(const double* V, int n, double* P, int32_t* status,
                                  hipStream_t stream);
 hipError_t stream_max_blocks_per_cu(int kind, int qdt, int* out);

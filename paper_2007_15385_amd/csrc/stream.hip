@@ -65,37 +65,15 @@ __device__ __forceinline__ float to_local(double p, float o) { return (float)(p 
 // Lane k (k < 8) stores label word k of the chunk.  The masks are
 // wave-uniform; a select tree on the lane's bits picks the word (plain
 // selects between scalar values, no per-lane array indexing).
-__device__ __forceinline__ void store_words(uint32_t* labels, int64_t base, int64_t nwords, int lane,
-                                            const uint64_t (&mask)[kPPL]) {
-    const uint32_t lo0 = (uint32_t)mask[0], hi0 = (uint32_t)(mask[0] >> 32);
-    const uint32_t lo1 = (uint32_t)mask[1], hi1 = (uint32_t)(mask[1] >> 32);
-    const uint32_t lo2 = (uint32_t)mask[2], hi2 = (uint32_t)(mask[2] >> 32);
-    const uint32_t lo3 = (uint32_t)mask[3], hi3 = (uint32_t)(mask[3] >> 32);
-    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4;
-    const uint32_t w0 = b0 ? hi0 : lo0, w1 = b0 ? hi1 : lo1;
-    const uint32_t w2 = b0 ? hi2 : lo2, w3 = b0 ? hi3 : lo3;
-    const uint32_t w01 = b1 ? w1 : w0, w23 = b1 ? w3 : w2;
-    const uint32_t w = b2 ? w23 : w01;
-    const int64_t widx = base / 32 + lane;
-    if (lane < kWordsPerChunk && widx < nwords) labels[widx] = w;
-}
-
-// Re-decide the queued points in binary64 and set the inside bits.
+// Re-decide the queued points in binary64 and set their inside bits.
 //
 // Only the wave that owns a chunk ever writes its label words: first the
-// chunk store (undecided bits 0), later these ORs.  `s_waitcnt 0` makes the
-// wave wait until all of its own earlier stores are acknowledged by the L2
-// of its XCD, where the (workgroup-scope) atomics are then performed, so no
-// OR can be overtaken by the store it modifies; the LDS queue writes of the
-// wave are complete too.  An agent-scope fence would also order them but
-// writes back and invalidates the whole L2 of the XCD, which stalls every
-// other wave's stream.
+// chunk store (undecided bits 0), later these ORs, issued after wave_drain()
+// so no OR can be overtaken by the store it modifies.
 template <int KIND, typename PT>
 __device__ void flush_queue(const PolyLds& S, const int64_t* q, int count, const void* Q,
                             uint32_t* labels, int lane) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    wave_drain();
     for (int e = lane; e < count; e += kWave) {
         const int64_t idx = q[e];
         const auto p = PointIO<PT>::load(Q, idx);
@@ -105,9 +83,7 @@ __device__ void flush_queue(const PolyLds& S, const int64_t* q, int count, const
             in = voronoi64(x, y, S.gen, S.n);
         else
             in = sign_of_offset64(x, y, S.vtx, S.n);
-        if (in)
-            __hip_atomic_fetch_or(&labels[idx >> 5], 1u << (uint32_t)(idx & 31), __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (in) or_label_bit(labels, idx >> 5, (uint32_t)(idx & 31));
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -185,6 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
 
     const float ox = S.ox, oy = S.oy;
     const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC;
+    (void)KQ; (void)KA; (void)KB; (void)KC;
     const int n4 = __builtin_amdgcn_readfirstlane(S.n4);
     const int nv = __builtin_amdgcn_readfirstlane(S.n);
     int qcount = 0;
@@ -194,6 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
         load_chunk<PT>(Q, m, chunk + stride, lane, nx, ny);
         const int64_t base = chunk * kChunk;
         uint64_t inm[kPPL];
+        bool valid[kPPL];
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) valid[j] = base + lane + kWave * j < m;
 
         if constexpr (KIND == K_RAY) {
             // Algorithm 1 in binary64 directly (exact replay, no band).
@@ -219,18 +199,17 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
             }
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
-                const int64_t idx = base + lane + kWave * j;
                 const bool fin = isfinite(x[j]) && isfinite(y[j]);
-                inm[j] = __ballot(idx < m && fin && cross[j]);
+                inm[j] = __ballot(valid[j] && fin && cross[j]);
             }
-        } else {
-            float X[kPPL], Y[kPPL], Mx[kPPL], Mn[kPPL];
+            store_chunk_words(labels, base / 32, nwords - base / 32, lane, inm);
+        } else if constexpr (KIND == K_MARGIN || KIND == K_PLAIN) {
+            float X[kPPL], Y[kPPL], Mx[kPPL];
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
                 X[j] = to_local(px[j], ox);
                 Y[j] = to_local(py[j], oy);
                 Mx[j] = -__builtin_huge_valf();
-                Mn[j] = __builtin_huge_valf();
             }
             for (int e = 0; e < n4; e += 4) {
                 const float4 c0 = S.coef[e + 0], c1 = S.coef[e + 1];
@@ -241,65 +220,42 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
                     const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
                     const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
                     const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
-                    Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);  // v_max3_f32
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
                     Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
-                    if constexpr (KIND == K_SOO) {
-                        Mn[j] = fminf(fminf(Mn[j], m0), m1);  // v_min3_f32
-                        Mn[j] = fminf(fminf(Mn[j], m2), m3);
-                    }
                 }
             }
             if constexpr (KIND == K_MARGIN) {
 #pragma unroll
-                for (int j = 0; j < kPPL; ++j) {
-                    const int64_t idx = base + lane + kWave * j;
-                    if (idx < m) margin[idx] = Mx[j];
-                }
-                px[0] = nx[0]; px[1] = nx[1]; px[2] = nx[2]; px[3] = nx[3];
-                py[0] = ny[0]; py[1] = ny[1]; py[2] = ny[2]; py[3] = ny[3];
-                continue;
-            } else if constexpr (KIND == K_PLAIN) {
-#pragma unroll
-                for (int j = 0; j < kPPL; ++j) {
-                    const int64_t idx = base + lane + kWave * j;
-                    inm[j] = __ballot(idx < m && Mx[j] <= 0.0f);
-                }
+                for (int j = 0; j < kPPL; ++j)
+                    if (valid[j]) margin[base + lane + kWave * j] = Mx[j];
             } else {
-                uint64_t unc[kPPL];
 #pragma unroll
-                for (int j = 0; j < kPPL; ++j) {
-                    const int64_t idx = base + lane + kWave * j;
-                    const bool valid = idx < m;
-                    const float ax = fabsf(X[j]), ay = fabsf(Y[j]);
-                    const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
-                    const float E = fmaf(KQ, r2, fmaf(KA, ax, fmaf(KB, ay, KC)));
-                    bool ins, outs;
-                    if constexpr (KIND == K_VORONOI) {
-                        ins = Mx[j] < -E;
-                        outs = Mx[j] > E;
-                    } else {
-                        ins = (Mx[j] < -E) || (Mn[j] > E);
-                        outs = (Mx[j] > E) && (Mn[j] < -E);
-                    }
-                    inm[j] = __ballot(valid && ins);
-                    unc[j] = __ballot(valid && !ins && !outs);
-                }
+                for (int j = 0; j < kPPL; ++j) inm[j] = __ballot(valid[j] && Mx[j] <= 0.0f);
+                store_chunk_words(labels, base / 32, nwords - base / 32, lane, inm);
+            }
+        } else {
+            float X[kPPL], Y[kPPL];
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                X[j] = to_local(px[j], ox);
+                Y[j] = to_local(py[j], oy);
+            }
+            uint64_t unc[kPPL];
+            screen_chunk<KIND>(S.coef, n4, KQ, KA, KB, KC, X, Y, valid, inm, unc);
+            const int nunc = __popcll(unc[0]) + __popcll(unc[1]) + __popcll(unc[2]) + __popcll(unc[3]);
+            if (nunc != 0 && qcount + nunc > kQueueCap) {  // flush before push
+                flush_queue<KIND, PT>(S, queue[wv], qcount, Q, labels, lane);
+                qcount = 0;
+            }
+            store_chunk_words(labels, base / 32, nwords - base / 32, lane, inm);
+            if (nunc != 0) {
                 const uint64_t lt = lanemask_lt();
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
-                    if (unc[j]) {
-                        if ((unc[j] >> lane) & 1ull)
-                            queue[wv][qcount + __popcll(unc[j] & lt)] = base + lane + kWave * j;
-                        qcount += __popcll(unc[j]);
-                    }
+                    if ((unc[j] >> lane) & 1ull)
+                        queue[wv][qcount + __popcll(unc[j] & lt)] = base + lane + kWave * j;
+                    qcount += __popcll(unc[j]);
                 }
-            }
-        }
-        store_words(labels, base, nwords, lane, inm);
-        if constexpr (kQueue) {
-            if (qcount > kQueueCap - kChunk) {
-                flush_queue<KIND, PT>(S, queue[wv], qcount, Q, labels, lane);
-                qcount = 0;
             }
         }
 #pragma unroll
