@@ -219,6 +219,34 @@ pip_status pip_plan_config(pip_plan plan, pip_batched_config *config, float *bes
 pip_status pip_plan_set_config(pip_plan plan, const pip_batched_config *config);
 void pip_plan_destroy(pip_plan plan);
 
+/* ------------------------------------------------------------------------
+ * Poses and all pairs (the collision check of Section 1: a convex car
+ * footprint placed at many poses, tested against a lidar point cloud).
+ *
+ * pip_poses_to_polygons: world vertices of footprint F ([n][2] binary64,
+ *   body frame) at K poses.  pose [K][3] float32 (x, y, theta), cs [K][2]
+ *   binary64 (cos theta, sin theta, supplied by the caller so that nobody
+ *   recomputes them); V_out [K][n][2] binary64 receives
+ *   ((c vx - s vy) + x, (s vx + c vy) + y) per vertex, evaluated in binary64
+ *   in that order.
+ *
+ * pip_voronoi_allpairs: P convex polygons of n vertices each (V [P][n][2]
+ *   binary64), every one against all m points of Q ([m][2] float32).
+ *   labels [P][ceil(m/32)] words, row k = polygon k, same bit layout as
+ *   pip_voronoi; counts optional [P] int32 = inside points per polygon
+ *   (overwritten); status optional [P].  Labels are bit-identical to the
+ *   binary64 Voronoi algorithm for each polygon.  workspace: device buffer of
+ *   pip_voronoi_allpairs_workspace_bytes(P, n) bytes, 256-byte aligned.
+ */
+pip_status pip_poses_to_polygons(pip_ctx ctx, const double *footprint, int32_t n, const float *pose,
+                                 const double *cs, int64_t K, double *V_out, hipStream_t stream);
+
+size_t pip_voronoi_allpairs_workspace_bytes(int32_t P, int32_t n);
+
+pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double *V, const float *Q,
+                                int64_t m, uint32_t *labels, int32_t *counts, int32_t *status,
+                                void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

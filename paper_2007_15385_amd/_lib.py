@@ -60,6 +60,10 @@ SIGNATURES = {
     "pip_plan_config": (_int, [_vp, _vp, _c.POINTER(_c.c_float)]),
     "pip_plan_set_config": (_int, [_vp, _vp]),
     "pip_plan_destroy": (None, [_vp]),
+    "pip_poses_to_polygons": (_int, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp]),
+    "pip_voronoi_allpairs_workspace_bytes": (_c.c_size_t, [_i32, _i32]),
+    "pip_voronoi_allpairs": (_int, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
+                                    _c.c_size_t, _vp]),
 }
 
 

@@ -277,3 +277,54 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# poses, all pairs
+# ---------------------------------------------------------------------------
+def pip_poses_to_polygons(footprint, pose, cs, out=None):
+    """[K, n, 2] float64 world vertices of `footprint` at `pose` ([K,3]
+    float32) with cos/sin `cs` ([K,2] float64)."""
+    F = _polygon(footprint)
+    d = _dev(F)
+    if pose.dtype != torch.float32 or pose.dim() != 2 or pose.shape[1] != 3 or \
+            not pose.is_contiguous():
+        raise ValueError("pose must be a contiguous float32 tensor of shape [K, 3]")
+    if cs.dtype != torch.float64 or tuple(cs.shape) != (pose.shape[0], 2) or not cs.is_contiguous():
+        raise ValueError("cs must be a contiguous float64 tensor of shape [K, 2]")
+    K, n = pose.shape[0], F.shape[0]
+    if out is None:
+        out = torch.empty((K, n, 2), dtype=torch.float64, device=F.device)
+    ctx = context(d)
+    s = _lib().pip_poses_to_polygons(ctx, F.data_ptr(), n, pose.data_ptr(), cs.data_ptr(), K,
+                                     out.data_ptr(), _stream(d))
+    _check(s, "pip_poses_to_polygons", ctx)
+    return out
+
+
+def pip_voronoi_allpairs(V, Q, labels=None, counts=None, status=None, workspace=None):
+    """V [P, n, 2] float64, Q [m, 2] float32 -> (labels [P, ceil(m/32)] int32,
+    counts [P] int32, status [P] int32)."""
+    if V.dtype != torch.float64 or V.dim() != 3 or V.shape[2] != 2 or not V.is_contiguous():
+        raise ValueError("V must be a contiguous float64 tensor of shape [P, n, 2]")
+    if Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != 2 or not Q.is_contiguous():
+        raise ValueError("Q must be a contiguous float32 tensor of shape [m, 2]")
+    d = _dev(V)
+    Pn, n = V.shape[0], V.shape[1]
+    m = Q.shape[0]
+    words = num_label_words(m)
+    if labels is None:
+        labels = torch.empty((Pn, max(words, 1)), dtype=torch.int32, device=V.device)
+    if counts is None:
+        counts = torch.empty(max(Pn, 1), dtype=torch.int32, device=V.device)
+    if status is None:
+        status = torch.empty(max(Pn, 1), dtype=torch.int32, device=V.device)
+    need = int(_lib().pip_voronoi_allpairs_workspace_bytes(Pn, n))
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=V.device)
+    ctx = context(d)
+    s = _lib().pip_voronoi_allpairs(ctx, Pn, n, V.data_ptr(), Q.data_ptr() if m else None, m,
+                                    labels.data_ptr(), counts.data_ptr(), status.data_ptr(),
+                                    workspace.data_ptr(), workspace.numel(), _stream(d))
+    _check(s, "pip_voronoi_allpairs", ctx)
+    return labels, counts[:Pn], status[:Pn]

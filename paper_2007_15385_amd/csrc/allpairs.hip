@@ -1,0 +1,244 @@
+// All pairs: every polygon of a set (typically one footprint placed at many
+// poses, the collision check of Section 1) against every point of one cloud.
+//
+//   k_poses_to_polygons  world vertices w = R(theta) v + t in binary64,
+//                        ((c vx - s vy) + tx, (s vx + c vy) + ty).
+//   k_prepare_uniform    one wave per polygon: generators (Section 3,
+//                        Algorithms 3-4, binary64), float32 coefficients of the
+//                        global-frame margin and its band constants.
+//   k_allpairs           workgroup = 1024-point tile x group of polygons whose
+//                        coefficients are staged in LDS; per (polygon, point):
+//                        n margins (2 FMA each), max3, compare with the band
+//                        bounded once per (polygon, wave) from the wave's
+//                        coordinate maxima; undecided pairs are re-decided in
+//                        binary64 on the spot (Algorithm 5); inside bits are
+//                        packed by ballot and counted per polygon.
+#include "device.hpp"
+#include "kernels.hpp"
+
+using namespace pipdev;
+
+namespace {
+
+constexpr int kTilePoints = kBlock * kPPL;  // 1024 points per workgroup tile
+constexpr int kLdsCoefBytes = 32768;        // coefficient staging per workgroup
+
+__global__ void k_poses_to_polygons(const double* __restrict__ F, int n,
+                                    const float* __restrict__ pose, const double* __restrict__ cs,
+                                    int64_t K, double* __restrict__ Wout) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K * n) return;
+    const int64_t k = i / n;
+    const int v = (int)(i - k * n);
+    const double c = cs[2 * k], s = cs[2 * k + 1];
+    const double tx = (double)pose[3 * k], ty = (double)pose[3 * k + 1];
+    const double vx = F[2 * v], vy = F[2 * v + 1];
+    Wout[2 * i] = (c * vx - s * vy) + tx;
+    Wout[2 * i + 1] = (s * vx + c * vy) + ty;
+}
+
+// Table rows of polygon k: hdr[k], coef[k * n4 ...], gen[k * (n + 1) ...].
+__global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
+                                                          const double* __restrict__ V,
+                                                          PolyHdr* __restrict__ hdr,
+                                                          float4* __restrict__ coef,
+                                                          double2* __restrict__ gen,
+                                                          int32_t* __restrict__ status) {
+    __shared__ PolyLds S[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int64_t k = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    if (k >= P) return;
+    PolyLds& L = S[wv];
+    if (lane < n) L.vtx[lane] = make_double2(V[2 * (k * n + lane)], V[2 * (k * n + lane) + 1]);
+    if (lane == 0) L.n = n;
+    __builtin_amdgcn_wave_barrier();
+    prepare_polygon(L, K_VORONOI, lane, /*global_frame=*/true);
+    __builtin_amdgcn_wave_barrier();
+    const int n4 = L.n4;
+    if (lane < n4) coef[k * n4 + lane] = L.coef[lane];
+    for (int i = lane; i <= n; i += kWave) gen[k * (n + 1) + i] = L.gen[i];
+    if (lane == 0) {
+        PolyHdr H;
+        H.ox = L.ox;
+        H.oy = L.oy;
+        H.KQ = L.KQ;
+        H.KA = L.KA;
+        H.KB = L.KB;
+        H.KC = L.KC;
+        H.n = n;
+        H.n4 = n4;
+        H.status = L.status;
+        hdr[k] = H;
+        if (status) status[k] = L.status;
+    }
+}
+
+__global__ void k_zero_counts(int32_t* counts, int64_t P) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P) counts[i] = 0;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// grid: x = point tiles of 1024, y = polygon groups of PG.
+__global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__ hdr,
+                                                   const float4* __restrict__ coef,
+                                                   const double2* __restrict__ gen, int64_t P,
+                                                   int n, int PG, const float2* __restrict__ Q,
+                                                   int64_t m, uint32_t* __restrict__ labels,
+                                                   int32_t* __restrict__ counts) {
+    extern __shared__ float4 coef_s[];  // [PG][n4]
+    __shared__ int32_t cnt_s[256];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int n4 = (n + 3) & ~3;
+    const int64_t k0 = (int64_t)blockIdx.y * PG;
+    const int pg = (int)((P - k0) < PG ? (P - k0) : PG);
+    const int64_t words = (m + 31) / 32;
+
+    for (int i = tid; i < pg * n4; i += kBlock) coef_s[i] = coef[k0 * n4 + i];
+    for (int i = tid; i < pg; i += kBlock) cnt_s[i] = 0;
+
+    // this wave's 256 points
+    const int64_t base = (int64_t)blockIdx.x * kTilePoints + (int64_t)wv * kChunk;
+    float x[kPPL], y[kPPL];
+    bool valid[kPPL], fin[kPPL];
+    float xm = 0.f, ym = 0.f;
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        const int64_t i = base + lane + kWave * j;
+        valid[j] = i < m;
+        const float2 p = Q[valid[j] ? i : 0];
+        x[j] = p.x;
+        y[j] = p.y;
+        fin[j] = isfinite(p.x) && isfinite(p.y);
+        valid[j] = valid[j] && fin[j];  // a non-finite point is outside for every polygon
+        if (valid[j]) {
+            xm = fmaxf(xm, fabsf(p.x));
+            ym = fmaxf(ym, fabsf(p.y));
+        }
+    }
+    xm = wave_max_f(xm);
+    ym = wave_max_f(ym);
+    const float r2m = fmaf(xm, xm, ym * ym);
+    __syncthreads();
+
+    const bool wave_live = base < m;
+    for (int p = 0; p < pg && wave_live; ++p) {
+        const int64_t k = k0 + p;
+        const PolyHdr& H = hdr[k];
+        // band for every point of this wave (monotone in |x|, |y|)
+        const float E = fmaf(H.KQ, r2m, fmaf(H.KA, xm, fmaf(H.KB, ym, H.KC)));
+        const float4* cf = coef_s + p * n4;
+        float M[kPPL];
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) M[j] = -__builtin_huge_valf();
+        for (int e = 0; e < n4; e += 4) {
+            const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
+                const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
+                const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
+                const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
+                M[j] = fmaxf(fmaxf(M[j], m0), m1);
+                M[j] = fmaxf(fmaxf(M[j], m2), m3);
+            }
+        }
+        uint64_t inm[kPPL];
+        uint64_t any_unc = 0;
+        bool in[kPPL], unc[kPPL];
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            in[j] = valid[j] && M[j] < -E;
+            unc[j] = valid[j] && !(M[j] < -E) && !(M[j] > E);
+            any_unc |= __ballot(unc[j]);
+        }
+        if (any_unc) {  // rare: re-decide in binary64 (Algorithm 5)
+            const double2* G = gen + k * (n + 1);
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j)
+                if (unc[j]) in[j] = voronoi64((double)x[j], (double)y[j], G, n);
+        }
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            inm[j] = __ballot(in[j]);
+            c += __popcll(inm[j]);
+        }
+        store_chunk_words(labels + k * words, base / 32, words - base / 32, lane, inm);
+        if (lane == 0 && c) atomicAdd(&cnt_s[p], c);
+    }
+    __syncthreads();
+    if (counts)
+        for (int i = tid; i < pg; i += kBlock)
+            if (cnt_s[i]) atomicAdd(&counts[k0 + i], cnt_s[i]);
+}
+
+}  // namespace
+
+namespace pipdev {
+
+size_t allpairs_workspace_layout(int64_t P, int n, AllpairsLayout* L) {
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const int n4 = (n + 3) & ~3;
+    size_t off = 0;
+    L->hdr = off;
+    off = up(off + sizeof(PolyHdr) * (size_t)P);
+    L->coef = off;
+    off = up(off + 16 * (size_t)P * n4);
+    L->gen = off;
+    off = up(off + 16 * (size_t)P * (n + 1));
+    return off;
+}
+
+int allpairs_group(int n) {
+    const int n4 = (n + 3) & ~3;
+    int pg = kLdsCoefBytes / (16 * n4);
+    return pg > 256 ? 256 : pg;
+}
+
+hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, const double* cs,
+                                    int64_t K, double* Wout, hipStream_t stream) {
+    const int64_t total = K * n;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_poses_to_polygons, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       stream, F, n, pose, cs, K, Wout);
+    return hipGetLastError();
+}
+
+hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
+                           uint32_t* labels, int32_t* counts, int32_t* status, void* ws,
+                           hipStream_t stream) {
+    AllpairsLayout L;
+    allpairs_workspace_layout(P, n, &L);
+    char* b = static_cast<char*>(ws);
+    PolyHdr* hdr = reinterpret_cast<PolyHdr*>(b + L.hdr);
+    float4* coef = reinterpret_cast<float4*>(b + L.coef);
+    double2* gen = reinterpret_cast<double2*>(b + L.gen);
+    const unsigned pblocks = (unsigned)((P + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_prepare_uniform, dim3(pblocks), dim3(kBlock), 0, stream, P, n, V, hdr,
+                       coef, gen, status);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (counts) {
+        hipLaunchKernelGGL(k_zero_counts, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream,
+                           counts, P);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (m == 0) return hipSuccess;
+    const int pg = allpairs_group(n);
+    const int n4 = (n + 3) & ~3;
+    dim3 grid((unsigned)((m + kTilePoints - 1) / kTilePoints), (unsigned)((P + pg - 1) / pg));
+    hipLaunchKernelGGL(k_allpairs, grid, dim3(kBlock), (size_t)pg * n4 * 16, stream, hdr, coef,
+                       gen, P, n, pg, reinterpret_cast<const float2*>(Q), m, labels, counts);
+    return hipGetLastError();
+}
+
+}  // namespace pipdev

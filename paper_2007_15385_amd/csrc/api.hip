@@ -547,4 +547,56 @@ pip_status pip_plan_set_config(pip_plan p, const pip_batched_config* cfg) {
     return capture_plan(p);
 }
 
+
+// ---------------------------------------------------------------------------
+// poses and all pairs
+// ---------------------------------------------------------------------------
+pip_status pip_poses_to_polygons(pip_ctx ctx, const double* footprint, int32_t n, const float* pose,
+                                 const double* cs, int64_t K, double* V_out, hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    pip_status s = check_polygon(footprint, n);
+    if (s != PIP_OK) return s;
+    if (K < 0) return fail(PIP_EINVAL, "K = %lld is negative", (long long)K);
+    if (K > 0 && (!pose || !aligned(pose, 4))) return fail(PIP_EINVAL, "pose is NULL or misaligned");
+    if (K > 0 && (!cs || !aligned(cs, 8))) return fail(PIP_EINVAL, "cs is NULL or misaligned");
+    if (K > 0 && (!V_out || !aligned(V_out, 8))) return fail(PIP_EINVAL, "V_out is NULL or misaligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_poses_to_polygons(footprint, n, pose, cs, K, V_out, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+size_t pip_voronoi_allpairs_workspace_bytes(int32_t P, int32_t n) {
+    if (P < 0 || n < 3 || n > PIP_MAX_EDGES) return 0;
+    pipdev::AllpairsLayout L;
+    return pipdev::allpairs_workspace_layout(P, n, &L);
+}
+
+pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double* V, const float* Q,
+                                int64_t m, uint32_t* labels, int32_t* counts, int32_t* status,
+                                void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (P < 0) return fail(PIP_EINVAL, "P = %d is negative", (int)P);
+    if (n < 3) return fail(PIP_EINVAL, "n = %d: a polygon needs at least 3 vertices", (int)n);
+    if (n > PIP_MAX_EDGES) return fail(PIP_EUNSUPPORTED, "n = %d exceeds %d", (int)n, PIP_MAX_EDGES);
+    if (P > 0 && (!V || !aligned(V, 8))) return fail(PIP_EINVAL, "V is NULL or misaligned");
+    pip_status s = check_points(Q, PIP_F32, m);
+    if (s != PIP_OK) return s;
+    if (P > 0 && m > 0 && (!labels || !aligned(labels, 4)))
+        return fail(PIP_EINVAL, "labels is NULL or not 4-byte aligned");
+    if (counts && !aligned(counts, 4)) return fail(PIP_EINVAL, "counts is not 4-byte aligned");
+    if (status && !aligned(status, 4)) return fail(PIP_EINVAL, "status is not 4-byte aligned");
+    if (P == 0) return PIP_OK;
+    const size_t need = pip_voronoi_allpairs_workspace_bytes(P, n);
+    if (!workspace || workspace_bytes < need)
+        return fail(PIP_EINVAL, "workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
+    if (!aligned(workspace, 256)) return fail(PIP_EINVAL, "workspace is not 256-byte aligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_allpairs(P, n, V, Q, m, labels, counts, status, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
 }  // extern "C"

@@ -184,7 +184,7 @@ __device__ inline int validate_polygon(const double2* vtx, int n, int lane, doub
 // frame, and the binary64 evaluation errs by at most
 // 2.0001 v (|dV_x| (|Q_y| + |V'_y|) + |dV_y| (|Q_x| + |V'_x|)).
 // ----------------------------------------------------------------------------
-__device__ inline void prepare_polygon(PolyLds& S, int kind, int lane) {
+__device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool global_frame = false) {
     const int n = S.n;
     double g0x, g0y, area, gx, gy, den;
     derive_generators(S.vtx, n, lane, &g0x, &g0y, &area, &gx, &gy, &den);
@@ -192,7 +192,10 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane) {
     if (lane < n) S.gen[1 + lane] = make_double2(gx, gy);
     if (lane == 0) S.gen[0] = make_double2(g0x, g0y);
 
-    const float ox = (float)g0x, oy = (float)g0y;
+    // Local frame o = fl32(p_0), or the global frame (o = 0, so X = p_x
+    // exactly); the band below holds for either.
+    const float ox = global_frame ? 0.0f : (float)g0x;
+    const float oy = global_frame ? 0.0f : (float)g0y;
     const double dox = (double)ox, doy = (double)oy;
     const int i = lane < n ? lane : 0;
     const double d2x = g0x - dox, d2y = g0y - doy;

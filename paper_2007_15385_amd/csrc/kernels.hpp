@@ -63,6 +63,16 @@ size_t batched_workspace_layout(int64_t P, int64_t total_vertices, int64_t total
                                 BatchedLayout* L);
 hipError_t launch_batched(const BatchedDev& D, int chunks_per_tile, int blocks, hipStream_t stream);
 hipError_t batched_max_blocks_per_cu(int* out);
+struct AllpairsLayout {
+    size_t hdr, coef, gen;
+};
+size_t allpairs_workspace_layout(int64_t P, int n, AllpairsLayout* L);
+int allpairs_group(int n);
+hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, const double* cs,
+                                    int64_t K, double* Wout, hipStream_t stream);
+hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
+                           uint32_t* labels, int32_t* counts, int32_t* status, void* ws,
+                           hipStream_t stream);
 hipError_t launch_count_diff(const uint32_t* a, const uint32_t* b, int64_t nwords,
                              unsigned long long* out, hipStream_t stream);
 hipError_t launch_generators_one(const double* V, int n, double* P, int32_t* status,
