@@ -247,6 +247,42 @@ pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double 
                                 int64_t m, uint32_t *labels, int32_t *counts, int32_t *status,
                                 void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Differentiable collision cost.  For edge i of a convex footprint the
+ * Voronoi margin (Eq. 11) divided by -2|p_i - p_0| is the signed distance of
+ * a point to edge line i, positive inside; the cost of a pose is the sum over
+ * the cloud of relu(min_i of it) -- the total penetration depth -- evaluated
+ * with every point moved into the body frame, p_b = R(theta)^T (p - t).
+ *
+ *   footprint  [n][2] float32 body-frame vertices, 3 <= n <= 16.
+ *   pose       [K][3] float32 (x, y, theta); cos/sin of theta are taken in
+ *              binary64 and rounded to float32.
+ *   Q          [m][2] float32 points (non-finite points contribute nothing).
+ *   cost       [K] float32 (forward output).
+ *   grad_cost  [K] float32 upstream gradient (backward input).
+ *   grad_pose  [K][3] float32, overwritten: d(sum_k grad_cost_k C_k)/d pose_k.
+ *   grad_footprint [n][2] float32, overwritten: gradient to the footprint
+ *              vertices, chained by hand through the generator construction
+ *              (reflection, Eq. 8; centroid, Algorithm 3) in binary64.
+ *   residual   optional [2] float32: |total gradient reaching p_0| and the
+ *              sum of the magnitudes it cancels (exactly 0 in exact
+ *              arithmetic, because every distance depends on its edge line
+ *              only).
+ *   workspace  pip_cost_workspace_bytes(n, K, m) bytes, 256-byte aligned.
+ * Conventions: relu'(0) = 0; on a tie in the min, the lowest edge index.
+ * Results are deterministic (fixed-order reductions, no float atomics).
+ */
+size_t pip_cost_workspace_bytes(int32_t n, int64_t K, int64_t m);
+
+pip_status pip_cost_fwd(pip_ctx ctx, const float *footprint, int32_t n, const float *pose, int64_t K,
+                        const float *Q, int64_t m, float *cost, void *workspace,
+                        size_t workspace_bytes, hipStream_t stream);
+
+pip_status pip_cost_bwd(pip_ctx ctx, const float *footprint, int32_t n, const float *pose, int64_t K,
+                        const float *Q, int64_t m, const float *grad_cost, float *grad_pose,
+                        float *grad_footprint, float *residual, void *workspace,
+                        size_t workspace_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,7 +63,9 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "oracle_allpairs": (None, [_D, _i64, _D, _D, _i64, _D, _i64, _U32, _I64]),
         "oracle_cost": (ctypes.c_int, [_D, _i64, _D, _i64, _D, _i64, _D]),
         "oracle_cost_state": (ctypes.c_int, [_D, _i64, _D, _D, _i64, _I32]),
-        "oracle_cost_grad": (ctypes.c_int, [_D, _i64, _D, _i64, _D, _i64, _D, _D, _D]),
+        "oracle_cost_grad": (ctypes.c_int, [_D, _i64, _D, _i64, _D, _i64, _D, _D, _D, _D, _D]),
+        "oracle_cost_with_hash": (ctypes.c_int, [_D, _i64, _D, _i64, _D, _i64, _D,
+                                                 ctypes.POINTER(ctypes.c_uint64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -197,8 +199,9 @@ class Oracle:
         self.lib.oracle_cost_state(_p(F), len(F), _p(pose), _p(Q), len(Q), _p(st, _I32))
         return st
 
-    def cost_grad(self, F, poses, Q, w=None):
-        """Closed-form gradient of sum_k w_k C_k: ([K][3], [n][2])."""
+    def cost_grad(self, F, poses, Q, w=None, with_scale=False):
+        """Closed-form gradient of sum_k w_k C_k: ([K][3], [n][2]); with
+        with_scale also the sums of |per-point contributions| (same shapes)."""
         F = _f64(F).reshape(-1, 2)
         poses = _f64(poses).reshape(-1, 3)
         Q = _f64(Q).reshape(-1, 2)
@@ -206,9 +209,23 @@ class Oracle:
         w = np.ones(K) if w is None else _f64(w).reshape(K)
         gp = np.zeros((K, 3))
         gF = np.zeros_like(F)
+        ap = np.zeros((K, 3))
+        aF = np.zeros_like(F)
         self.lib.oracle_cost_grad(_p(F), len(F), _p(poses), K, _p(Q), len(Q), _p(w), _p(gp),
-                                  _p(gF))
-        return gp, gF
+                                  _p(gF), _p(ap), _p(aF))
+        return (gp, gF, ap, aF) if with_scale else (gp, gF)
+
+    def cost_with_hash(self, F, poses, Q):
+        """Costs [K] and per-pose hashes of the per-point kink states."""
+        F = _f64(F).reshape(-1, 2)
+        poses = _f64(poses).reshape(-1, 3)
+        Q = _f64(Q).reshape(-1, 2)
+        K = len(poses)
+        c = np.zeros(K)
+        h = np.zeros(K, dtype=np.uint64)
+        self.lib.oracle_cost_with_hash(_p(F), len(F), _p(poses), K, _p(Q), len(Q), _p(c),
+                                       h.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+        return c, h
 
 
 def pack_bits(b: np.ndarray) -> np.ndarray:

@@ -415,10 +415,13 @@ int oracle_cost_state(const double *F, int64_t n, const double *pose, const doub
  *   dd/da   = sigma ((e_y - r_y, r_x - e_x) / L + f e / L^3),
  * with r = p_b - a and f = cross(e, r).  Through p_b = R^T (p - t):
  *   dC/dt = -R dd/dp_b,   dC/dtheta = dd/dp_b . (p_b,y, -p_b,x).
- * grad_pose [K][3] and grad_F [n][2] are overwritten.
+ * grad_pose [K][3] and grad_F [n][2] are overwritten.  abs_pose and abs_F
+ * (optional, same shapes) receive the sums of the magnitudes of the
+ * per-point contributions, the scale against which a float result is judged.
  */
 int oracle_cost_grad(const double *F, int64_t n, const double *poses, int64_t K, const double *Q,
-                     int64_t m, const double *w, double *grad_pose, double *grad_F)
+                     int64_t m, const double *w, double *grad_pose, double *grad_F,
+                     double *abs_pose, double *abs_F)
 {
     double *P = (double *)malloc(sizeof(double) * 2 * (size_t)(n + 1));
     if (!P) return -100;
@@ -429,16 +432,21 @@ int oracle_cost_grad(const double *F, int64_t n, const double *poses, int64_t K,
     /* per-pose footprint gradients, summed over poses in index order so
      * that the result does not depend on the thread count */
     double *gF_pose = (double *)calloc((size_t)K * 2 * (size_t)n, sizeof(double));
-    if (!gF_pose) {
+    double *aF_pose = (double *)calloc((size_t)K * 2 * (size_t)n, sizeof(double));
+    if (!gF_pose || !aF_pose) {
+        free(gF_pose);
+        free(aF_pose);
         free(P);
         return -100;
     }
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < K; ++k) {
         double *gF = gF_pose + (size_t)k * 2 * (size_t)n;
+        double *aF = aF_pose + (size_t)k * 2 * (size_t)n;
         double tx = poses[3 * k], ty = poses[3 * k + 1], th = poses[3 * k + 2];
         double c = cos(th), s = sin(th);
         double gtx = 0.0, gty = 0.0, gth = 0.0;
+        double atx = 0.0, aty = 0.0, ath = 0.0;
         for (int64_t j = 0; j < m; ++j) {
             double dx = Q[2 * j] - tx;
             double dy = Q[2 * j + 1] - ty;
@@ -461,23 +469,80 @@ int oracle_cost_grad(const double *F, int64_t n, const double *poses, int64_t K,
             double rx = bx - ax, ry = by - ay;
             double f = ex * ry - ey * rx;
             double gpx = sigma * (-ey) / L, gpy = sigma * ex / L;
-            gtx += -(c * gpx - s * gpy);
-            gty += -(s * gpx + c * gpy);
-            gth += gpx * by + gpy * (-bx);
+            double ctx_ = -(c * gpx - s * gpy);
+            double cty = -(s * gpx + c * gpy);
+            double cth = gpx * by + gpy * (-bx);
+            gtx += ctx_;
+            gty += cty;
+            gth += cth;
+            atx += fabs(ctx_);
+            aty += fabs(cty);
+            ath += fabs(cth);
             double L3 = L * L * L;
-            gF[2 * ib] += sigma * (ry / L - f * ex / L3);
-            gF[2 * ib + 1] += sigma * (-rx / L - f * ey / L3);
-            gF[2 * ia] += sigma * ((ey - ry) / L + f * ex / L3);
-            gF[2 * ia + 1] += sigma * ((rx - ex) / L + f * ey / L3);
+            double cbx = sigma * (ry / L - f * ex / L3);
+            double cby = sigma * (-rx / L - f * ey / L3);
+            double cax = sigma * ((ey - ry) / L + f * ex / L3);
+            double cay = sigma * ((rx - ex) / L + f * ey / L3);
+            gF[2 * ib] += cbx;
+            gF[2 * ib + 1] += cby;
+            gF[2 * ia] += cax;
+            gF[2 * ia + 1] += cay;
+            aF[2 * ib] += fabs(cbx);
+            aF[2 * ib + 1] += fabs(cby);
+            aF[2 * ia] += fabs(cax);
+            aF[2 * ia + 1] += fabs(cay);
         }
         grad_pose[3 * k] = w[k] * gtx;
         grad_pose[3 * k + 1] = w[k] * gty;
         grad_pose[3 * k + 2] = w[k] * gth;
+        if (abs_pose) {
+            abs_pose[3 * k] = fabs(w[k]) * atx;
+            abs_pose[3 * k + 1] = fabs(w[k]) * aty;
+            abs_pose[3 * k + 2] = fabs(w[k]) * ath;
+        }
     }
-    for (int64_t i = 0; i < 2 * n; ++i) grad_F[i] = 0.0;
+    for (int64_t i = 0; i < 2 * n; ++i) {
+        grad_F[i] = 0.0;
+        if (abs_F) abs_F[i] = 0.0;
+    }
     for (int64_t k = 0; k < K; ++k)
-        for (int64_t i = 0; i < 2 * n; ++i) grad_F[i] += w[k] * gF_pose[(size_t)k * 2 * (size_t)n + (size_t)i];
+        for (int64_t i = 0; i < 2 * n; ++i) {
+            grad_F[i] += w[k] * gF_pose[(size_t)k * 2 * (size_t)n + (size_t)i];
+            if (abs_F) abs_F[i] += fabs(w[k]) * aF_pose[(size_t)k * 2 * (size_t)n + (size_t)i];
+        }
     free(gF_pose);
+    free(aF_pose);
+    free(P);
+    return rc;
+}
+
+/*
+ * Costs of K poses plus, per pose, a 64-bit hash of every point's
+ * (contributes?, minimising edge) state, so that finite differences can tell
+ * whether a perturbation crossed a relu or min kink for any point.
+ */
+int oracle_cost_with_hash(const double *F, int64_t n, const double *poses, int64_t K,
+                          const double *Q, int64_t m, double *cost, uint64_t *hash)
+{
+    double *P = (double *)malloc(sizeof(double) * 2 * (size_t)(n + 1));
+    if (!P) return -100;
+    int rc = oracle_generators(F, n, P);
+#pragma omp parallel
+    {
+        int32_t *st = (int32_t *)malloc(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < K; ++k) {
+            double th = poses[3 * k + 2];
+            cost[k] = cost_one_pose(P, n, poses[3 * k], poses[3 * k + 1], cos(th), sin(th), Q, m, st);
+            uint64_t h = 1469598103934665603ull;
+            for (int64_t j = 0; j < m; ++j) {
+                h ^= (uint64_t)(uint32_t)(st[j] + 2) * 0x9E3779B97F4A7C15ull + (uint64_t)j;
+                h *= 1099511628211ull;
+            }
+            hash[k] = h;
+        }
+        free(st);
+    }
     free(P);
     return rc;
 }

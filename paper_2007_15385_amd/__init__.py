@@ -19,11 +19,13 @@ from .api import (BatchedPlan, batched_workspace_bytes, label_word_offsets, pip_
                   pip_ray_crossing, pip_sign_of_offset, pip_voronoi, pip_voronoi_allpairs,
                   pip_voronoi_batched, pip_voronoi_fp32_plain, pip_voronoi_max_margin,
                   polygon_to_generators, unpack_labels)
+from .autograd import CollisionCost, collision_cost, pip_cost_bwd, pip_cost_fwd
 
 __all__ = [
     "PIP_F32", "PIP_F64", "PipError", "lib_path", "load_library", "num_label_words",
     "status_name", "polygon_to_generators", "pip_voronoi", "pip_sign_of_offset",
     "pip_ray_crossing", "pip_voronoi_fp32_plain", "pip_voronoi_max_margin", "unpack_labels",
     "pip_voronoi_batched", "batched_workspace_bytes", "label_word_offsets", "BatchedPlan",
-    "pip_poses_to_polygons", "pip_voronoi_allpairs",
+    "pip_poses_to_polygons", "pip_voronoi_allpairs", "pip_cost_fwd", "pip_cost_bwd",
+    "CollisionCost", "collision_cost",
 ]

@@ -599,4 +599,74 @@ pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double*
     return PIP_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// differentiable collision cost
+// ---------------------------------------------------------------------------
+size_t pip_cost_workspace_bytes(int32_t n, int64_t K, int64_t m) {
+    if (n < 3 || n > pipdev::cost_max_edges() || K < 0 || m < 0) return 0;
+    pipdev::CostLayout L;
+    return pipdev::cost_workspace_layout(n, K, m, &L);
+}
+
+}  // extern "C"
+
+namespace {
+pip_status check_cost(pip_ctx ctx, const float* F, int32_t n, const float* pose, int64_t K,
+                      const float* Q, int64_t m, void* ws, size_t ws_bytes) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (!F || !aligned(F, 4)) return fail(PIP_EINVAL, "footprint is NULL or misaligned");
+    if (n < 3) return fail(PIP_EINVAL, "n = %d: a polygon needs at least 3 vertices", (int)n);
+    if (n > pipdev::cost_max_edges())
+        return fail(PIP_EUNSUPPORTED, "n = %d exceeds the cost path's limit of %d edges", (int)n,
+                    pipdev::cost_max_edges());
+    if (K < 0 || m < 0) return fail(PIP_EINVAL, "K and m must be >= 0");
+    if (K > 0 && (!pose || !aligned(pose, 4))) return fail(PIP_EINVAL, "pose is NULL or misaligned");
+    if (m > 0 && (!Q || !aligned(Q, 8))) return fail(PIP_EINVAL, "Q is NULL or not 8-byte aligned");
+    if (K > ((int64_t)1 << 31) || m > ((int64_t)1 << 40)) return fail(PIP_EUNSUPPORTED, "too large");
+    const size_t need = pip_cost_workspace_bytes(n, K, m);
+    if (!ws || ws_bytes < need)
+        return fail(PIP_EINVAL, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
+    if (!aligned(ws, 256)) return fail(PIP_EINVAL, "workspace is not 256-byte aligned");
+    return PIP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pip_status pip_cost_fwd(pip_ctx ctx, const float* footprint, int32_t n, const float* pose, int64_t K,
+                        const float* Q, int64_t m, float* cost, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream) {
+    pip_status s = check_cost(ctx, footprint, n, pose, K, Q, m, workspace, workspace_bytes);
+    if (s != PIP_OK) return s;
+    if (K > 0 && (!cost || !aligned(cost, 4))) return fail(PIP_EINVAL, "cost is NULL or misaligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_cost(false, footprint, n, pose, K, Q, m, nullptr, cost, nullptr,
+                                       nullptr, nullptr, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+pip_status pip_cost_bwd(pip_ctx ctx, const float* footprint, int32_t n, const float* pose, int64_t K,
+                        const float* Q, int64_t m, const float* grad_cost, float* grad_pose,
+                        float* grad_footprint, float* residual, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream) {
+    pip_status s = check_cost(ctx, footprint, n, pose, K, Q, m, workspace, workspace_bytes);
+    if (s != PIP_OK) return s;
+    if (K > 0 && (!grad_cost || !aligned(grad_cost, 4)))
+        return fail(PIP_EINVAL, "grad_cost is NULL or misaligned");
+    if (K > 0 && (!grad_pose || !aligned(grad_pose, 4)))
+        return fail(PIP_EINVAL, "grad_pose is NULL or misaligned");
+    if (!grad_footprint || !aligned(grad_footprint, 4))
+        return fail(PIP_EINVAL, "grad_footprint is NULL or misaligned");
+    if (residual && !aligned(residual, 4)) return fail(PIP_EINVAL, "residual is misaligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_cost(true, footprint, n, pose, K, Q, m, grad_cost, nullptr, grad_pose,
+                                       grad_footprint, residual, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
 }  // extern "C"

@@ -1,0 +1,425 @@
+// Differentiable collision cost of a convex footprint at many poses against
+// a point cloud, built on the Voronoi margin (Section 4, Eq. 11).
+//
+// For edge i the margin m_i = |p - p_0|^2 - |p - p_i|^2 divided by
+// -2|p_i - p_0| is the signed distance of p to edge line i, positive on the
+// side of p_0:  d_i(p) = k_i - n_i.p,  n_i = h_i / |h_i|,
+// k_i = n_i.p_0 + |h_i|/2,  h_i = p_i - p_0  (p_i = p_0 mirrored across the
+// edge line, Eq. 8).  The cost of pose (t, theta) is
+//     C = sum_j relu(min_i d_i(p_b,j)),   p_b = R(theta)^T (p_j - t),
+// the total penetration depth of the cloud into the footprint.
+//
+//   k_cost_prepare   one wave: generators of the footprint in binary64
+//                    (Algorithms 3-4), float32 line table (-n_x, -n_y, k, |h|)
+//                    and p_0.
+//   k_cost<false>    forward: workgroup = 1024-point tile x 64 poses; per
+//                    (pose, point) body-frame coordinates, min over edges,
+//                    relu; per-(pose, tile) partial sums in a fixed order.
+//   k_cost<true>     backward: recomputes the minimising edge (lowest index on
+//                    ties) and accumulates, for every contributing pair,
+//                    d/dt = R n, d/dtheta = -n_x p_b,y + n_y p_b,x (pose
+//                    partials) and the derivatives of d to p_i and p_0 (table
+//                    partials, per-lane LDS accumulators, no float atomics).
+//   k_cost_finish    per pose: binary64 sum of the partials in tile order.
+//   k_gen_backward   binary64 sum of the table partials, then the chain rule
+//                    through the reflection (Eq. 8) and the centroid
+//                    (Algorithm 3) to the footprint vertices.  The path
+//                    through p_0 cancels in exact arithmetic (d_i depends on
+//                    the edge line only); its float residual is reported.
+#include "device.hpp"
+#include "kernels.hpp"
+
+using namespace pipdev;
+
+namespace {
+
+constexpr int kTile = kBlock * kPPL;  // 1024 points per workgroup
+constexpr int kPG = 64;               // poses per workgroup
+constexpr int kCostMaxEdges = 16;     // footprint size limit of the cost path
+
+struct CostTab {
+    float4 line[kMaxEdges];  // (-n_x, -n_y, k, |h|)
+    float2 g0;
+    int n, n4, status;
+};
+
+__global__ __launch_bounds__(kWave) void k_cost_prepare(const float* __restrict__ F, int n,
+                                                      CostTab* __restrict__ tab) {
+    __shared__ PolyLds S;
+    const int lane = threadIdx.x;
+    if (lane < n) S.vtx[lane] = make_double2((double)F[2 * lane], (double)F[2 * lane + 1]);
+    if (lane == 0) S.n = n;
+    __syncthreads();
+    prepare_polygon(S, K_VORONOI, lane);
+    __syncthreads();
+    const int i = lane < n ? lane : 0;
+    const double2 g0 = S.gen[0], gi = S.gen[1 + i];
+    const double hx = gi.x - g0.x, hy = gi.y - g0.y;
+    const double L = sqrt(hx * hx + hy * hy);
+    const double nx = hx / L, ny = hy / L;
+    const double k = (nx * g0.x + ny * g0.y) + 0.5 * L;
+    tab->line[lane] = make_float4((float)(-nx), (float)(-ny), (float)k, (float)L);
+    if (lane == 0) {
+        tab->g0 = make_float2((float)g0.x, (float)g0.y);
+        tab->n = n;
+        tab->n4 = (n + 3) & ~3;
+        tab->status = S.status;
+    }
+}
+
+struct PoseCS {
+    float c, s, tx, ty;
+};
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// grid: x = point tiles, y = pose groups of kPG.
+template <bool BWD>
+__global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab,
+                                               const float* __restrict__ pose, int64_t K,
+                                               const float2* __restrict__ Q, int64_t m,
+                                               const float* __restrict__ grad_cost,
+                                               float* __restrict__ part_cost,
+                                               float* __restrict__ part_pose,
+                                               float* __restrict__ part_gen, int T) {
+    __shared__ float4 line_s[kMaxEdges];
+    __shared__ PoseCS pose_s[kPG];
+    __shared__ float red_s[kPG][kWavesPerBlock][3];
+    // backward only: per-lane accumulators [wave][component][lane], 2(n+1)
+    // components (p_0, then p_i), each lane adding to its own slots in order
+    extern __shared__ float acc_dyn[];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int n = tab->n, n4 = tab->n4;
+    const float2 g0 = tab->g0;
+    const int64_t k0 = (int64_t)blockIdx.y * kPG;
+    const int pg = (int)((K - k0) < kPG ? (K - k0) : kPG);
+    const int t = blockIdx.x;
+
+    if (tid < n4) line_s[tid] = tab->line[tid];
+    if (tid < pg) {
+        const float* pp = pose + 3 * (k0 + tid);
+        const double th = (double)pp[2];
+        PoseCS P;
+        P.c = (float)cos(th);
+        P.s = (float)sin(th);
+        P.tx = pp[0];
+        P.ty = pp[1];
+        pose_s[tid] = P;
+    }
+    const int ncomp = 2 * (n + 1);
+    auto acc = [&](int q, int c, int l) -> float& { return acc_dyn[(q * ncomp + c) * kWave + l]; };
+    if constexpr (BWD) {
+        for (int i = tid; i < kWavesPerBlock * ncomp * kWave; i += kBlock) acc_dyn[i] = 0.f;
+    }
+    const int64_t base = (int64_t)t * kTile + (int64_t)wv * kChunk;
+    float x[kPPL], y[kPPL];
+    bool valid[kPPL];
+#pragma unroll
+    for (int j = 0; j < kPPL; ++j) {
+        const int64_t i = base + lane + kWave * j;
+        valid[j] = i < m;
+        const float2 p = Q[valid[j] ? i : 0];
+        x[j] = p.x;
+        y[j] = p.y;
+        valid[j] = valid[j] && isfinite(p.x) && isfinite(p.y);  // contributes nothing otherwise
+    }
+    __syncthreads();
+
+    for (int p = 0; p < pg; ++p) {
+        const PoseCS P = pose_s[p];
+        float bx[kPPL], by[kPPL], dmin[kPPL];
+        int arg[kPPL];
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            const float dx = x[j] - P.tx, dy = y[j] - P.ty;
+            bx[j] = fmaf(P.c, dx, P.s * dy);
+            by[j] = fmaf(P.c, dy, -(P.s * dx));
+            dmin[j] = __builtin_huge_valf();
+            arg[j] = 0;
+        }
+        for (int e = 0; e < n; ++e) {
+            const float4 L = line_s[e];
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                const float d = fmaf(L.x, bx[j], fmaf(L.y, by[j], L.z));
+                if constexpr (BWD) {
+                    if (d < dmin[j]) {
+                        dmin[j] = d;
+                        arg[j] = e;
+                    }
+                } else {
+                    dmin[j] = fminf(dmin[j], d);
+                }
+            }
+        }
+        if constexpr (!BWD) {
+            float sum = 0.f;
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) sum += (valid[j] && dmin[j] > 0.f) ? dmin[j] : 0.f;
+            sum = wave_sum(sum);
+            if (lane == 0) red_s[p][wv][0] = sum;
+        } else {
+            const float w = grad_cost[k0 + p];
+            float sx = 0.f, sy = 0.f, sth = 0.f;
+#pragma unroll
+            for (int j = 0; j < kPPL; ++j) {
+                if (valid[j] && dmin[j] > 0.f) {
+                    const float4 L = line_s[arg[j]];
+                    const float nx = -L.x, ny = -L.y, len = L.w;
+                    sx += nx;
+                    sy += ny;
+                    sth += fmaf(-nx, by[j], ny * bx[j]);
+                    // derivatives of d = |h|/2 - u.h/|h| (u = p_b - p_0) to h and p_0
+                    const float ux = bx[j] - g0.x, uy = by[j] - g0.y;
+                    const float un = fmaf(ux, nx, uy * ny);
+                    const float dhx = 0.5f * nx - (ux - un * nx) / len;
+                    const float dhy = 0.5f * ny - (uy - un * ny) / len;
+                    const int a = arg[j];
+                    acc(wv, 2 * (1 + a), lane) += w * dhx;
+                    acc(wv, 2 * (1 + a) + 1, lane) += w * dhy;
+                    acc(wv, 0, lane) += w * (nx - dhx);
+                    acc(wv, 1, lane) += w * (ny - dhy);
+                }
+            }
+            sx = wave_sum(sx);
+            sy = wave_sum(sy);
+            sth = wave_sum(sth);
+            if (lane == 0) {
+                red_s[p][wv][0] = sx;
+                red_s[p][wv][1] = sy;
+                red_s[p][wv][2] = sth;
+            }
+        }
+    }
+    __syncthreads();
+    // per-(pose, tile) partials, waves summed in a fixed order
+    if constexpr (!BWD) {
+        if (tid < pg) {
+            float s = red_s[tid][0][0];
+            for (int q = 1; q < kWavesPerBlock; ++q) s += red_s[tid][q][0];
+            part_cost[(k0 + tid) * T + t] = s;
+        }
+    } else {
+        if (tid < pg) {
+            for (int c = 0; c < 3; ++c) {
+                float s = red_s[tid][0][c];
+                for (int q = 1; q < kWavesPerBlock; ++q) s += red_s[tid][q][c];
+                part_pose[((k0 + tid) * T + t) * 3 + c] = s;
+            }
+        }
+        // table partials of this workgroup: lanes, then waves, in a fixed order
+        for (int c = tid; c < ncomp; c += kBlock) {
+            float s = 0.f;
+            for (int q = 0; q < kWavesPerBlock; ++q)
+                for (int l = 0; l < kWave; ++l) s += acc(q, c, l);
+            part_gen[((int64_t)blockIdx.y * T + t) * (2 * (kMaxEdges + 1)) + c] = s;
+        }
+    }
+}
+
+__global__ void k_cost_finish(const float* __restrict__ part_cost, int64_t K, int T,
+                              float* __restrict__ cost) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double s = 0.0;
+    for (int t = 0; t < T; ++t) s += (double)part_cost[k * T + t];
+    cost[k] = (float)s;
+}
+
+__global__ void k_pose_grad_finish(const float* __restrict__ part_pose, const float* __restrict__ pose,
+                                   const float* __restrict__ grad_cost, int64_t K, int T,
+                                   float* __restrict__ grad_pose) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    double sx = 0.0, sy = 0.0, st = 0.0;
+    for (int t = 0; t < T; ++t) {
+        sx += (double)part_pose[(k * T + t) * 3 + 0];
+        sy += (double)part_pose[(k * T + t) * 3 + 1];
+        st += (double)part_pose[(k * T + t) * 3 + 2];
+    }
+    const double th = (double)pose[3 * k + 2];
+    const double c = (double)(float)cos(th), s = (double)(float)sin(th);
+    const double w = (double)grad_cost[k];
+    grad_pose[3 * k + 0] = (float)(w * (c * sx - s * sy));  // R n summed
+    grad_pose[3 * k + 1] = (float)(w * (s * sx + c * sy));
+    grad_pose[3 * k + 2] = (float)(w * st);
+}
+
+// One workgroup: binary64 sums of the table partials (fixed order), then the
+// chain rule to the vertices.  residual (optional, [2]): |total gradient to
+// p_0| and the scale it is measured against.
+__global__ __launch_bounds__(256) void k_gen_backward(const float* __restrict__ F, int n,
+                                                    const float* __restrict__ part_gen, int64_t nparts,
+                                                    float* __restrict__ grad_F,
+                                                    float* __restrict__ residual) {
+    constexpr int NC = 2 * (kMaxEdges + 1);
+    __shared__ double red[256];
+    __shared__ double G[NC];
+    const int tid = threadIdx.x;
+    const int ncomp = 2 * (n + 1);
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int64_t i = tid; i < nparts; i += 256) s += (double)part_gen[i * NC + c];
+        red[tid] = s;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red[tid] += red[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) G[c] = red[0];
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    // forward quantities in binary64 (Algorithms 3-4, same order as the
+    // preparation kernel)
+    double vx[kMaxEdges], vy[kMaxEdges], gV[2 * kMaxEdges];
+    for (int i = 0; i < n; ++i) {
+        vx[i] = (double)F[2 * i];
+        vy[i] = (double)F[2 * i + 1];
+        gV[2 * i] = 0.0;
+        gV[2 * i + 1] = 0.0;
+    }
+    double S = 0.0, Sx = 0.0, Sy = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const int j = prev_edge(i, n);
+        const double Ai = vx[j] * vy[i] - vx[i] * vy[j];
+        S = S + Ai;
+        Sx = Sx + (vx[i] + vx[j]) * Ai;
+        Sy = Sy + (vy[i] + vy[j]) * Ai;
+    }
+    const double g0x = Sx / (3.0 * S), g0y = Sy / (3.0 * S);
+    double Gg0x = G[0], Gg0y = G[1];
+    double scale = fabs(G[0]) + fabs(G[1]);
+    // reflections: g = (W g0 - 2 c [a; b]) / (a^2 + b^2), edge v_{i-1} -> v_i
+    for (int i = 0; i < n; ++i) {
+        const int j = prev_edge(i, n);
+        const double bx = vx[i], by = vy[i], ax = vx[j], ay = vy[j];
+        const double ea = by - ay, eb = ax - bx;
+        const double ec = -(ea * bx + eb * by);
+        const double den = ea * ea + eb * eb;
+        const double w11 = eb * eb - ea * ea, w12 = -2.0 * ea * eb, w22 = ea * ea - eb * eb;
+        const double Nx = w11 * g0x + w12 * g0y - 2.0 * ec * ea;
+        const double Ny = w12 * g0x + w22 * g0y - 2.0 * ec * eb;
+        const double Gx = G[2 * (1 + i)], Gy = G[2 * (1 + i) + 1];
+        scale += fabs(Gx) + fabs(Gy);
+        const double GNx = Gx / den, GNy = Gy / den;
+        const double Gden = -(Gx * Nx + Gy * Ny) / (den * den);
+        double Gea = 2.0 * ea * Gden, Geb = 2.0 * eb * Gden;
+        Gea += GNx * (-2.0 * ea * g0x - 2.0 * eb * g0y - 2.0 * ec) + GNy * (-2.0 * eb * g0x + 2.0 * ea * g0y);
+        Geb += GNx * (2.0 * eb * g0x - 2.0 * ea * g0y) + GNy * (-2.0 * ea * g0x - 2.0 * eb * g0y - 2.0 * ec);
+        const double Gec = GNx * (-2.0 * ea) + GNy * (-2.0 * eb);
+        Gg0x += w11 * GNx + w12 * GNy;
+        Gg0y += w12 * GNx + w22 * GNy;
+        // ec = -(ea bx + eb by)
+        Gea += -bx * Gec;
+        Geb += -by * Gec;
+        gV[2 * i] += -ea * Gec;
+        gV[2 * i + 1] += -eb * Gec;
+        // ea = by - ay, eb = ax - bx
+        gV[2 * i + 1] += Gea;
+        gV[2 * j + 1] -= Gea;
+        gV[2 * j] += Geb;
+        gV[2 * i] -= Geb;
+    }
+    // centroid: g0 = (Sx, Sy) / (3 S)
+    const double GSx = Gg0x / (3.0 * S), GSy = Gg0y / (3.0 * S);
+    const double GS = -(Gg0x * Sx + Gg0y * Sy) / (3.0 * S * S);
+    for (int i = 0; i < n; ++i) {
+        const int j = prev_edge(i, n);
+        const double Ai = vx[j] * vy[i] - vx[i] * vy[j];
+        const double GA = GS + GSx * (vx[i] + vx[j]) + GSy * (vy[i] + vy[j]);
+        gV[2 * i] += GSx * Ai;
+        gV[2 * j] += GSx * Ai;
+        gV[2 * i + 1] += GSy * Ai;
+        gV[2 * j + 1] += GSy * Ai;
+        gV[2 * j] += GA * vy[i];
+        gV[2 * i + 1] += GA * vx[j];
+        gV[2 * i] -= GA * vy[j];
+        gV[2 * j + 1] -= GA * vx[i];
+    }
+    for (int i = 0; i < 2 * n; ++i) grad_F[i] = (float)gV[i];
+    if (residual) {
+        residual[0] = (float)sqrt(Gg0x * Gg0x + Gg0y * Gg0y);
+        residual[1] = (float)scale;
+    }
+}
+
+}  // namespace
+
+namespace pipdev {
+
+int cost_max_edges() { return kCostMaxEdges; }
+
+size_t cost_workspace_layout(int n, int64_t K, int64_t m, CostLayout* L) {
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    (void)n;
+    const int64_t T = (m + kTile - 1) / kTile;
+    const int64_t G = (K + kPG - 1) / kPG;
+    size_t off = 0;
+    L->tab = off;
+    off = up(off + sizeof(CostTab));
+    L->part_cost = off;
+    off = up(off + 4 * (size_t)(K * (T > 0 ? T : 1)));
+    L->part_pose = off;
+    off = up(off + 12 * (size_t)(K * (T > 0 ? T : 1)));
+    L->part_gen = off;
+    off = up(off + 4 * (size_t)(G * (T > 0 ? T : 1)) * 2 * (kMaxEdges + 1));
+    L->T = (int)T;
+    L->G = G;
+    return off;
+}
+
+hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, int64_t K,
+                       const float* Q, int64_t m, const float* grad_cost, float* cost,
+                       float* grad_pose, float* grad_F, float* residual, void* ws,
+                       hipStream_t stream) {
+    CostLayout L;
+    cost_workspace_layout(n, K, m, &L);
+    char* b = static_cast<char*>(ws);
+    CostTab* tab = reinterpret_cast<CostTab*>(b + L.tab);
+    float* pc = reinterpret_cast<float*>(b + L.part_cost);
+    float* pp = reinterpret_cast<float*>(b + L.part_pose);
+    float* pgn = reinterpret_cast<float*>(b + L.part_gen);
+    hipLaunchKernelGGL(k_cost_prepare, dim3(1), dim3(kWave), 0, stream, F, n, tab);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int T = L.T > 0 ? L.T : 1;
+    if (L.T > 0 && K > 0) {
+        dim3 grid((unsigned)L.T, (unsigned)L.G);
+        if (!backward)
+            hipLaunchKernelGGL(k_cost<false>, grid, dim3(kBlock), 0, stream, tab, pose, K,
+                               reinterpret_cast<const float2*>(Q), m, grad_cost, pc, pp, pgn, T);
+        else
+            hipLaunchKernelGGL(k_cost<true>, grid, dim3(kBlock),
+                               (size_t)kWavesPerBlock * 2 * (n + 1) * kWave * sizeof(float), stream,
+                               tab, pose, K, reinterpret_cast<const float2*>(Q), m, grad_cost, pc,
+                               pp, pgn, T);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else {
+        // no points: every partial is zero
+        const size_t nb = backward ? (size_t)L.G * T * 2 * (kMaxEdges + 1) * 4 : (size_t)K * T * 4;
+        if ((e = hipMemsetAsync(backward ? (void*)pgn : (void*)pc, 0, nb, stream)) != hipSuccess)
+            return e;
+        if (backward && (e = hipMemsetAsync(pp, 0, (size_t)K * T * 12, stream)) != hipSuccess)
+            return e;
+    }
+    const unsigned kb = (unsigned)((K + 255) / 256);
+    if (!backward) {
+        if (K > 0) hipLaunchKernelGGL(k_cost_finish, dim3(kb), dim3(256), 0, stream, pc, K, T, cost);
+    } else {
+        if (K > 0)
+            hipLaunchKernelGGL(k_pose_grad_finish, dim3(kb), dim3(256), 0, stream, pp, pose, grad_cost,
+                               K, T, grad_pose);
+        hipLaunchKernelGGL(k_gen_backward, dim3(1), dim3(256), 0, stream, F, n, pgn,
+                           (int64_t)L.G * T, grad_F, residual);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pipdev

@@ -73,6 +73,17 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws,
                            hipStream_t stream);
+struct CostLayout {
+    size_t tab, part_cost, part_pose, part_gen;
+    int T;
+    int64_t G;
+};
+int cost_max_edges();
+size_t cost_workspace_layout(int n, int64_t K, int64_t m, CostLayout* L);
+hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, int64_t K,
+                       const float* Q, int64_t m, const float* grad_cost, float* cost,
+                       float* grad_pose, float* grad_F, float* residual, void* ws,
+                       hipStream_t stream);
 hipError_t launch_count_diff(const uint32_t* a, const uint32_t* b, int64_t nwords,
                              unsigned long long* out, hipStream_t stream);
 hipError_t launch_generators_one(const double* V, int n, double* P, int32_t* status,

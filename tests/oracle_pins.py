@@ -428,6 +428,28 @@ def pin_cost_gradient_cw(o):
     assert np.allclose(gF, gF2[::-1], rtol=1e-9, atol=1e-9)
 
 
+def pin_cost_hash(o):
+    """oracle_cost_with_hash returns the same costs as oracle_cost, a hash
+    that changes when one point crosses the footprint boundary, and the
+    same hash when a far point moves a little."""
+    rng = _rng(11)
+    F = W.car_footprint()
+    Q = rng.uniform(-3, 3, size=(800, 2))
+    poses = np.array([[0.1, 0.0, 0.2], [0.5, -0.3, 1.1]])
+    c, h = o.cost_with_hash(F, poses, Q)
+    assert np.allclose(c, o.cost(F, poses, Q), rtol=0, atol=0)
+    Q2 = Q.copy()
+    Q2[0] = [0.0, 0.0]          # now inside both placements
+    Q2[1] = [50.0, 50.0]
+    _, h2 = o.cost_with_hash(F, poses, Q2)
+    Q3 = Q2.copy()
+    Q3[1] = [50.0, 50.5]        # far point moves: state unchanged
+    _, h3 = o.cost_with_hash(F, poses, Q3)
+    assert np.all(h2 == h3) and np.any(h != h2)
+    gp, gF, ap, aF = o.cost_grad(F, poses, Q, with_scale=True)
+    assert np.all(np.abs(gp) <= ap + 1e-12) and np.all(np.abs(gF) <= aF + 1e-12)
+
+
 ALL_PINS = [
     pin_square_and_triangle,
     pin_regular_ngon,
@@ -446,4 +468,5 @@ ALL_PINS = [
     pin_cost_rigid_invariance,
     pin_cost_gradient_fd,
     pin_cost_gradient_cw,
+    pin_cost_hash,
 ]

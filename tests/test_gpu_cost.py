@@ -1,0 +1,183 @@
+"""GPU collision cost (forward + hand-written backward) against the FP64
+oracle: cost within 1e-4 relative, gradients against the oracle's closed
+form and against binary64 central finite differences (h = 1e-6) on 16
+trajectories, with entries whose kink state changes excluded."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+H = 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_15385_amd as P
+    P.load_library()
+    return P
+
+
+@pytest.fixture(scope="module")
+def scene():
+    F = W.car_footprint().astype(np.float32)
+    Q = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)
+    trajs = W.trajectories()
+    rng = np.random.default_rng(55)
+    pick = np.sort(rng.choice(len(trajs), 16, replace=False))
+    poses = trajs[pick].reshape(-1, 3)
+    return F, Q, poses
+
+
+def gpu_cost(P, F, poses, Q):
+    c = P.pip_cost_fwd(torch.from_numpy(F).cuda(), torch.from_numpy(poses).cuda(),
+                       torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    return c.cpu().numpy()
+
+
+def gpu_grad(P, F, poses, Q, w):
+    gp, gF, res = P.pip_cost_bwd(torch.from_numpy(F).cuda(), torch.from_numpy(poses).cuda(),
+                                 torch.from_numpy(Q).cuda(), torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    return gp.cpu().numpy(), gF.cpu().numpy(), res.cpu().numpy()
+
+
+def test_cost_forward_small(P, oracle):
+    rng = np.random.default_rng(1)
+    F = W.car_footprint().astype(np.float32)
+    Q = rng.uniform(-4, 4, size=(5000, 2)).astype(np.float32)
+    Q[::331] = np.nan
+    poses = np.stack([rng.uniform(-1, 1, 130), rng.uniform(-1, 1, 130),
+                      rng.uniform(-np.pi, np.pi, 130)], 1).astype(np.float32)
+    got = gpu_cost(P, F, poses, Q)
+    want = oracle.cost(F.astype(np.float64), poses.astype(np.float64), Q.astype(np.float64))
+    assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + 1e-6), np.abs(got - want).max()
+    assert want.max() > 0
+
+
+def test_cost_golden_cases(P):
+    import json
+    import os
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "collision_cost.json")))
+    for case in d["cases"]:
+        F = (W.car_footprint() if case["footprint"] == "car" else
+             np.array(case["footprint"], dtype=float)).astype(np.float32)
+        got = gpu_cost(P, F, np.array([case["pose"]], np.float32),
+                       np.array(case["points"], np.float32))
+        assert abs(got[0] - case["cost"]) <= 1e-6 * max(1.0, case["cost"]), (case, got)
+
+
+def test_cost_gradient_vs_closed_form_and_fd(P, oracle, scene):
+    F, Q, poses = scene
+    F64, Q64, p64 = F.astype(np.float64), Q.astype(np.float64), poses.astype(np.float64)
+    K = len(poses)
+    rng = np.random.default_rng(2)
+    w = rng.uniform(0.5, 2.0, K).astype(np.float32)
+
+    c_gpu = gpu_cost(P, F, poses, Q)
+    c_ref, _ = oracle.cost_with_hash(F64, p64, Q64)
+    assert np.all(np.abs(c_gpu - c_ref) <= 1e-4 * np.abs(c_ref) + 1e-6)
+    say(f"[stat] cost: {int((c_ref > 0).sum())} of {K} poses penetrate")
+
+    gp, gF, res = gpu_grad(P, F, poses, Q, w)
+    gp_ref, gF_ref, ap, aF = oracle.cost_grad(F64, p64, Q64, w.astype(np.float64), with_scale=True)
+
+    # zero-cost poses: gradient exactly zero
+    zero = c_ref == 0
+    assert np.all(gp[zero & (c_gpu == 0)] == 0.0)
+
+    # closed form (same kink conventions; float32 vs binary64)
+    assert np.all(np.abs(gp - gp_ref) <= 1e-4 * (np.abs(gp_ref) + ap) + 1e-7)
+    assert np.all(np.abs(gF - gF_ref) <= 1e-4 * (np.abs(gF_ref) + aF) + 1e-7)
+
+    # binary64 central differences of the oracle cost, pose parameters
+    fd = np.zeros((K, 3))
+    ok = np.zeros((K, 3), dtype=bool)
+    for d in range(3):
+        pp = p64.copy()
+        pm = p64.copy()
+        pp[:, d] += H
+        pm[:, d] -= H
+        cp, hp = oracle.cost_with_hash(F64, pp, Q64)
+        cm, hm = oracle.cost_with_hash(F64, pm, Q64)
+        fd[:, d] = w * (cp - cm) / (2 * H)
+        ok[:, d] = hp == hm
+    sel = ok & (c_ref[:, None] > 0)
+    err = np.abs(gp - fd)
+    say(f"[stat] pose FD: {int(sel.sum())} compared, {int((~ok).sum())} excluded at kinks, "
+        f"max rel err {float((err[sel] / (np.abs(fd[sel]) + ap[sel])).max()):.2e}")
+    assert sel.sum() > 100
+    assert np.all(err[sel] <= 1e-4 * (np.abs(fd[sel]) + ap[sel]) + 1e-7)
+    assert np.linalg.norm((gp - fd)[sel]) <= 1e-4 * np.linalg.norm(fd[sel])
+
+    # footprint vertices (through the generator construction on the GPU)
+    fdF = np.zeros_like(F64)
+    okF = np.zeros(F64.shape, dtype=bool)
+    for i in range(len(F64)):
+        for d in range(2):
+            Fp = F64.copy()
+            Fm = F64.copy()
+            Fp[i, d] += H
+            Fm[i, d] -= H
+            cp, hp = oracle.cost_with_hash(Fp, p64, Q64)
+            cm, hm = oracle.cost_with_hash(Fm, p64, Q64)
+            fdF[i, d] = np.dot(w, cp - cm) / (2 * H)
+            okF[i, d] = np.array_equal(hp, hm)
+    errF = np.abs(gF - fdF)
+    say(f"[stat] footprint FD: {int(okF.sum())} of {okF.size} compared, max rel err "
+        f"{float((errF[okF] / (np.abs(fdF[okF]) + aF[okF])).max()):.2e}; g0 residual "
+        f"{res[0]:.3e} of {res[1]:.3e}")
+    assert okF.sum() >= 8
+    assert np.all(errF[okF] <= 1e-4 * (np.abs(fdF[okF]) + aF[okF]) + 1e-7)
+    assert np.linalg.norm((gF - fdF)[okF]) <= 1e-4 * np.linalg.norm(fdF[okF])
+    assert res[0] <= 1e-4 * res[1]
+
+
+def test_cost_backward_deterministic_and_autograd(P, scene):
+    F, Q, poses = scene
+    w = np.ones(len(poses), np.float32)
+    a = gpu_grad(P, F, poses, Q, w)
+    b = gpu_grad(P, F, poses, Q, w)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    Ft = torch.from_numpy(F).cuda().requires_grad_(True)
+    pt = torch.from_numpy(poses).cuda().reshape(16, 64, 3).requires_grad_(True)
+    Qt = torch.from_numpy(Q).cuda()
+    c = P.collision_cost(pt, Ft, Qt)
+    assert c.shape == (16, 64)
+    c.sum().backward()
+    assert np.array_equal(pt.grad.reshape(-1, 3).cpu().numpy(), a[0])
+    assert np.array_equal(Ft.grad.cpu().numpy(), a[1])
+    c2 = P.pip_cost_fwd(Ft.detach(), pt.detach(), Qt)
+    assert torch.equal(c2.reshape(16, 64), c.detach())
+
+
+def test_cost_full_size_timing(P, oracle):
+    """1024 trajectories x 64 poses against 65,536 points (2^32 pairs): the
+    forward and backward run; costs of 256 sampled poses against the oracle."""
+    F = W.car_footprint().astype(np.float32)
+    Q = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)
+    poses = W.trajectories().reshape(-1, 3)
+    Ft, pt, Qt = (torch.from_numpy(F).cuda(), torch.from_numpy(poses).cuda(),
+                  torch.from_numpy(Q).cuda())
+    c = P.pip_cost_fwd(Ft, pt, Qt)
+    gp, gF, res = P.pip_cost_bwd(Ft, pt, Qt, torch.ones_like(c))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    idx = rng.choice(len(poses), 256, replace=False)
+    want = oracle.cost(F.astype(np.float64), poses[idx].astype(np.float64), Q.astype(np.float64))
+    got = c.cpu().numpy()[idx]
+    assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + 1e-6)
+    assert torch.isfinite(gp).all() and torch.isfinite(gF).all()

@@ -44,12 +44,13 @@ MUTANTS = [
     ("cost_body_frame_sign", "double by = (-s) * dx + c * dy;\n        double best = 0.0;",
      "double by = s * dx + c * dy;\n        double best = 0.0;"),
     ("normalized_margin_scale", "return -(M0 - Mi) / (2.0 * len);", "return -(M0 - Mi) / len;"),
-    ("grad_theta_swap", "gth += gpx * by + gpy * (-bx);", "gth += gpx * bx + gpy * (-by);"),
-    ("grad_t_sign", "gtx += -(c * gpx - s * gpy);", "gtx += -(c * gpx + s * gpy);"),
-    ("grad_b_sign", "gF[2 * ib] += sigma * (ry / L - f * ex / L3);",
-     "gF[2 * ib] += sigma * (ry / L + f * ex / L3);"),
-    ("grad_a_index", "gF[2 * ia + 1] += sigma * ((rx - ex) / L + f * ey / L3);",
-     "gF[2 * ia + 1] += sigma * ((rx - ey) / L + f * ey / L3);"),
+    ("grad_theta_swap", "double cth = gpx * by + gpy * (-bx);",
+     "double cth = gpx * bx + gpy * (-by);"),
+    ("grad_t_sign", "double ctx_ = -(c * gpx - s * gpy);", "double ctx_ = -(c * gpx + s * gpy);"),
+    ("grad_b_sign", "double cbx = sigma * (ry / L - f * ex / L3);",
+     "double cbx = sigma * (ry / L + f * ex / L3);"),
+    ("grad_a_index", "double cay = sigma * ((rx - ex) / L + f * ey / L3);",
+     "double cay = sigma * ((rx - ey) / L + f * ey / L3);"),
 ]
 
 
