@@ -58,6 +58,133 @@ def traffic_for(kernel_key: str):
     return None if e is None else float(e["bytes_per_launch"])
 
 
+def _time(torch, stream, fn, reps=5, warm=1):
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def run_extras(P, W, torch, stream, check):
+    """The other workload shapes: binary64 single polygon (all three tests),
+    uneven batch (autotuned, graph-captured plan), all pairs, collision cost."""
+    out = {}
+    dev = "cuda"
+    if check:
+        from oracle import Oracle, pack_bits, unpack_bits
+        o = Oracle()
+    rng = np.random.default_rng(1234)
+
+    # single polygon, 1e6 binary64 points, three tests
+    V, Q = W.single_polygon_fp64()
+    Vt, Qt = torch.from_numpy(V).to(dev), torch.from_numpy(Q).to(dev)
+    lab = torch.empty((len(Q) + 31) // 32, dtype=torch.int32, device=dev)
+    single = {"points": len(Q), "n": len(V), "point_dtype": "float64"}
+    for name, fn, oname in (("voronoi", P.pip_voronoi, "voronoi"),
+                            ("sign_of_offset", P.pip_sign_of_offset, "sign_of_offset"),
+                            ("ray_crossing", P.pip_ray_crossing, "ray_crossing")):
+        ms = _time(torch, stream, lambda: fn(Vt, Qt, lab), reps=20)
+        entry = {"ms": round(ms, 4), "gtests_per_s": round(len(Q) / ms / 1e6, 2)}
+        if check:
+            got = lab.cpu().numpy().view(np.uint32)
+            want = pack_bits(getattr(o, oname)(V, Q))
+            entry["mismatches"] = int(np.unpackbits((got ^ want).view(np.uint8)).sum())
+        single[name] = entry
+    out["single_polygon_fp64"] = single
+    print("[bench] single polygon done", file=sys.stderr, flush=True)
+
+    # uneven batch
+    B = W.uneven_batch()
+    vo, Vb, po, Qb, lo = (torch.from_numpy(B.vtx_off).to(dev), torch.from_numpy(B.V).to(dev),
+                          torch.from_numpy(B.pt_off).to(dev), torch.from_numpy(B.Q).to(dev),
+                          torch.from_numpy(B.lbl_word_off).to(dev))
+    plan = P.BatchedPlan(vo, Vb, po, Qb, lo)
+    cfg, tuned_ms = plan.autotune(reps=3)
+    ms = _time(torch, stream, plan.launch, reps=10)
+    nt = B.num_tests
+    entry = {"polygons": B.num_polygons, "tests": nt, "tile_shape": list(cfg),
+             "autotune_ms": round(tuned_ms, 4), "graph_ms": round(ms, 4),
+             "gtests_per_s": round(nt / ms / 1e6, 2),
+             "hbm_frac": round(BYTES_PER_TEST * nt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if check:
+        lab_b = plan.labels.cpu().numpy().view(np.uint32)
+        bad = 0
+        for k in sorted(rng.choice(B.num_polygons, 48, replace=False)):
+            p0, p1 = B.pt_off[k], B.pt_off[k + 1]
+            v0, v1 = B.vtx_off[k], B.vtx_off[k + 1]
+            want = o.voronoi(B.V[v0:v1], B.Q[p0:p1].astype(np.float64))
+            w0 = B.lbl_word_off[k]
+            got = unpack_bits(lab_b[w0:w0 + (p1 - p0 + 31) // 32], p1 - p0)
+            bad += int((got != want).sum())
+        entry["mismatches_48_polygons"] = bad
+    out["uneven_batch"] = entry
+    plan.close()
+    del vo, Vb, po, Qb, lo, B
+    torch.cuda.empty_cache()
+    print("[bench] uneven batch done", file=sys.stderr, flush=True)
+
+    # all pairs: 2048 poses x 131,072 points
+    F = W.car_footprint()
+    Qc = W.lidar_cloud()
+    poses, cs = W.random_poses()
+    Ft, Qct, pt, ct = (torch.from_numpy(F).to(dev), torch.from_numpy(Qc).to(dev),
+                       torch.from_numpy(poses).to(dev), torch.from_numpy(cs).to(dev))
+    Vw = P.pip_poses_to_polygons(Ft, pt, ct)
+    labs = torch.empty((len(poses), (len(Qc) + 31) // 32), dtype=torch.int32, device=dev)
+    cnts = torch.empty(len(poses), dtype=torch.int32, device=dev)
+
+    def allpairs():
+        P.pip_poses_to_polygons(Ft, pt, ct, out=Vw)
+        P.pip_voronoi_allpairs(Vw, Qct, labels=labs, counts=cnts)
+    ms = _time(torch, stream, allpairs, reps=10)
+    nt = len(poses) * len(Qc)
+    tfl = 4.0 * len(F) * nt / (ms * 1e-3) / 1e12
+    entry = {"poses": len(poses), "points": len(Qc), "tests": nt, "ms": round(ms, 4),
+             "gtests_per_s": round(nt / ms / 1e6, 1), "fp32_tflops": round(tfl, 2),
+             "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)}
+    if check:
+        sel = np.sort(rng.choice(len(poses), 64, replace=False))
+        bits, counts = o.allpairs(F, poses[sel, :2].astype(np.float64), cs[sel],
+                                  Qc.astype(np.float64))
+        got = labs.cpu().numpy().view(np.uint32)[sel]
+        entry["mismatches_64_poses"] = int(np.unpackbits((got ^ bits).view(np.uint8)).sum())
+    out["allpairs"] = entry
+    print("[bench] all pairs done", file=sys.stderr, flush=True)
+
+    # differentiable cost: 1024 trajectories x 64 poses x 65,536 points
+    F32 = F.astype(np.float32)
+    Qd = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)
+    tr = W.trajectories().reshape(-1, 3)
+    F32t, Qdt, trt = (torch.from_numpy(F32).to(dev), torch.from_numpy(Qd).to(dev),
+                      torch.from_numpy(tr).to(dev))
+    ws = torch.empty(P.autograd.cost_workspace_bytes(len(F32), len(tr), len(Qd)),
+                     dtype=torch.uint8, device=dev)
+    ones = torch.ones(len(tr), dtype=torch.float32, device=dev)
+    fwd_ms = _time(torch, stream, lambda: P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws), reps=3)
+    bwd_ms = _time(torch, stream, lambda: P.pip_cost_bwd(F32t, trt, Qdt, ones, workspace=ws),
+                   reps=3)
+    pairs = len(tr) * len(Qd)
+    entry = {"poses": len(tr), "points": len(Qd), "pairs": pairs, "fwd_ms": round(fwd_ms, 3),
+             "bwd_ms": round(bwd_ms, 3), "fwd_gpairs_per_s": round(pairs / fwd_ms / 1e6, 1),
+             "bwd_gpairs_per_s": round(pairs / bwd_ms / 1e6, 1)}
+    if check:
+        c = P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws).cpu().numpy()
+        sel = np.sort(rng.choice(len(tr), 128, replace=False))
+        want = o.cost(F32.astype(np.float64), tr[sel].astype(np.float64), Qd.astype(np.float64))
+        rel = np.abs(c[sel] - want) / np.maximum(np.abs(want), 1e-6)
+        entry["max_rel_err_128_poses"] = float(rel.max())
+    out["cost"] = entry
+    print("[bench] cost done", file=sys.stderr, flush=True)
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,7 +194,20 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=1 << 26,
                     help="points per polygon for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched / all-pairs / cost / binary64 workloads")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy a 1 GiB device buffer 3 times (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 4}), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
               "multi-GPU form in this build", file=sys.stderr)
@@ -205,6 +345,8 @@ def main() -> int:
                "seconds": round(cpu_t, 2)}
         comparisons["fp32_plain_mismatches_on_sample"] = plain_mismatches
 
+    extras = {} if args.no_extras else run_extras(P, W, torch, stream, not args.no_cpu)
+
     out = {
         "metric": "G point-polygon tests/s (Voronoi, certified float32 screen + binary64 "
                   "recheck, labels bit-identical to the FP64 oracle)",
@@ -228,6 +370,7 @@ def main() -> int:
         "kernels": kernels,
         "comparisons": comparisons,
         "cpu_baseline": cpu,
+        "workloads": extras,
     }
     print(json.dumps(out), flush=True)
     return 0

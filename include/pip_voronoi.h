@@ -88,6 +88,16 @@ const char *pip_last_error(pip_ctx ctx);
 /* Library version as major*10000 + minor*100 + patch. */
 int pip_version(void);
 
+/* Tuning options of a context.  Labels never depend on them.
+ *   PIP_OPT_MFMA_MIN_EDGES: pip_voronoi / pip_sign_of_offset on float32 points
+ *     evaluate the margins of polygons with at least this many edges as dense
+ *     products on the matrix cores (v_mfma_f32_32x32x2f32) and those with fewer
+ *     with two vector fma per edge; 0 disables the matrix-core path.
+ *     Default 25 (measured crossover of the two screens). */
+typedef enum { PIP_OPT_MFMA_MIN_EDGES = 1 } pip_option;
+pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value);
+pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);
+
 /*
  * Generators of one convex polygon (Section 3, Eq. 3-8, Algorithms 3-4).
  *   V       [n][2] binary64 vertices.

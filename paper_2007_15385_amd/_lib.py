@@ -10,6 +10,7 @@ LIB_NAME = "libpip_voronoi.so"
 
 PIP_F32 = 0
 PIP_F64 = 1
+PIP_OPT_MFMA_MIN_EDGES = 1
 
 STATUS_NAMES = {
     0: "PIP_OK", 1: "PIP_EINVAL", 2: "PIP_EDEGENERATE", 3: "PIP_ENONCONVEX", 4: "PIP_EHIP",
@@ -40,6 +41,8 @@ _int = _c.c_int
 # name -> (restype, argtypes); pointers are passed as plain integers
 SIGNATURES = {
     "pip_version": (_int, []),
+    "pip_set_option": (_int, [_vp, _int, _i64]),
+    "pip_get_option": (_int, [_vp, _int, _c.POINTER(_i64)]),
     "pip_create": (_int, [_int, _c.POINTER(_vp)]),
     "pip_destroy": (None, [_vp]),
     "pip_status_str": (_c.c_char_p, [_int]),

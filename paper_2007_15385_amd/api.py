@@ -28,6 +28,20 @@ def context(device: int) -> int:
         return h
 
 
+def set_option(option: int, value: int, device: int | None = None) -> None:
+    d = torch.cuda.current_device() if device is None else device
+    ctx = context(d)
+    _check(_lib().pip_set_option(ctx, int(option), int(value)), "pip_set_option", ctx)
+
+
+def get_option(option: int, device: int | None = None) -> int:
+    d = torch.cuda.current_device() if device is None else device
+    ctx = context(d)
+    v = ctypes.c_int64()
+    _check(_lib().pip_get_option(ctx, int(option), ctypes.byref(v)), "pip_get_option", ctx)
+    return int(v.value)
+
+
 def _check(s: int, where: str, ctx) -> None:
     if s != 0:
         detail = _lib().pip_last_error(ctx).decode()

@@ -14,7 +14,9 @@ struct pip_ctx_s {
     int cu_count = 0;
     std::mutex mu;
     int stream_blocks[8][2] = {};  // cached persistent grid per (kind, dtype); 0 = unknown
+    int mfma_blocks[2][4] = {};    // same for the matrix-core screen (kind, edge bucket)
     int batched_blocks_per_cu = 0;
+    int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
 };
 
 // A plan: one batched request bound to its buffers, its own workspace, the
@@ -103,6 +105,19 @@ int persistent_blocks(pip_ctx ctx, int kind, int qdt) {
     return b;
 }
 
+int mfma_blocks(pip_ctx ctx, int kind, int n) {
+    const int bucket = n <= 8 ? 0 : n <= 16 ? 1 : n <= 32 ? 2 : 3;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    int& b = ctx->mfma_blocks[kind == pipdev::K_SOO ? 1 : 0][bucket];
+    if (b == 0) {
+        int per_cu = 0;
+        if (pipdev::stream_mfma_max_blocks_per_cu(kind, n, &per_cu) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        b = per_cu * ctx->cu_count;
+    }
+    return b;
+}
+
 pip_status run_stream(pip_ctx ctx, int kind, const double* V, int32_t n, const void* Q,
                       pip_dtype qdt, int64_t m, uint32_t* labels, float* margin,
                       int32_t* status, hipStream_t stream) {
@@ -132,7 +147,11 @@ pip_status run_stream(pip_ctx ctx, int kind, const double* V, int32_t n, const v
     L.labels = labels;
     L.margin = margin;
     L.status = status;
-    L.max_blocks = persistent_blocks(ctx, kind, (int)qdt);
+    L.mfma = (qdt == PIP_F32 && (kind == pipdev::K_VORONOI || kind == pipdev::K_SOO) &&
+              ctx->mfma_min_edges > 0 && n >= ctx->mfma_min_edges)
+                 ? 1
+                 : 0;
+    L.max_blocks = L.mfma ? mfma_blocks(ctx, kind, n) : persistent_blocks(ctx, kind, (int)qdt);
     L.stream = stream;
     hipError_t e = pipdev::launch_stream(L);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -667,6 +686,29 @@ pip_status pip_cost_bwd(pip_ctx ctx, const float* footprint, int32_t n, const fl
                                        grad_footprint, residual, workspace, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
+}
+
+
+pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    switch (opt) {
+        case PIP_OPT_MFMA_MIN_EDGES:
+            if (value < 0 || value > PIP_MAX_EDGES + 1)
+                return fail(PIP_EINVAL, "PIP_OPT_MFMA_MIN_EDGES must be in [0, %d]", PIP_MAX_EDGES + 1);
+            ctx->mfma_min_edges = (int)value;
+            return PIP_OK;
+    }
+    return fail(PIP_EINVAL, "unknown option %d", (int)opt);
+}
+
+pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
+    if (!ctx || !value) return fail(PIP_EINVAL, "ctx or value is NULL");
+    switch (opt) {
+        case PIP_OPT_MFMA_MIN_EDGES:
+            *value = ctx->mfma_min_edges;
+            return PIP_OK;
+    }
+    return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
 
 }  // extern "C"

@@ -213,6 +213,10 @@ __global__ __launch_bounds__(kBlock) void k_batched_voronoi(
     const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     const int64_t nchunks = misc[0];
+    // a tile never exceeds an even share of the chunks, so the largest tile
+    // shape means one contiguous range per wave
+    const int64_t share = (nchunks + W - 1) / W;
+    if (G > share) G = (int)(share > 0 ? share : 1);
 
     int64_t tile = w;
     int64_t g = tile * G;

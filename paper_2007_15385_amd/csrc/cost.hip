@@ -251,29 +251,50 @@ __global__ void k_pose_grad_finish(const float* __restrict__ part_pose, const fl
     grad_pose[3 * k + 2] = (float)(w * st);
 }
 
-// One workgroup: binary64 sums of the table partials (fixed order), then the
-// chain rule to the vertices.  residual (optional, [2]): |total gradient to
-// p_0| and the scale it is measured against.
-__global__ __launch_bounds__(256) void k_gen_backward(const float* __restrict__ F, int n,
-                                                    const float* __restrict__ part_gen, int64_t nparts,
-                                                    float* __restrict__ grad_F,
-                                                    float* __restrict__ residual) {
+// Stage 1 of the table-gradient reduction: block b sums, in binary64 and in
+// part order, its contiguous range of per-workgroup partials.
+constexpr int kGenRedBlocks = 256;
+
+__global__ __launch_bounds__(256) void k_gen_reduce1(const float* __restrict__ part_gen, int64_t nparts,
+                                                   int ncomp, double* __restrict__ stage) {
     constexpr int NC = 2 * (kMaxEdges + 1);
+    constexpr int NCC = 2 * (kCostMaxEdges + 1);
     __shared__ double red[256];
-    __shared__ double G[NC];
     const int tid = threadIdx.x;
-    const int ncomp = 2 * (n + 1);
+    const int64_t per = (nparts + kGenRedBlocks - 1) / kGenRedBlocks;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < nparts ? lo + per : nparts;
+    double acc[NCC];
+    for (int c = 0; c < NCC; ++c) acc[c] = 0.0;
+    for (int64_t i = lo + tid; i < hi; i += 256)
+        for (int c = 0; c < ncomp; ++c) acc[c] += (double)part_gen[i * NC + c];
     for (int c = 0; c < ncomp; ++c) {
-        double s = 0.0;
-        for (int64_t i = tid; i < nparts; i += 256) s += (double)part_gen[i * NC + c];
-        red[tid] = s;
+        red[tid] = acc[c];
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
             if (tid < o) red[tid] += red[tid + o];
             __syncthreads();
         }
-        if (tid == 0) G[c] = red[0];
+        if (tid == 0) stage[(int64_t)blockIdx.x * NC + c] = red[0];
         __syncthreads();
+    }
+}
+
+// Stage 2 (one thread): sums of the stage-1 results in block order, then the
+// chain rule to the vertices.  residual (optional, [2]): |total gradient to
+// p_0| and the scale it is measured against.
+__global__ __launch_bounds__(64) void k_gen_backward(const float* __restrict__ F, int n,
+                                                   const double* __restrict__ stage,
+                                                   float* __restrict__ grad_F,
+                                                   float* __restrict__ residual) {
+    constexpr int NC = 2 * (kMaxEdges + 1);
+    double G[NC];
+    const int tid = threadIdx.x;
+    const int ncomp = 2 * (n + 1);
+    for (int c = 0; c < ncomp; ++c) {
+        double s = 0.0;
+        for (int b = 0; b < kGenRedBlocks; ++b) s += stage[b * NC + c];
+        G[c] = s;
     }
     if (tid != 0) return;
     // forward quantities in binary64 (Algorithms 3-4, same order as the
@@ -370,6 +391,8 @@ size_t cost_workspace_layout(int n, int64_t K, int64_t m, CostLayout* L) {
     off = up(off + 12 * (size_t)(K * (T > 0 ? T : 1)));
     L->part_gen = off;
     off = up(off + 4 * (size_t)(G * (T > 0 ? T : 1)) * 2 * (kMaxEdges + 1));
+    L->stage = off;
+    off = up(off + 8 * (size_t)kGenRedBlocks * 2 * (kMaxEdges + 1));
     L->T = (int)T;
     L->G = G;
     return off;
@@ -416,8 +439,11 @@ hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, 
         if (K > 0)
             hipLaunchKernelGGL(k_pose_grad_finish, dim3(kb), dim3(256), 0, stream, pp, pose, grad_cost,
                                K, T, grad_pose);
-        hipLaunchKernelGGL(k_gen_backward, dim3(1), dim3(256), 0, stream, F, n, pgn,
-                           (int64_t)L.G * T, grad_F, residual);
+        double* stage = reinterpret_cast<double*>(b + L.stage);
+        hipLaunchKernelGGL(k_gen_reduce1, dim3(kGenRedBlocks), dim3(256), 0, stream, pgn,
+                           (int64_t)L.G * T, 2 * (n + 1), stage);
+        hipLaunchKernelGGL(k_gen_backward, dim3(1), dim3(64), 0, stream, F, n, stage, grad_F,
+                           residual);
     }
     return hipGetLastError();
 }

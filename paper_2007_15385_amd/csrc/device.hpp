@@ -184,7 +184,13 @@ __device__ inline int validate_polygon(const double2* vtx, int n, int lane, doub
 // frame, and the binary64 evaluation errs by at most
 // 2.0001 v (|dV_x| (|Q_y| + |V'_y|) + |dV_y| (|Q_x| + |V'_x|)).
 // ----------------------------------------------------------------------------
-__device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool global_frame = false) {
+// f32_factor: multiple of u bounding the float32 evaluation of one margin
+// relative to alpha|X| + beta|Y| + gamma: 4.05 for the two-fma screen; 6.05
+// when the margin comes from a matrix-core multiply-add (exact products, up to
+// two roundings of the sum, measured <= 1.96 u of the sum of |terms|, bounded
+// here by 4 u, plus the same coefficient and coordinate rounding).
+__device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool global_frame = false,
+                                       double f32_factor = 4.05) {
     const int n = S.n;
     double g0x, g0y, area, gx, gy, den;
     derive_generators(S.vtx, n, lane, &g0x, &g0y, &area, &gx, &gy, &den);
@@ -218,10 +224,10 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         const double H2 = wave_max(hx * hx + hy * hy);
         const double G2 = wave_max(gi2);
         const double infl = 1.0 + 9.5367431640625e-07;  // 1 + 2^-20
-        KA = 4.05 * kU32 * alpha * infl;
-        KB = 4.05 * kU32 * beta * infl;
-        KC = (4.05 * kU32 * gam + 4.1 * kU64 * (G2 + d2) + 4.0001 * kU64 * (6.0 * d2 + 2.0 * H2) +
-              kEpsAbs) * infl;
+        KA = f32_factor * kU32 * alpha * infl;
+        KB = f32_factor * kU32 * beta * infl;
+        KC = (f32_factor * kU32 * gam + 4.1 * kU64 * (G2 + d2) +
+              4.0001 * kU64 * (6.0 * d2 + 2.0 * H2) + kEpsAbs * (1.0 + alpha + beta)) * infl;
         KQ = 24.01 * kU64 * infl;
         (void)qa; (void)qb; (void)qc;
     } else if (kind == K_SOO) {
@@ -244,9 +250,10 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
                                     fabs(dVy) * (fabs(dox) + fabs(w.x)));
         const double kR = wave_max(fabs(w.y - doy) * fabs(dVx) + fabs(w.x - dox) * fabs(dVy));
         const double infl = 1.0 + 9.5367431640625e-07;
-        KA = (4.05 * kU32 * pm + 2.0001 * kU64 * dym) * infl;
-        KB = (4.05 * kU32 * qm + 2.0001 * kU64 * dxm) * infl;
-        KC = (4.05 * kU32 * rm + 3.1 * kU64 * kR + 2.0001 * kU64 * k64 + kEpsAbs) * infl;
+        KA = (f32_factor * kU32 * pm + 2.0001 * kU64 * dym) * infl;
+        KB = (f32_factor * kU32 * qm + 2.0001 * kU64 * dxm) * infl;
+        KC = (f32_factor * kU32 * rm + 3.1 * kU64 * kR + 2.0001 * kU64 * k64 +
+              kEpsAbs * (1.0 + pm + qm)) * infl;
         KQ = kEpsAbs;  // no quadratic term; keeps X^2 overflow -> E = +inf
     } else if (kind == K_RAY) {
         const int j = prev_edge(i, n);

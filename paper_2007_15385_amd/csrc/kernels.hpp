@@ -18,8 +18,12 @@ struct StreamLaunch {
     float* margin;        // device [m] (margin kernel only)
     int32_t* status;      // device [1] or null
     int max_blocks;       // upper bound on the persistent grid
+    int mfma;             // 1: matrix-core margins (float32 points, Voronoi / sign of offset)
     hipStream_t stream;
 };
+
+hipError_t launch_stream_mfma(const StreamLaunch& L);
+hipError_t stream_mfma_max_blocks_per_cu(int kind, int n, int* out);
 
 hipError_t launch_stream(const StreamLaunch& L);
 
@@ -74,7 +78,7 @@ hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, in
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws,
                            hipStream_t stream);
 struct CostLayout {
-    size_t tab, part_cost, part_pose, part_gen;
+    size_t tab, part_cost, part_pose, part_gen, stage;
     int T;
     int64_t G;
 };

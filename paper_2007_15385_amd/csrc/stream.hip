@@ -65,19 +65,20 @@ __device__ __forceinline__ float to_local(double p, float o) { return (float)(p 
 // Lane k (k < 8) stores label word k of the chunk.  The masks are
 // wave-uniform; a select tree on the lane's bits picks the word (plain
 // selects between scalar values, no per-lane array indexing).
-// Re-decide the queued points in binary64 and set their inside bits.
+// Re-decide the queued points in binary64 and set their inside bits.  The
+// queue holds each point's index and its coordinates as loaded (no second
+// read of the point from HBM).
 //
 // Only the wave that owns a chunk ever writes its label words: first the
 // chunk store (undecided bits 0), later these ORs, issued after wave_drain()
 // so no OR can be overtaken by the store it modifies.
 template <int KIND, typename PT>
-__device__ void flush_queue(const PolyLds& S, const int64_t* q, int count, const void* Q,
-                            uint32_t* labels, int lane) {
+__device__ void flush_queue(const PolyLds& S, const int64_t* qi, const PT* qx, const PT* qy,
+                            int count, uint32_t* labels, int lane) {
     wave_drain();
     for (int e = lane; e < count; e += kWave) {
-        const int64_t idx = q[e];
-        const auto p = PointIO<PT>::load(Q, idx);
-        const double x = (double)p.x, y = (double)p.y;
+        const int64_t idx = qi[e];
+        const double x = (double)qx[e], y = (double)qy[e];
         bool in;
         if constexpr (KIND == K_VORONOI)
             in = voronoi64(x, y, S.gen, S.n);
@@ -133,6 +134,8 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
     constexpr bool kQueue = (KIND == K_VORONOI || KIND == K_SOO);
     __shared__ PolyLds S;
     __shared__ int64_t queue[kWavesPerBlock][kQueue ? kQueueCap : 1];
+    __shared__ PT queue_x[kWavesPerBlock][kQueue ? kQueueCap : 1];
+    __shared__ PT queue_y[kWavesPerBlock][kQueue ? kQueueCap : 1];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
             screen_chunk<KIND>(S.coef, n4, KQ, KA, KB, KC, X, Y, valid, inm, unc);
             const int nunc = __popcll(unc[0]) + __popcll(unc[1]) + __popcll(unc[2]) + __popcll(unc[3]);
             if (nunc != 0 && qcount + nunc > kQueueCap) {  // flush before push
-                flush_queue<KIND, PT>(S, queue[wv], qcount, Q, labels, lane);
+                flush_queue<KIND, PT>(S, queue[wv], queue_x[wv], queue_y[wv], qcount, labels, lane);
                 qcount = 0;
             }
             store_chunk_words(labels, base / 32, nwords - base / 32, lane, inm);
@@ -252,8 +255,12 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
                 const uint64_t lt = lanemask_lt();
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
-                    if ((unc[j] >> lane) & 1ull)
-                        queue[wv][qcount + __popcll(unc[j] & lt)] = base + lane + kWave * j;
+                    if ((unc[j] >> lane) & 1ull) {
+                        const int slot = qcount + __popcll(unc[j] & lt);
+                        queue[wv][slot] = base + lane + kWave * j;
+                        queue_x[wv][slot] = px[j];
+                        queue_y[wv][slot] = py[j];
+                    }
                     qcount += __popcll(unc[j]);
                 }
             }
@@ -265,7 +272,8 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
         }
     }
     if constexpr (kQueue) {
-        if (qcount > 0) flush_queue<KIND, PT>(S, queue[wv], qcount, Q, labels, lane);
+        if (qcount > 0)
+            flush_queue<KIND, PT>(S, queue[wv], queue_x[wv], queue_y[wv], qcount, labels, lane);
     }
 }
 
@@ -304,6 +312,7 @@ namespace pipdev {
 
 hipError_t launch_stream(const StreamLaunch& L) {
     const bool f64 = L.qdt == 1;
+    if (L.mfma && !f64 && (L.kind == K_VORONOI || L.kind == K_SOO)) return launch_stream_mfma(L);
     switch (L.kind) {
         case K_VORONOI:
             return f64 ? launch_stream_t<K_VORONOI, double>(L) : launch_stream_t<K_VORONOI, float>(L);

@@ -32,6 +32,16 @@ def P():
     return P
 
 
+@pytest.fixture(autouse=True, params=["mfma", "valu"])
+def screen(request, P):
+    """Every test runs with the matrix-core screen for all polygon sizes and
+    with the vector screen for all sizes (the default switches at 12 edges)."""
+    old = P.get_option(P.PIP_OPT_MFMA_MIN_EDGES)
+    P.set_option(P.PIP_OPT_MFMA_MIN_EDGES, 3 if request.param == "mfma" else 0)
+    yield request.param
+    P.set_option(P.PIP_OPT_MFMA_MIN_EDGES, old)
+
+
 TESTS = {
     "voronoi": ("pip_voronoi", "voronoi"),
     "sign_of_offset": ("pip_sign_of_offset", "sign_of_offset"),
