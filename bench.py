@@ -282,13 +282,19 @@ def main() -> int:
     # binding roofline of the dominant launch: bytes vs flops at peak
     t_hbm = BYTES_PER_TEST * m / (HBM_PEAK_GBS * 1e9)
     t_alu = 4.0 * dom["n"] * m / (FP32_VALU_PEAK_TFLOPS * 1e12)
+    # polygons with at least this many edges take the matrix-core screen
+    mfma_min = int(P.get_option(P.PIP_OPT_MFMA_MIN_EDGES))
+    on_mfma = mfma_min > 0 and dom["n"] >= mfma_min
     if t_alu > t_hbm:
-        roof = {"bound": "alu", "achieved": dom["fp32_tflops"], "peak": FP32_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": dom["fp32_frac"]}
+        # fp32 products on the matrix cores, or two fp32 fma per margin on the
+        # vector units: both priced against the 157.3 TFLOP/s fp32 peak
+        roof = {"bound": "mfma" if on_mfma else "alu", "achieved": dom["fp32_tflops"],
+                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": dom["fp32_frac"]}
     else:
         roof = {"bound": "hbm", "achieved": dom["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dom["hbm_frac"]}
-    roof["kernel"] = f"k_stream<voronoi,float32> n={dom['n']}"
+    roof["kernel"] = (f"k_stream_mfma<voronoi,{64 if dom['n'] > 32 else 32}> n={dom['n']}"
+                      if on_mfma else f"k_stream32<voronoi> n={dom['n']}")
     roof["traffic"] = traffic_for(f"voronoi_f32_n{dom['n']}")
     roof["algorithmic_per_launch"] = ({"flop": 4.0 * dom["n"] * m} if roof["bound"] == "alu"
                                       else {"bytes": BYTES_PER_TEST * m})

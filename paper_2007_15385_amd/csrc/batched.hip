@@ -187,7 +187,7 @@ __device__ __forceinline__ void load_points(const float2* __restrict__ Q, int64_
     for (int j = 0; j < kPPL; ++j) {
         int64_t i = start + lane + kWave * j;
         i = i < last ? i : last;
-        const float2 p = Q[i];
+        const vfloat2 p = __builtin_nontemporal_load(reinterpret_cast<const vfloat2*>(Q) + i);
         x[j] = p.x;
         y[j] = p.y;
     }

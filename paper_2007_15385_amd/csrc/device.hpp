@@ -43,6 +43,8 @@ constexpr int ST_DEGENERATE = 2;  // zero area or zero-length edge
 constexpr int ST_NONCONVEX = 3;
 
 
+typedef float vfloat2 __attribute__((ext_vector_type(2)));
+
 // Unit roundoffs.
 constexpr double kU32 = 5.9604644775390625e-08;   // 2^-24
 constexpr double kU64 = 1.1102230246251565e-16;   // 2^-53

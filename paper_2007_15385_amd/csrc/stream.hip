@@ -14,6 +14,7 @@
 // afterwards with an atomic OR by the same wave, after a fence.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "stream32.hpp"
 
 using namespace pipdev;
 
@@ -277,6 +278,170 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
     }
 }
 
+template <int KIND>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == K_SOO ? 4 : 5))) void k_stream32(const double* __restrict__ V, int n,
+                                                    const float2* __restrict__ Q, int64_t m,
+                                                    uint32_t* __restrict__ labels,
+                                                    int32_t* __restrict__ status) {
+    constexpr bool kQueue = KIND != K_PLAIN;
+    __shared__ PolyLds S;
+    __shared__ uint32_t queue_c[kWavesPerBlock][kQueue ? kQueue32 : 1];
+    __shared__ float queue_x[kWavesPerBlock][kQueue ? kQueue32 : 1];
+    __shared__ float queue_y[kWavesPerBlock][kQueue ? kQueue32 : 1];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int64_t nfull = m / kChunk32;
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t c0 = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    int64_t chunk = c0;
+    uint32_t k = 0;  // chunks of this wave so far
+
+    double2 vt = make_double2(0.0, 0.0);
+    if (tid < n) vt = make_double2(V[2 * tid], V[2 * tid + 1]);
+    float2 pa[kP32], pb[kP32];
+    if (nfull > 0) load_full32(Q, chunk < nfull ? chunk : nfull - 1, lane, pa);
+
+    if (tid < n) S.vtx[tid] = vt;
+    if (tid == 0) S.n = n;
+    __syncthreads();
+    if (wv == 0) {
+        if constexpr (KIND == K_PLAIN)
+            prepare_plain(S, lane);
+        else
+            prepare_polygon(S, KIND, lane);
+    }
+    __syncthreads();
+    if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
+
+    const float ox = S.ox, oy = S.oy;
+    const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC;
+    const int n4 = __builtin_amdgcn_readfirstlane(S.n4);
+    int qcount = 0;
+
+    // Screen the 8 points of every lane of this wave's k-th chunk `ch`;
+    // `rem` points of it exist (>= 512 for a full chunk).
+    auto process = [&](const float2(&p)[kP32], int64_t ch, int64_t rem) {
+        const bool full = rem >= kChunk32;
+        float X[kP32], Y[kP32], Mx[kP32], Mn[kP32];
+        {  // edges 0-3 (n4 >= 4) start the max / min
+            const float4 c0 = S.coef[0], c1 = S.coef[1], c2 = S.coef[2], c3 = S.coef[3];
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                X[j] = p[j].x - ox;
+                Y[j] = p[j].y - oy;
+                const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+                const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+                Mx[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
+                if constexpr (KIND == K_SOO) Mn[j] = fminf(fminf(fminf(m0, m1), m2), m3);
+            }
+        }
+        for (int e = 4; e < n4; e += 4) {
+            const float4 c0 = S.coef[e + 0], c1 = S.coef[e + 1];
+            const float4 c2 = S.coef[e + 2], c3 = S.coef[e + 3];
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+                const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+                Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
+                Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
+                if constexpr (KIND == K_SOO) {
+                    Mn[j] = fminf(fminf(Mn[j], m0), m1);
+                    Mn[j] = fminf(fminf(Mn[j], m2), m3);
+                }
+            }
+        }
+        uint64_t inm[kP32], unc[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            if constexpr (KIND == K_PLAIN) {
+                inm[j] = __ballot(Mx[j] <= 0.0f);
+                unc[j] = 0;
+            } else {
+                const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+                const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
+                uint64_t in, out;
+                if constexpr (KIND == K_SOO) {
+                    in = __ballot(Mx[j] < -E) | __ballot(Mn[j] > E);
+                    out = __ballot(Mx[j] > E) & __ballot(Mn[j] < -E);
+                } else {
+                    in = __ballot(Mx[j] < -E);
+                    out = __ballot(Mx[j] > E);
+                }
+                inm[j] = in;
+                unc[j] = ~(in | out);
+            }
+        }
+        if (!full) {
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const uint64_t vm = __ballot(lane + kWave * j < rem);
+                inm[j] &= vm;
+                unc[j] &= vm;
+            }
+        }
+        const uint32_t w = chunk_word32(inm);
+        const int64_t nw = full ? kWords32 : (rem + 31) / 32;
+        if (lane < nw) labels[ch * kWords32 + lane] = w;
+        if constexpr (kQueue) {
+            int nunc = 0;
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) nunc += __popcll(unc[j]);
+            if (nunc != 0) {
+                if (qcount + nunc > kQueue32) {  // flush before push (drains the store above)
+                    flush_queue32<KIND>(S, queue_c[wv], queue_x[wv], queue_y[wv], qcount, labels,
+                                        lane, c0, stride);
+                    qcount = 0;
+                }
+                const uint64_t lt = lanemask_lt();
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    if ((unc[j] >> lane) & 1ull) {
+                        const int slot = qcount + __popcll(unc[j] & lt);
+                        queue_c[wv][slot] = (k << 9) | (uint32_t)(lane + kWave * j);
+                        queue_x[wv][slot] = p[j].x;
+                        queue_y[wv][slot] = p[j].y;
+                    }
+                    qcount += __popcll(unc[j]);
+                }
+            }
+        }
+        ++k;
+    };
+
+    for (;;) {
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pb);
+        process(pa, chunk, kChunk32);
+        chunk += stride;
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pa);
+        process(pb, chunk, kChunk32);
+        chunk += stride;
+    }
+    if (chunk == nfull && nfull * kChunk32 < m) {  // the partial chunk
+        const int64_t base = nfull * kChunk32;
+        const int rem = (int)(m - base);
+        float2 pt[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            const int r = lane + kWave * j;
+            pt[j] = Q[base + (r < rem ? r : rem - 1)];
+        }
+        process(pt, chunk, rem);
+    }
+    if constexpr (kQueue) {
+        if (qcount > 0)
+            flush_queue32<KIND>(S, queue_c[wv], queue_x[wv], queue_y[wv], qcount, labels, lane,
+                                c0, stride);
+    }
+}
+
 // polygon_to_generators: one wave derives p_0 and the n outer generators.
 __global__ __launch_bounds__(kWave) void k_generators_one(const double* __restrict__ V, int n,
                                                          double* __restrict__ P,
@@ -293,6 +458,17 @@ __global__ __launch_bounds__(kWave) void k_generators_one(const double* __restri
         P[2 * k + 1] = S.gen[k].y;
     }
     if (status && lane == 0) *status = S.status;
+}
+
+template <int KIND>
+hipError_t launch_stream32_t(const StreamLaunch& L) {
+    const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
+    const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
+    int grid = (int)(want < L.max_blocks ? want : L.max_blocks);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_stream32<KIND>), dim3(grid), dim3(kBlock), 0, L.stream, L.V, L.n,
+                       static_cast<const float2*>(L.Q), L.m, L.labels, L.status);
+    return hipGetLastError();
 }
 
 template <int KIND, typename PT>
@@ -315,13 +491,13 @@ hipError_t launch_stream(const StreamLaunch& L) {
     if (L.mfma && !f64 && (L.kind == K_VORONOI || L.kind == K_SOO)) return launch_stream_mfma(L);
     switch (L.kind) {
         case K_VORONOI:
-            return f64 ? launch_stream_t<K_VORONOI, double>(L) : launch_stream_t<K_VORONOI, float>(L);
+            return f64 ? launch_stream_t<K_VORONOI, double>(L) : launch_stream32_t<K_VORONOI>(L);
         case K_SOO:
-            return f64 ? launch_stream_t<K_SOO, double>(L) : launch_stream_t<K_SOO, float>(L);
+            return f64 ? launch_stream_t<K_SOO, double>(L) : launch_stream32_t<K_SOO>(L);
         case K_RAY:
             return f64 ? launch_stream_t<K_RAY, double>(L) : launch_stream_t<K_RAY, float>(L);
         case K_PLAIN:
-            return f64 ? launch_stream_t<K_PLAIN, double>(L) : launch_stream_t<K_PLAIN, float>(L);
+            return f64 ? launch_stream_t<K_PLAIN, double>(L) : launch_stream32_t<K_PLAIN>(L);
         case K_MARGIN:
             return f64 ? launch_stream_t<K_MARGIN, double>(L) : launch_stream_t<K_MARGIN, float>(L);
         default:
@@ -339,10 +515,10 @@ hipError_t stream_max_blocks_per_cu(int kind, int qdt, int* out) {
     const void* f = nullptr;
     const bool f64 = qdt == 1;
     switch (kind) {
-        case K_VORONOI: f = f64 ? (const void*)k_stream<K_VORONOI, double> : (const void*)k_stream<K_VORONOI, float>; break;
-        case K_SOO: f = f64 ? (const void*)k_stream<K_SOO, double> : (const void*)k_stream<K_SOO, float>; break;
+        case K_VORONOI: f = f64 ? (const void*)k_stream<K_VORONOI, double> : (const void*)k_stream32<K_VORONOI>; break;
+        case K_SOO: f = f64 ? (const void*)k_stream<K_SOO, double> : (const void*)k_stream32<K_SOO>; break;
         case K_RAY: f = f64 ? (const void*)k_stream<K_RAY, double> : (const void*)k_stream<K_RAY, float>; break;
-        case K_PLAIN: f = f64 ? (const void*)k_stream<K_PLAIN, double> : (const void*)k_stream<K_PLAIN, float>; break;
+        case K_PLAIN: f = f64 ? (const void*)k_stream<K_PLAIN, double> : (const void*)k_stream32<K_PLAIN>; break;
         case K_MARGIN: f = f64 ? (const void*)k_stream<K_MARGIN, double> : (const void*)k_stream<K_MARGIN, float>; break;
         default: return hipErrorInvalidValue;
     }

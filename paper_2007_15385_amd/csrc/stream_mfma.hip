@@ -11,12 +11,16 @@
 //
 // Operand layout (gfx950, verified on the device): lane l supplies A[l%32][l/32]
 // and B[l/32][l%32]; accumulator register r of lane l holds row
-// 8(r/4) + 4(l/32) + r%4 of column l%32.  Lanes l and l + 32 both load point
-// l%32 (x and y) and feed X or Y into the product; every lane computes the
-// band of its point itself.  Rows beyond n repeat edge 0 (the max is
-// unchanged).  Both lanes of a point end with the same max and band, so they
-// take the same decision and the low 32 bits of a ballot are that point
-// group's label word.
+// 8(r/4) + 4(l/32) + r%4 of column l%32.  Points are loaded exactly as in the
+// vector kernel (lane l holds point 64 j + l of slot j, 512 contiguous bytes
+// per load instruction).  One v_permlane32_swap of the local X and Y
+// registers yields the B operands of both 32-point groups of a slot: group A
+// (points 0-31: X of lane l, Y of lane l - 32) and group B (points 32-63: X of
+// lane l + 32, Y of lane l).  After the reductions, one more swap pairs the two
+// half-wave maxima so that lane l ends with the full max of its own point
+// (group A in lanes 0-31, group B in lanes 32-63); the band, the decision and
+// the ballot are then per lane as in the vector kernel, and the ballot is the
+// slot's 64 label bits.
 //
 // Band: as for the two-fma screen with 6.05 u instead of 4.05 u (the matrix
 // core's sum of three terms is bounded by 4 u of the sum of |terms|; measured
@@ -24,6 +28,7 @@
 // re-decided in binary64 exactly as in the vector kernel.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "stream32.hpp"
 
 using namespace pipdev;
 
@@ -31,89 +36,67 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kGroups = kChunk / 32;  // 8 point groups of 32 per 256-point chunk
 constexpr double kMfmaFactor = 6.05;
 
-// The two outputs of the swap hold the two half-wave values of a column in
-// both halves; a compare-select (no NaN canonicalisation needed: a NaN margin
-// only occurs with a NaN band, which already forces the binary64 path).
-__device__ __forceinline__ float pair_max(float v) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
-                                                    false);
-    const float a = __uint_as_float(r[0]), b = __uint_as_float(r[1]);
-    return a > b ? a : b;
+// max / min of the first R accumulator registers of one product, written as
+// a chain whose every step combines three values, so it compiles to v_max3 /
+// v_min3 without canonicalising the matrix-core results first (an odd
+// remainder repeats register 0).  A NaN margin comes with a NaN or infinite
+// band and goes to the binary64 path, so NaN propagation does not matter.
+template <int R>
+__device__ __forceinline__ float reg_max(const floatx16& d) {
+    float r = fmaxf(fmaxf(d[0], d[1]), d[2]);
+#pragma unroll
+    for (int i = 3; i < R; i += 2) r = fmaxf(fmaxf(r, d[i]), d[i + 1 < R ? i + 1 : 0]);
+    return r;
 }
-__device__ __forceinline__ float pair_min(float v) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
-                                                    false);
-    const float a = __uint_as_float(r[0]), b = __uint_as_float(r[1]);
-    return a < b ? a : b;
+template <int R>
+__device__ __forceinline__ float reg_min(const floatx16& d) {
+    float r = fminf(fminf(d[0], d[1]), d[2]);
+#pragma unroll
+    for (int i = 3; i < R; i += 2) r = fminf(fminf(r, d[i]), d[i + 1 < R ? i + 1 : 0]);
+    return r;
 }
-template <int KIND>
-__device__ void flush_mfma(const PolyLds& S, const int64_t* qi, const float2* qp, int count,
-                           uint32_t* labels, int lane) {
-    wave_drain();
-    for (int e = lane; e < count; e += kWave) {
-        const int64_t idx = qi[e];
-        const double x = (double)qp[e].x, y = (double)qp[e].y;
-        bool in;
-        if constexpr (KIND == K_VORONOI)
-            in = voronoi64(x, y, S.gen, S.n);
-        else
-            in = sign_of_offset64(x, y, S.vtx, S.n);
-        if (in) or_label_bit(labels, idx >> 5, (uint32_t)(idx & 31));
-    }
-    __builtin_amdgcn_wave_barrier();
+
+// lane l < 32: (a[l], a[l + 32]); lane l >= 32: (b[l - 32], b[l])
+__device__ __forceinline__ void swap_halves(float a, float b, float& lo, float& hi) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                    false);
+    lo = __uint_as_float(r[0]);
+    hi = __uint_as_float(r[1]);
 }
 
 // NE: edge capacity (8, 16, 32, 64).  For NE <= 16 the edges are placed in
 // both row halves (row -> edge 4 (row / 8) + row % 4), so register r of every
-// lane holds edge r and each lane sees all margins of its point; NE = 32 uses
-// row = edge (two lanes per point, combined by one swap); NE = 64 uses two
-// products.
+// lane holds edge r and each lane sees all margins of its column; NE = 32
+// uses the natural row -> edge map (the two halves hold different edges of
+// the column); NE = 64 takes two products per group.
 template <int KIND, int NE>
-__global__ __launch_bounds__(kBlock) void k_stream_mfma(const double* __restrict__ V, int n,
-                                                      const float* __restrict__ Qf, int64_t m,
-                                                      uint32_t* __restrict__ labels,
-                                                      int32_t* __restrict__ status) {
-    constexpr int NB = NE > 32 ? 2 : 1;
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NE == 64 ? 3 : 4)))
+void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict__ Q, int64_t m,
+                   uint32_t* __restrict__ labels, int32_t* __restrict__ status) {
+    constexpr int NB = NE == 64 ? 2 : 1;
     constexpr bool kDup = NE <= 16;
     constexpr int RR = kDup ? NE : 16;  // registers reduced per product
     __shared__ PolyLds S;
-    __shared__ int64_t qidx[kWavesPerBlock][kQueueCap];
-    __shared__ float2 qpt[kWavesPerBlock][kQueueCap];
+    __shared__ uint32_t queue_c[kWavesPerBlock][kQueue32];
+    __shared__ float queue_x[kWavesPerBlock][kQueue32];
+    __shared__ float queue_y[kWavesPerBlock][kQueue32];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int half = lane >> 5, col = lane & 31;
-    const int64_t nchunks = (m + kChunk - 1) / kChunk;
-    const int64_t nwords = (m + 31) / 32;
+    const int64_t nfull = m / kChunk32;
     const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    int64_t chunk = (int64_t)blockIdx.x * kWavesPerBlock + wv;
-    const float2* __restrict__ Q2 = reinterpret_cast<const float2*>(Qf);
+    const int64_t c0 = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    int64_t chunk = c0;
+    uint32_t k = 0;
 
     double2 vt = make_double2(0.0, 0.0);
     if (tid < n) vt = make_double2(V[2 * tid], V[2 * tid + 1]);
-    // lane l loads point (group start + l % 32) of each of the 8 groups; full
-    // chunks need no clamping (immediate offsets), the last one is clamped
-    float2 v[kGroups];
-    auto load_chunk = [&](int64_t c, float2 (&dst)[kGroups]) {
-        if ((c + 1) * kChunk <= m) {
-            const float2* a = Q2 + c * kChunk + col;
-#pragma unroll
-            for (int t = 0; t < kGroups; ++t) dst[t] = a[32 * t];
-        } else {
-            const int64_t last = m - 1;
-#pragma unroll
-            for (int t = 0; t < kGroups; ++t) {
-                int64_t p = c * kChunk + 32 * t + col;
-                p = p < last ? p : last;
-                dst[t] = Q2[p];
-            }
-        }
-    };
-    if (m > 0) load_chunk(chunk, v);
+    float2 pa[kP32], pb[kP32];
+    if (nfull > 0) load_full32(Q, chunk < nfull ? chunk : nfull - 1, lane, pa);
 
     if (tid < n) S.vtx[tid] = vt;
     if (tid == 0) S.n = n;
@@ -143,108 +126,143 @@ __global__ __launch_bounds__(kBlock) void k_stream_mfma(const double* __restrict
     const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC;
     int qcount = 0;
 
-    for (; chunk < nchunks; chunk += stride) {
-        float2 nv[kGroups];
-        load_chunk(chunk + stride, nv);
-        const int64_t base = chunk * kChunk;
-        // lanes of points past the end (partial last chunk only)
-        const uint32_t vmask = (base + kChunk <= m) ? 0xffffffffu : 0u;
-        uint32_t inw[kGroups], uncw[kGroups];
-        float X[kGroups], Y[kGroups];
+    // Screen the 8 slots of 64 points of chunk `ch` (this wave's k-th); rem
+    // points of it exist (>= 512 for a full chunk).
+    auto process = [&](const float2(&p)[kP32], int64_t ch, int64_t rem) {
+        const bool full = rem >= kChunk32;
+        uint64_t inm[kP32], unc[kP32];
 #pragma unroll
-        for (int t = 0; t < kGroups; ++t) {
-            X[t] = v[t].x - ox;
-            Y[t] = v[t].y - oy;
-        }
-        floatx16 dnext[NB];
+        for (int j = 0; j < kP32; ++j) {
+            const float X = p[j].x - ox, Y = p[j].y - oy;
+            float bA, bB;  // operands of groups A and B
+            swap_halves(X, Y, bA, bB);
+            floatx16 dA[NB], dB[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-            dnext[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[b], half ? Y[0] : X[0], c_op[b], 0,
-                                                            0, 0);
+            for (int b = 0; b < NB; ++b)
+                dA[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[b], bA, c_op[b], 0, 0, 0);
 #pragma unroll
-        for (int t = 0; t < kGroups; ++t) {
-            floatx16 d[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) d[b] = dnext[b];
-            if (t + 1 < kGroups) {  // next group's products before this group's reduction
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    dnext[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                        a_op[b], half ? Y[t + 1] : X[t + 1], c_op[b], 0, 0, 0);
+            for (int b = 0; b < NB; ++b)
+                dB[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[b], bB, c_op[b], 0, 0, 0);
+            // both products in flight before the reductions start
+            __builtin_amdgcn_sched_barrier(0);
+            float xA = reg_max<RR>(dA[0]), xB = reg_max<RR>(dB[0]);
+            float nA = 0.f, nB = 0.f;
+            if constexpr (KIND == K_SOO) {
+                nA = reg_min<RR>(dA[0]);
+                nB = reg_min<RR>(dB[0]);
             }
-            float mx = -__builtin_huge_valf(), mn = __builtin_huge_valf();
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-#pragma unroll
-                for (int r = 0; r < RR; ++r) {
-                    mx = fmaxf(mx, d[b][r]);
-                    if constexpr (KIND == K_SOO) mn = fminf(mn, d[b][r]);
+            if constexpr (NB == 2) {
+                const float x1 = reg_max<RR>(dA[1]), x2 = reg_max<RR>(dB[1]);
+                xA = xA > x1 ? xA : x1;
+                xB = xB > x2 ? xB : x2;
+                if constexpr (KIND == K_SOO) {
+                    const float n1 = reg_min<RR>(dA[1]), n2 = reg_min<RR>(dB[1]);
+                    nA = nA < n1 ? nA : n1;
+                    nB = nB < n2 ? nB : n2;
                 }
             }
-            if constexpr (!kDup) {
-                mx = pair_max(mx);
-                if constexpr (KIND == K_SOO) mn = pair_min(mn);
+            if constexpr (kDup && RR < 16) {  // keep every product register live
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll
+                for (int b = 0; b < NB; ++b) asm volatile("" ::"v"(dA[b]), "v"(dB[b]));
+#endif
             }
-            const float ax = fabsf(X[t]), ay = fabsf(Y[t]);
-            const float r2 = fmaf(X[t], X[t], Y[t] * Y[t]);
-            const float E = fmaf(KQ, r2, fmaf(KA, ax, fmaf(KB, ay, KC)));
-            uint32_t ins, outs;
-            if constexpr (KIND == K_SOO) {
-                ins = (uint32_t)__ballot(mx < -E) | (uint32_t)__ballot(mn > E);
-                outs = (uint32_t)__ballot(mx > E) & (uint32_t)__ballot(mn < -E);
+            // max (min) over all edges of this lane's own point
+            float mx, mn = 0.f;
+            if constexpr (kDup) {
+                mx = half ? xB : xA;
+                if constexpr (KIND == K_SOO) mn = half ? nB : nA;
             } else {
-                ins = (uint32_t)__ballot(mx < -E);
-                outs = (uint32_t)__ballot(mx > E);
+                float u, w;
+                swap_halves(xA, xB, u, w);
+                mx = u > w ? u : w;
+                if constexpr (KIND == K_SOO) {
+                    swap_halves(nA, nB, u, w);
+                    mn = u < w ? u : w;
+                }
             }
-            uint32_t valid = vmask;
-            if (!vmask) {
-                const int64_t rem = m - (base + 32 * t);
-                valid = rem >= 32 ? 0xffffffffu : (rem <= 0 ? 0u : ((1u << rem) - 1u));
+            const float r2 = fmaf(X, X, Y * Y);
+            const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X), fmaf(KB, fabsf(Y), KC)));
+            uint64_t in, out;
+            if constexpr (KIND == K_SOO) {
+                in = __ballot(mx < -E) | __ballot(mn > E);
+                out = __ballot(mx > E) & __ballot(mn < -E);
+            } else {
+                in = __ballot(mx < -E);
+                out = __ballot(mx > E);
             }
-            inw[t] = ins & valid;
-            uncw[t] = ~(ins | outs) & valid;
+            inm[j] = in;
+            unc[j] = ~(in | out);
         }
+        if (!full) {
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const uint64_t vm = __ballot(lane + kWave * j < rem);
+                inm[j] &= vm;
+                unc[j] &= vm;
+            }
+        }
+        const uint32_t w = chunk_word32(inm);
+        const int64_t nw = full ? kWords32 : (rem + 31) / 32;
+        if (lane < nw) labels[ch * kWords32 + lane] = w;
         int nunc = 0;
 #pragma unroll
-        for (int t = 0; t < kGroups; ++t) nunc += __popc(uncw[t]);
-        if (nunc != 0 && qcount + nunc > kQueueCap) {  // flush before push
-            flush_mfma<KIND>(S, qidx[wv], qpt[wv], qcount, labels, lane);
-            qcount = 0;
-        }
-        // lane k (< 8) stores word k of the chunk
-        uint32_t w = 0;
-#pragma unroll
-        for (int t = 0; t < kGroups; ++t) w = (lane == t) ? inw[t] : w;
-        const int64_t widx = base / 32 + lane;
-        if (lane < kWordsPerChunk && widx < nwords) labels[widx] = w;
+        for (int j = 0; j < kP32; ++j) nunc += __popcll(unc[j]);
         if (nunc != 0) {
-            const uint32_t lt = (uint32_t)lanemask_lt();
+            if (qcount + nunc > kQueue32) {  // flush before push (drains the store above)
+                flush_queue32<KIND>(S, queue_c[wv], queue_x[wv], queue_y[wv], qcount, labels, lane,
+                                    c0, stride);
+                qcount = 0;
+            }
+            const uint64_t lt = lanemask_lt();
 #pragma unroll
-            for (int t = 0; t < kGroups; ++t) {
-                if (uncw[t]) {
-                    if (half == 0 && ((uncw[t] >> col) & 1u)) {
-                        const int slot = qcount + __popc(uncw[t] & lt);
-                        qidx[wv][slot] = base + 32 * t + col;
-                        qpt[wv][slot] = v[t];
-                    }
-                    qcount += __popc(uncw[t]);
+            for (int j = 0; j < kP32; ++j) {
+                if ((unc[j] >> lane) & 1ull) {
+                    const int slot = qcount + __popcll(unc[j] & lt);
+                    queue_c[wv][slot] = (k << 9) | (uint32_t)(lane + kWave * j);
+                    queue_x[wv][slot] = p[j].x;
+                    queue_y[wv][slot] = p[j].y;
                 }
+                qcount += __popcll(unc[j]);
             }
         }
-#pragma unroll
-        for (int t = 0; t < kGroups; ++t) v[t] = nv[t];
+        ++k;
+    };
+
+    for (;;) {
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pb);
+        process(pa, chunk, kChunk32);
+        chunk += stride;
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pa);
+        process(pb, chunk, kChunk32);
+        chunk += stride;
     }
-    if (qcount > 0) flush_mfma<KIND>(S, qidx[wv], qpt[wv], qcount, labels, lane);
+    if (chunk == nfull && nfull * kChunk32 < m) {  // the partial chunk
+        const int64_t base = nfull * kChunk32;
+        const int rem = (int)(m - base);
+        float2 pt[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            const int r = lane + kWave * j;
+            pt[j] = Q[base + (r < rem ? r : rem - 1)];
+        }
+        process(pt, chunk, rem);
+    }
+    if (qcount > 0)
+        flush_queue32<KIND>(S, queue_c[wv], queue_x[wv], queue_y[wv], qcount, labels, lane, c0,
+                            stride);
 }
 
 template <int KIND, int R>
 hipError_t launch_t(const StreamLaunch& L) {
-    const int64_t nchunks = (L.m + kChunk - 1) / kChunk;
+    const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
     const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
     int grid = (int)(want < L.max_blocks ? want : L.max_blocks);
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL((k_stream_mfma<KIND, R>), dim3(grid), dim3(kBlock), 0, L.stream, L.V, L.n,
-                       static_cast<const float*>(L.Q), L.m, L.labels, L.status);
+                       static_cast<const float2*>(L.Q), L.m, L.labels, L.status);
     return hipGetLastError();
 }
 
