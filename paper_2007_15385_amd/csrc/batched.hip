@@ -19,6 +19,7 @@
 // static polygons (Section 7: generators stored beside the vertices).
 #include "device.hpp"
 #include "kernels.hpp"
+#include "stream32.hpp"
 
 using namespace pipdev;
 
@@ -27,8 +28,12 @@ namespace {
 struct alignas(16) ChunkDesc {
     int64_t start;  // global index of the chunk's first point
     int32_t k;      // polygon
-    int32_t count;  // points in the chunk (1..256)
+    int32_t count;  // points in the chunk (1..512)
 };
+
+// buffer resource word 3 of the gfx9 family (raw 32-bit data, no swizzle)
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kLoadNT = 2;  // cache-policy bit of a non-temporal (streaming) load
 
 __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
     __shared__ PolyLds S[kWavesPerBlock];
@@ -47,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
     else if (nn > kMaxEdges) bad = 6;  // PIP_EUNSUPPORTED
     // an unusable polygon with a valid point range gets all-zero labels
     const int64_t s = range_bad ? 0 : p1 - p0;
-    const int64_t chunks = (s + kChunk - 1) / kChunk;
+    const int64_t chunks = (s + kChunk32 - 1) / kChunk32;
     PolyHdr* H = D.hdr + k;
     if (bad != ST_OK) {
         if (lane == 0) {
@@ -139,8 +144,8 @@ __global__ __launch_bounds__(kBlock) void k_fill_chunks(BatchedDev D) {
     const int64_t s = (c1 - c0) > 0 ? D.pt_off[k + 1] - p0 : 0;
     ChunkDesc* desc = reinterpret_cast<ChunkDesc*>(D.desc);
     for (int64_t c = c0 + lane; c < c1 && c < D.max_chunks; c += kWave) {
-        const int64_t first = (c - c0) * kChunk;
-        const int64_t cnt = s - first < kChunk ? s - first : kChunk;
+        const int64_t first = (c - c0) * kChunk32;
+        const int64_t cnt = s - first < kChunk32 ? s - first : kChunk32;
         ChunkDesc d;
         d.start = p0 + first;
         d.k = (int32_t)k;
@@ -161,35 +166,43 @@ struct MainArgs {
     const int64_t* __restrict__ lbl_word_off;
 };
 
+// Queue of undecided points of a wave: polygon, index within the polygon's
+// point set, and the coordinates as loaded (no second read from HBM).
+struct QueueB {
+    int32_t k[kQueueCap];
+    uint32_t local[kQueueCap];
+    float x[kQueueCap], y[kQueueCap];
+};
+
 // Re-decide queued (point, polygon) pairs in binary64 against the stored
 // generators and set their inside bits.
-__device__ void flush_batched(const int64_t* __restrict__ vtx_off, const int64_t* __restrict__ pt_off,
+__device__ void flush_batched(const int64_t* __restrict__ vtx_off,
                               const int64_t* __restrict__ lbl_word_off,
                               const PolyHdr* __restrict__ hdr, const double2* __restrict__ gen,
-                              const float2* __restrict__ Q, uint32_t* __restrict__ labels,
-                              const int64_t* qi, const int32_t* qk, int count, int lane) {
+                              uint32_t* __restrict__ labels, const QueueB& q, int count, int lane) {
     wave_drain();
     for (int e = lane; e < count; e += kWave) {
-        const int64_t idx = qi[e];
-        const int32_t k = qk[e];
-        const float2 p = Q[idx];
+        const int32_t k = q.k[e];
+        const uint32_t local = q.local[e];
         const int n = hdr[k].n;
-        const bool in = voronoi64((double)p.x, (double)p.y, gen + gen_base(vtx_off, k), n);
-        const int64_t local = idx - pt_off[k];
-        if (in) or_label_bit(labels, lbl_word_off[k] + (local >> 5), (uint32_t)(local & 31));
+        const bool in = voronoi64((double)q.x[e], (double)q.y[e], gen + gen_base(vtx_off, k), n);
+        if (in) or_label_bit(labels, lbl_word_off[k] + (local >> 5), local & 31u);
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void load_points(const float2* __restrict__ Q, int64_t start, int64_t last,
-                                            int lane, float (&x)[kPPL], float (&y)[kPPL]) {
+// Points of one chunk: a buffer resource spanning exactly its count points,
+// so lanes past the end read 0 without any per-lane address arithmetic.
+__device__ __forceinline__ void load_chunk_b(const float2* __restrict__ Q, const ChunkDesc& d,
+                                             int lane, float2 (&p)[kP32]) {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<float2*>(Q + d.start), (short)0, d.count * (int)sizeof(float2), kRsrcWord3);
 #pragma unroll
-    for (int j = 0; j < kPPL; ++j) {
-        int64_t i = start + lane + kWave * j;
-        i = i < last ? i : last;
-        const vfloat2 p = __builtin_nontemporal_load(reinterpret_cast<const vfloat2*>(Q) + i);
-        x[j] = p.x;
-        y[j] = p.y;
+    for (int j = 0; j < kP32; ++j) {
+        const vfloat2 v = __builtin_bit_cast(
+            vfloat2, __builtin_amdgcn_raw_buffer_load_b64(r, (lane + kWave * j) * (int)sizeof(float2),
+                                                          0, kLoadNT));
+        p[j] = make_float2(v.x, v.y);
     }
 }
 
@@ -199,15 +212,14 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
-__global__ __launch_bounds__(kBlock) void k_batched_voronoi(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_batched_voronoi(
     const ChunkDesc* __restrict__ desc, const PolyHdr* __restrict__ hdr,
     const float4* __restrict__ coef, const double2* __restrict__ gen,
     const int64_t* __restrict__ vtx_off, const int64_t* __restrict__ pt_off,
     const int64_t* __restrict__ lbl_word_off, const float2* __restrict__ Q,
     uint32_t* __restrict__ labels, const int64_t* __restrict__ misc, int G) {
-    __shared__ float4 coefs[kWavesPerBlock][kMaxEdges];
-    __shared__ int64_t qidx[kWavesPerBlock][kQueueCap];
-    __shared__ int32_t qpoly[kWavesPerBlock][kQueueCap];
+    __shared__ float4 coefs[kWavesPerBlock][2][kMaxEdges];  // current / next polygon
+    __shared__ QueueB queue[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int64_t W = (int64_t)gridDim.x * kWavesPerBlock;
@@ -222,90 +234,190 @@ __global__ __launch_bounds__(kBlock) void k_batched_voronoi(
     int64_t g = tile * G;
     if (g >= nchunks) return;  // whole wave, nothing to do
     ChunkDesc d = desc[g];
-    float px[kPPL], py[kPPL];
-    load_points(Q, d.start, d.start + d.count - 1, lane, px, py);
+    float2 pa[kP32], pb[kP32];
+    load_chunk_b(Q, d, lane, pa);
+    int cb = 0;  // LDS table of the current polygon; rows past n4 are never read
+    coefs[wv][1][lane] = coef[coef_base(vtx_off, d.k) + lane];
 
     int cur_k = -1;
     float ox = 0.f, oy = 0.f, KQ = 0.f, KA = 0.f, KB = 0.f, KC = 0.f;
     int n4 = 0;
     int64_t ptk = 0, wk = 0;
     int qcount = 0;
-    for (;;) {
-        // the chunk after g in this wave's sequence
-        int64_t g2 = g + 1;
-        if (g2 % G == 0 || g2 >= nchunks) {
-            tile += W;
-            g2 = tile * G;
-        }
-        const bool more = g2 < nchunks;
-        const ChunkDesc d2 = desc[uniform64(more ? g2 : g)];
+    QueueB& q = queue[wv];
 
-        const int k = __builtin_amdgcn_readfirstlane(d.k);
-        if (k != cur_k) {  // stage the polygon's table (before the prefetch)
-            const PolyHdr& H = hdr[k];
-            ox = H.ox;
-            oy = H.oy;
-            KQ = H.KQ;
-            KA = H.KA;
-            KB = H.KB;
-            KC = H.KC;
-            n4 = __builtin_amdgcn_readfirstlane(H.n4);
-            ptk = pt_off[k];
-            wk = lbl_word_off[k];
-            if (lane < n4) coefs[wv][lane] = coef[coef_base(vtx_off, k) + lane];
-            __builtin_amdgcn_wave_barrier();
-            cur_k = k;
-        }
-        float nx[kPPL], ny[kPPL];
-        load_points(Q, d2.start, d2.start + d2.count - 1, lane, nx, ny);
-
-        bool valid[kPPL];
-        float X[kPPL], Y[kPPL];
-#pragma unroll
-        for (int j = 0; j < kPPL; ++j) {
-            valid[j] = lane + kWave * j < d.count;
-            X[j] = px[j] - ox;
-            Y[j] = py[j] - oy;
-        }
-        uint64_t inm[kPPL], unc[kPPL];
+    // Screen chunk `cd` (points p) against polygon cur_k.
+    auto process = [&](const float2(&p)[kP32], const ChunkDesc& cd) {
+        const int cnt = __builtin_amdgcn_readfirstlane(cd.count);
+        const bool full = cnt >= kChunk32;
+        uint64_t inm[kP32], unc[kP32];
         if (n4 > 0) {
-            screen_chunk<K_VORONOI>(coefs[wv], n4, KQ, KA, KB, KC, X, Y, valid, inm, unc);
+            float X[kP32], Y[kP32], Mx[kP32];
+            {  // edges 0-3 (n4 >= 4) start the max
+                const float4* cf = coefs[wv][cb];
+                const float4 c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    X[j] = p[j].x - ox;
+                    Y[j] = p[j].y - oy;
+                    const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                    const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                    const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+                    const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+                    Mx[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
+                }
+            }
+            for (int e = 4; e < n4; e += 4) {
+                const float4* cf = coefs[wv][cb];
+                const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                    const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                    const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+                    const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+                const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
+                const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
+                inm[j] = in;
+                unc[j] = ~(in | out);
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < kPPL; ++j) inm[j] = unc[j] = 0;  // invalid polygon: labels 0
+            for (int j = 0; j < kP32; ++j) inm[j] = unc[j] = 0;  // invalid polygon: labels 0
         }
-        const int nunc = __popcll(unc[0]) + __popcll(unc[1]) + __popcll(unc[2]) + __popcll(unc[3]);
-        if (nunc != 0 && qcount + nunc > kQueueCap) {
-            flush_batched(vtx_off, pt_off, lbl_word_off, hdr, gen, Q, labels, qidx[wv], qpoly[wv],
-                          qcount, lane);
-            qcount = 0;
-        }
-        const int64_t local = d.start - ptk;  // multiple of 256
-        store_chunk_words(labels, wk + local / 32, ((int64_t)d.count + 31) / 32, lane, inm);
-        if (nunc != 0) {
-            const uint64_t lt = lanemask_lt();
+        if (!full) {
 #pragma unroll
-            for (int j = 0; j < kPPL; ++j) {
+            for (int j = 0; j < kP32; ++j) {
+                const uint64_t vm = __ballot(lane + kWave * j < cnt);
+                inm[j] &= vm;
+                unc[j] &= vm;
+            }
+        }
+        const int64_t local = cd.start - ptk;  // multiple of 512
+        const uint32_t wd = chunk_word32(inm);
+        const int nw = full ? kWords32 : (cnt + 31) / 32;
+        if (lane < nw) labels[wk + local / 32 + lane] = wd;
+        // queue in two halves of at most 256 points (flush before push)
+        const uint64_t lt = lanemask_lt();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            int c = 0;
+#pragma unroll
+            for (int j = 4 * h; j < 4 * h + 4; ++j) c += __popcll(unc[j]);
+            if (c == 0) continue;
+            if (qcount + c > kQueueCap) {  // drains this chunk's store too
+                flush_batched(vtx_off, lbl_word_off, hdr, gen, labels, q, qcount, lane);
+                qcount = 0;
+            }
+#pragma unroll
+            for (int j = 4 * h; j < 4 * h + 4; ++j) {
                 if ((unc[j] >> lane) & 1ull) {
                     const int slot = qcount + __popcll(unc[j] & lt);
-                    qidx[wv][slot] = d.start + lane + kWave * j;
-                    qpoly[wv][slot] = k;
+                    q.k[slot] = cur_k;
+                    q.local[slot] = (uint32_t)(local + lane + kWave * j);
+                    q.x[slot] = p[j].x;
+                    q.y[slot] = p[j].y;
                 }
                 qcount += __popcll(unc[j]);
             }
         }
-        if (!more) break;
-        g = g2;
-        d = d2;
-#pragma unroll
-        for (int j = 0; j < kPPL; ++j) {
-            px[j] = nx[j];
-            py[j] = ny[j];
+    };
+    // Polygon table of chunk `cd` (its coefficient rows are in the other LDS
+    // table, written when its first chunk was prefetched).
+    auto stage = [&](const ChunkDesc& cd) {
+        const int k = __builtin_amdgcn_readfirstlane(cd.k);
+        if (k == cur_k) return;
+        const PolyHdr& H = hdr[k];
+        ox = H.ox;
+        oy = H.oy;
+        KQ = H.KQ;
+        KA = H.KA;
+        KB = H.KB;
+        KC = H.KC;
+        n4 = __builtin_amdgcn_readfirstlane(H.n4);
+        ptk = pt_off[k];
+        wk = lbl_word_off[k];
+        cb ^= 1;
+        __builtin_amdgcn_wave_barrier();
+        cur_k = k;
+    };
+    // the chunk after g in this wave's sequence
+    auto next_chunk = [&](int64_t gg) -> int64_t {
+        int64_t g2 = gg + 1;
+        if (g2 % G == 0 || g2 >= nchunks) {
+            tile += W;
+            g2 = tile * G;
         }
+        return g2;
+    };
+
+    // Descriptors travel by vector load, issued after the point prefetch, so
+    // that waiting for the next one coincides with waiting for the points
+    // that are screened next (no scalar-load latency before each prefetch).
+    auto load_desc_v = [&](int64_t gg) {
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<ChunkDesc*>(desc + gg), (short)0, (int)sizeof(ChunkDesc), kRsrcWord3);
+        return __builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0);
+    };
+    auto unpack = [&](const decltype(load_desc_v(0))& v) {
+        ChunkDesc c;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)v[0]);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)v[1]);
+        c.start = (int64_t)(((uint64_t)hi << 32) | lo);
+        c.k = __builtin_amdgcn_readfirstlane((int)v[2]);
+        c.count = __builtin_amdgcn_readfirstlane((int)v[3]);
+        return c;
+    };
+    const int64_t g0 = g;  // a valid index for the descriptor loads past the end
+    int64_t g2 = next_chunk(g);
+    bool more = g2 < nchunks;
+    auto d2v = load_desc_v(more ? g2 : g0);
+
+    for (;;) {
+        stage(d);
+        ChunkDesc d2 = unpack(d2v);
+        {  // a new polygon's rows go to the spare LDS table (load issued first)
+            const bool newpoly = d2.k != d.k;
+            float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (newpoly) cn = coef[coef_base(vtx_off, d2.k) + lane];
+            load_chunk_b(Q, d2, lane, pb);
+            if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
+        }
+        int64_t g3 = more ? next_chunk(g2) : g2;
+        bool more3 = more && g3 < nchunks;
+        d2v = load_desc_v(more3 ? g3 : (more ? g2 : g0));
+        process(pa, d);
+        if (!more) break;
+        d = d2;
+        g2 = g3;
+        more = more3;
+
+        stage(d);
+        d2 = unpack(d2v);
+        {
+            const bool newpoly = d2.k != d.k;
+            float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (newpoly) cn = coef[coef_base(vtx_off, d2.k) + lane];
+            load_chunk_b(Q, d2, lane, pa);
+            if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
+        }
+        g3 = more ? next_chunk(g2) : g2;
+        more3 = more && g3 < nchunks;
+        d2v = load_desc_v(more3 ? g3 : (more ? g2 : g0));
+        process(pb, d);
+        if (!more) break;
+        d = d2;
+        g2 = g3;
+        more = more3;
     }
-    if (qcount > 0)
-        flush_batched(vtx_off, pt_off, lbl_word_off, hdr, gen, Q, labels, qidx[wv], qpoly[wv], qcount,
-                      lane);
+    if (qcount > 0) flush_batched(vtx_off, lbl_word_off, hdr, gen, labels, q, qcount, lane);
 }
 
 }  // namespace
@@ -318,15 +430,15 @@ size_t batched_workspace_layout(int64_t P, int64_t total_vertices, int64_t total
     size_t off = 0;
     L->hdr = off;
     off = up(off + sizeof(PolyHdr) * (size_t)P);
-    L->coef = off;
-    off = up(off + 16 * (size_t)(total_vertices + 3 * P));
+    L->coef = off;  // + 64 rows: a whole wave may read 64 rows from any polygon's base
+    off = up(off + 16 * (size_t)(total_vertices + 3 * P + kWave));
     L->gen = off;
     off = up(off + 16 * (size_t)(total_vertices + P));
     L->chunk_cnt = off;
     off = up(off + 8 * (size_t)P);
     L->chunk_off = off;
     off = up(off + 8 * (size_t)(P + 1));
-    L->max_chunks = total_points / kChunk + P + 1;
+    L->max_chunks = total_points / kChunk32 + P + 1;
     L->desc = off;
     off = up(off + sizeof(ChunkDesc) * (size_t)L->max_chunks);
     L->misc = off;
