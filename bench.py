@@ -58,6 +58,55 @@ def traffic_for(kernel_key: str):
     return None if e is None else float(e["bytes_per_launch"])
 
 
+def _counter_rows(d: str, counter: str):
+    """(dispatch id, kernel name, value summed over the counter's rows) per
+    dispatch of a rocprofv3 --pmc csv run, in dispatch order."""
+    import csv
+    import glob
+    f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+    agg = {}
+    with open(f) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            did = int(r["Dispatch_Id"])
+            agg.setdefault(did, [r["Kernel_Name"], 0.0])[1] += float(r["Counter_Value"])
+    return [(k, agg[k][0], agg[k][1]) for k in sorted(agg)]
+
+
+def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir) -> int:
+    """profiles/hbm_traffic.json from counter runs of `--traffic-run` (one
+    Voronoi launch per n, in NS order) and `--copy-probe` (1 GiB copies),
+    each counter scaled by what it reads for the copy of known size."""
+    copy_bytes = float(1 << 30)
+    cf = max(v for _, name, v in _counter_rows(copy_fetch_dir, "FETCH_SIZE"))
+    cw = max(v for _, name, v in _counter_rows(copy_write_dir, "WRITE_SIZE"))
+    sf, sw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+
+    def voronoi(rows):
+        return [v for _, name, v in rows if "k_stream32<0>" in name or "k_stream_mfma<0," in name]
+    fe = voronoi(_counter_rows(fetch_dir, "FETCH_SIZE"))
+    wr = voronoi(_counter_rows(write_dir, "WRITE_SIZE"))
+    if len(fe) != len(NS) or len(wr) != len(NS):
+        print(f"expected {len(NS)} Voronoi dispatches, got {len(fe)} / {len(wr)}", file=sys.stderr)
+        return 1
+    m = 1 << 28
+    out = {"source_hash": kernel_source_hash(),
+           "scale": {"FETCH_SIZE": round(sf, 4), "WRITE_SIZE": round(sw, 4)},
+           "algorithmic_bytes_per_launch": BYTES_PER_TEST * m, "kernels": {}}
+    print("| n | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | / algorithmic |")
+    print("|---|---|---|---|---|")
+    for n, f, w in zip(NS, fe, wr):
+        b = f * 1024.0 * sf + w * 1024.0 * sw
+        out["kernels"][f"voronoi_f32_n{n}"] = {"fetch_kib": f, "write_kib": w,
+                                               "bytes_per_launch": round(b)}
+        print(f"| {n} | {f:.0f} | {w:.0f} | {b:.4g} | {b / (BYTES_PER_TEST * m):.3f} |")
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"scale FETCH_SIZE {sf:.4f}, WRITE_SIZE {sw:.4f}; wrote profiles/hbm_traffic.json")
+    return 0
+
+
 def _time(torch, stream, fn, reps=5, warm=1):
     for _ in range(warm):
         fn()
@@ -198,7 +247,15 @@ def main() -> int:
                     help="skip the batched / all-pairs / cost / binary64 workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (counter calibration)")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="only one Voronoi launch per polygon size (for counter runs)")
+    ap.add_argument("--ingest-counters", nargs=4,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="turn rocprofv3 FETCH_SIZE / WRITE_SIZE runs of --traffic-run and "
+                         "--copy-probe into profiles/hbm_traffic.json")
     args = ap.parse_args()
+    if args.ingest_counters:
+        return ingest_counters(*args.ingest_counters)
     if args.copy_probe:
         import torch
         x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
@@ -237,6 +294,12 @@ def main() -> int:
         del Q
         print(f"[bench] inputs n={n} ready ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    if args.traffic_run:
+        for n in NS:
+            P.pip_voronoi(polys[n], pts[n], labels[n])
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_run": list(NS)}), flush=True)
+        return 0
 
     def step():
         for n in NS:
@@ -296,7 +359,8 @@ def main() -> int:
     roof["kernel"] = (f"k_stream_mfma<voronoi,{64 if dom['n'] > 32 else 32}> n={dom['n']}"
                       if on_mfma else f"k_stream32<voronoi> n={dom['n']}")
     roof["traffic"] = traffic_for(f"voronoi_f32_n{dom['n']}")
-    roof["algorithmic_per_launch"] = ({"flop": 4.0 * dom["n"] * m} if roof["bound"] == "alu"
+    roof["algorithmic_per_launch"] = ({"flop": 4.0 * dom["n"] * m}
+                                      if roof["bound"] in ("alu", "mfma")
                                       else {"bytes": BYTES_PER_TEST * m})
 
     # ---- comparison kernels (outside the timed step) -----------------------

@@ -6,22 +6,27 @@
 //   k_prepare_uniform    one wave per polygon: generators (Section 3,
 //                        Algorithms 3-4, binary64), float32 coefficients of the
 //                        global-frame margin and its band constants.
-//   k_allpairs           workgroup = 1024-point tile x group of polygons whose
-//                        coefficients are staged in LDS; per (polygon, point):
-//                        n margins (2 FMA each), max3, compare with the band
-//                        bounded once per (polygon, wave) from the wave's
-//                        coordinate maxima; undecided pairs are re-decided in
-//                        binary64 on the spot (Algorithm 5); inside bits are
-//                        packed by ballot and counted per polygon.
+//   k_allpairs           workgroup = 2048-point tile (8 points per lane) x
+//                        group of up to 16 polygons whose coefficients are
+//                        staged in LDS; per (polygon, point): n margins (2 FMA
+//                        each), max3, compare with the band bounded once per
+//                        (polygon, wave) from the wave's coordinate maxima;
+//                        undecided pairs are re-decided in binary64 on the spot
+//                        (Algorithm 5); inside bits go straight from the
+//                        compares into ballots, 16 label words per (polygon,
+//                        wave) are assembled in one VGPR and stored at once,
+//                        and the inside bits are counted per polygon.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "stream32.hpp"
 
 using namespace pipdev;
 
 namespace {
 
-constexpr int kTilePoints = kBlock * kPPL;  // 1024 points per workgroup tile
-constexpr int kLdsCoefBytes = 32768;        // coefficient staging per workgroup
+constexpr int kTilePoints = kWavesPerBlock * kChunk32;  // 2048 points per workgroup tile
+constexpr int kLdsCoefBytes = 16384;                    // coefficient staging per workgroup
+constexpr int kMaxGroup = 16;                           // polygons per workgroup
 
 __global__ void k_poses_to_polygons(const double* __restrict__ F, int n,
                                     const float* __restrict__ pose, const double* __restrict__ cs,
@@ -43,7 +48,8 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
                                                           PolyHdr* __restrict__ hdr,
                                                           float4* __restrict__ coef,
                                                           double2* __restrict__ gen,
-                                                          int32_t* __restrict__ status) {
+                                                          int32_t* __restrict__ status,
+                                                          int32_t* __restrict__ counts) {
     __shared__ PolyLds S[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
@@ -71,12 +77,8 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
         H.status = L.status;
         hdr[k] = H;
         if (status) status[k] = L.status;
+        if (counts) counts[k] = 0;  // k_allpairs accumulates into it
     }
-}
-
-__global__ void k_zero_counts(int32_t* counts, int64_t P) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P) counts[i] = 0;
 }
 
 __device__ __forceinline__ float wave_max_f(float v) {
@@ -85,7 +87,7 @@ __device__ __forceinline__ float wave_max_f(float v) {
     return v;
 }
 
-// grid: x = point tiles of 1024, y = polygon groups of PG.
+// grid: x = point tiles of 2048, y = polygon groups of PG (<= 16).
 __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__ hdr,
                                                    const float4* __restrict__ coef,
                                                    const double2* __restrict__ gen, int64_t P,
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
                                                    int64_t m, uint32_t* __restrict__ labels,
                                                    int32_t* __restrict__ counts) {
     extern __shared__ float4 coef_s[];  // [PG][n4]
-    __shared__ int32_t cnt_s[256];
+    __shared__ int32_t cnt_s[kMaxGroup];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -105,75 +107,94 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
     for (int i = tid; i < pg * n4; i += kBlock) coef_s[i] = coef[k0 * n4 + i];
     for (int i = tid; i < pg; i += kBlock) cnt_s[i] = 0;
 
-    // this wave's 256 points
-    const int64_t base = (int64_t)blockIdx.x * kTilePoints + (int64_t)wv * kChunk;
-    float x[kPPL], y[kPPL];
-    bool valid[kPPL], fin[kPPL];
+    // this wave's 512 points (lane l holds points l + 64 j); past the end and
+    // non-finite points are outside for every polygon
+    const int64_t base = (int64_t)blockIdx.x * kTilePoints + (int64_t)wv * kChunk32;
+    const int64_t rem64 = m - base;
+    const int rem = (int)(rem64 < kChunk32 ? (rem64 > 0 ? rem64 : 0) : kChunk32);
+    float x[kP32], y[kP32];
+    uint64_t live[kP32];
     float xm = 0.f, ym = 0.f;
+    if (rem > 0) {
 #pragma unroll
-    for (int j = 0; j < kPPL; ++j) {
-        const int64_t i = base + lane + kWave * j;
-        valid[j] = i < m;
-        const float2 p = Q[valid[j] ? i : 0];
-        x[j] = p.x;
-        y[j] = p.y;
-        fin[j] = isfinite(p.x) && isfinite(p.y);
-        valid[j] = valid[j] && fin[j];  // a non-finite point is outside for every polygon
-        if (valid[j]) {
-            xm = fmaxf(xm, fabsf(p.x));
-            ym = fmaxf(ym, fabsf(p.y));
+        for (int j = 0; j < kP32; ++j) {
+            const int r = lane + kWave * j;
+            const float2 p = Q[base + (r < rem ? r : rem - 1)];
+            x[j] = p.x;
+            y[j] = p.y;
+            const bool ok = r < rem && isfinite(p.x) && isfinite(p.y);
+            live[j] = __ballot(ok);
+            if (ok) {
+                xm = fmaxf(xm, fabsf(p.x));
+                ym = fmaxf(ym, fabsf(p.y));
+            }
         }
+        xm = wave_max_f(xm);
+        ym = wave_max_f(ym);
     }
-    xm = wave_max_f(xm);
-    ym = wave_max_f(ym);
     const float r2m = fmaf(xm, xm, ym * ym);
     __syncthreads();
 
-    const bool wave_live = base < m;
-    for (int p = 0; p < pg && wave_live; ++p) {
-        const int64_t k = k0 + p;
-        const PolyHdr& H = hdr[k];
-        // band for every point of this wave (monotone in |x|, |y|)
-        const float E = fmaf(H.KQ, r2m, fmaf(H.KA, xm, fmaf(H.KB, ym, H.KC)));
-        const float4* cf = coef_s + p * n4;
-        float M[kPPL];
+    if (rem > 0) {
+        const int nw = (rem + 31) / 32;
+        for (int p = 0; p < pg; ++p) {
+            const int64_t k = k0 + p;
+            const PolyHdr& H = hdr[k];
+            // band for every point of this wave (monotone in |x|, |y|)
+            const float E = fmaf(H.KQ, r2m, fmaf(H.KA, xm, fmaf(H.KB, ym, H.KC)));
+            const float4* cf = coef_s + p * n4;
+            float M[kP32];
+            {  // edges 0-3 start the max (n4 >= 4)
+                const float4 c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
 #pragma unroll
-        for (int j = 0; j < kPPL; ++j) M[j] = -__builtin_huge_valf();
-        for (int e = 0; e < n4; e += 4) {
-            const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
-#pragma unroll
-            for (int j = 0; j < kPPL; ++j) {
-                const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
-                const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
-                const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
-                const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
-                M[j] = fmaxf(fmaxf(M[j], m0), m1);
-                M[j] = fmaxf(fmaxf(M[j], m2), m3);
+                for (int j = 0; j < kP32; ++j) {
+                    const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
+                    const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
+                    const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
+                    const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
+                    M[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
+                }
             }
-        }
-        uint64_t inm[kPPL];
-        uint64_t any_unc = 0;
-        bool in[kPPL], unc[kPPL];
+            for (int e = 4; e < n4; e += 4) {
+                const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
 #pragma unroll
-        for (int j = 0; j < kPPL; ++j) {
-            in[j] = valid[j] && M[j] < -E;
-            unc[j] = valid[j] && !(M[j] < -E) && !(M[j] > E);
-            any_unc |= __ballot(unc[j]);
-        }
-        if (any_unc) {  // rare: re-decide in binary64 (Algorithm 5)
-            const double2* G = gen + k * (n + 1);
+                for (int j = 0; j < kP32; ++j) {
+                    const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
+                    const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
+                    const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
+                    const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
+                    M[j] = fmaxf(fmaxf(M[j], m0), m1);
+                    M[j] = fmaxf(fmaxf(M[j], m2), m3);
+                }
+            }
+            uint64_t inm[kP32];
+            uint64_t any_unc = 0;
 #pragma unroll
-            for (int j = 0; j < kPPL; ++j)
-                if (unc[j]) in[j] = voronoi64((double)x[j], (double)y[j], G, n);
-        }
-        int c = 0;
+            for (int j = 0; j < kP32; ++j) {
+                const uint64_t in = __ballot(M[j] < -E) & live[j];
+                const uint64_t out = __ballot(M[j] > E);
+                inm[j] = in;
+                any_unc |= ~(in | out) & live[j];
+            }
+            if (any_unc) {  // rare: re-decide in binary64 (Algorithm 5)
+                const double2* G = gen + k * (n + 1);
 #pragma unroll
-        for (int j = 0; j < kPPL; ++j) {
-            inm[j] = __ballot(in[j]);
-            c += __popcll(inm[j]);
+                for (int j = 0; j < kP32; ++j) {
+                    const uint64_t unc = ~(inm[j] | __ballot(M[j] > E)) & live[j];
+                    if (unc) {
+                        bool r = false;
+                        if ((unc >> lane) & 1ull) r = voronoi64((double)x[j], (double)y[j], G, n);
+                        inm[j] = (inm[j] & ~unc) | (__ballot(r) & unc);
+                    }
+                }
+            }
+            int c = 0;
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) c += __popcll(inm[j]);
+            const uint32_t w = chunk_word32(inm);
+            if (lane < nw) labels[k * words + base / 32 + lane] = w;
+            if (lane == 0 && c) atomicAdd(&cnt_s[p], c);
         }
-        store_chunk_words(labels + k * words, base / 32, words - base / 32, lane, inm);
-        if (lane == 0 && c) atomicAdd(&cnt_s[p], c);
     }
     __syncthreads();
     if (counts)
@@ -201,7 +222,7 @@ size_t allpairs_workspace_layout(int64_t P, int n, AllpairsLayout* L) {
 int allpairs_group(int n) {
     const int n4 = (n + 3) & ~3;
     int pg = kLdsCoefBytes / (16 * n4);
-    return pg > 256 ? 256 : pg;
+    return pg > kMaxGroup ? kMaxGroup : pg;
 }
 
 hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, const double* cs,
@@ -224,14 +245,9 @@ hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, in
     double2* gen = reinterpret_cast<double2*>(b + L.gen);
     const unsigned pblocks = (unsigned)((P + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(k_prepare_uniform, dim3(pblocks), dim3(kBlock), 0, stream, P, n, V, hdr,
-                       coef, gen, status);
+                       coef, gen, status, counts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (counts) {
-        hipLaunchKernelGGL(k_zero_counts, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream,
-                           counts, P);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     if (m == 0) return hipSuccess;
     const int pg = allpairs_group(n);
     const int n4 = (n + 3) & ~3;
