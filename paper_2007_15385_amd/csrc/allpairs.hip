@@ -96,6 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
                                                    int32_t* __restrict__ counts) {
     extern __shared__ float4 coef_s[];  // [PG][n4]
     __shared__ int32_t cnt_s[kMaxGroup];
+    __shared__ float band_s[kWavesPerBlock][kMaxGroup];  // per (wave, polygon)
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -133,15 +134,19 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
         ym = wave_max_f(ym);
     }
     const float r2m = fmaf(xm, xm, ym * ym);
+    // band for every point of this wave and polygon p of the group (monotone
+    // in |x|, |y|), one lane per polygon
+    if (lane < pg) {
+        const PolyHdr& H = hdr[k0 + lane];
+        band_s[wv][lane] = fmaf(H.KQ, r2m, fmaf(H.KA, xm, fmaf(H.KB, ym, H.KC)));
+    }
     __syncthreads();
 
     if (rem > 0) {
         const int nw = (rem + 31) / 32;
         for (int p = 0; p < pg; ++p) {
             const int64_t k = k0 + p;
-            const PolyHdr& H = hdr[k];
-            // band for every point of this wave (monotone in |x|, |y|)
-            const float E = fmaf(H.KQ, r2m, fmaf(H.KA, xm, fmaf(H.KB, ym, H.KC)));
+            const float E = band_s[wv][p];
             const float4* cf = coef_s + p * n4;
             float M[kP32];
             {  // edges 0-3 start the max (n4 >= 4)
