@@ -35,10 +35,16 @@ BYTES_PER_TEST = 8.125         # float2 point in + 1 label bit out
 NS = (3, 4, 8, 16, 32, 64)
 
 
+# sources of the single-polygon streaming path (the kernels whose HBM traffic
+# profiles/hbm_traffic.json records)
+STREAM_SOURCES = ("api.hip", "device.hpp", "kernels.hpp", "stream.hip", "stream32.hpp",
+                  "stream_mfma.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2007_15385_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
+    for fn in STREAM_SOURCES:
         with open(os.path.join(csrc, fn), "rb") as f:
             h.update(fn.encode() + f.read())
     return h.hexdigest()[:16]
