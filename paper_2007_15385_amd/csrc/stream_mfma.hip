@@ -72,7 +72,7 @@ __device__ __forceinline__ void swap_halves(float a, float b, float& lo, float& 
 // uses the natural row -> edge map (the two halves hold different edges of
 // the column); NE = 64 takes two products per group.
 template <int KIND, int NE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(NE == 64 ? 3 : 4)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict__ Q, int64_t m,
                    uint32_t* __restrict__ labels, int32_t* __restrict__ status) {
     constexpr int NB = NE == 64 ? 2 : 1;
@@ -136,36 +136,41 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
             const float X = p[j].x - ox, Y = p[j].y - oy;
             float bA, bB;  // operands of groups A and B
             swap_halves(X, Y, bA, bB);
-            floatx16 dA[NB], dB[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                dA[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[b], bA, c_op[b], 0, 0, 0);
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                dB[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[b], bB, c_op[b], 0, 0, 0);
-            // both products in flight before the reductions start
-            __builtin_amdgcn_sched_barrier(0);
-            float xA = reg_max<RR>(dA[0]), xB = reg_max<RR>(dB[0]);
-            float nA = 0.f, nB = 0.f;
-            if constexpr (KIND == K_SOO) {
-                nA = reg_min<RR>(dA[0]);
-                nB = reg_min<RR>(dB[0]);
-            }
-            if constexpr (NB == 2) {
-                const float x1 = reg_max<RR>(dA[1]), x2 = reg_max<RR>(dB[1]);
-                xA = xA > x1 ? xA : x1;
-                xB = xB > x2 ? xB : x2;
+            float xA, xB, nA = 0.f, nB = 0.f;
+            if constexpr (NB == 1) {
+                floatx16 dA = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[0], bA, c_op[0], 0, 0, 0);
+                floatx16 dB = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[0], bB, c_op[0], 0, 0, 0);
+                // both products in flight before the reductions start
+                __builtin_amdgcn_sched_barrier(0);
+                xA = reg_max<RR>(dA);
+                xB = reg_max<RR>(dB);
                 if constexpr (KIND == K_SOO) {
-                    const float n1 = reg_min<RR>(dA[1]), n2 = reg_min<RR>(dB[1]);
-                    nA = nA < n1 ? nA : n1;
-                    nB = nB < n2 ? nB : n2;
+                    nA = reg_min<RR>(dA);
+                    nB = reg_min<RR>(dB);
                 }
-            }
-            if constexpr (kDup && RR < 16) {  // keep every product register live
+                if constexpr (kDup && RR < 16) {  // keep every product register live
 #if defined(__HIP_DEVICE_COMPILE__)
-#pragma unroll
-                for (int b = 0; b < NB; ++b) asm volatile("" ::"v"(dA[b]), "v"(dB[b]));
+                    asm volatile("" ::"v"(dA), "v"(dB));
 #endif
+                }
+            } else {
+                // 64 edges: the two products of group A, then those of group B
+                // (two accumulator sets live at a time, for occupancy)
+                auto group = [&](float bop, float& mx, float& mn) {
+                    const floatx16 d0 =
+                        __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[0], bop, c_op[0], 0, 0, 0);
+                    const floatx16 d1 =
+                        __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[1], bop, c_op[1], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const float x0 = reg_max<RR>(d0), x1 = reg_max<RR>(d1);
+                    mx = x0 > x1 ? x0 : x1;
+                    if constexpr (KIND == K_SOO) {
+                        const float n0 = reg_min<RR>(d0), n1 = reg_min<RR>(d1);
+                        mn = n0 < n1 ? n0 : n1;
+                    }
+                };
+                group(bA, xA, nA);
+                group(bB, xB, nB);
             }
             // max (min) over all edges of this lane's own point
             float mx, mn = 0.f;
