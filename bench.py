@@ -211,6 +211,19 @@ def run_extras(P, W, torch, stream, check):
         got = labs.cpu().numpy().view(np.uint32)[sel]
         entry["mismatches_64_poses"] = int(np.unpackbits((got ^ bits).view(np.uint8)).sum())
     out["allpairs"] = entry
+    # culled variant (a layer in front of the test, reported apart from the
+    # dense row): (pose, wave) pairs whose bounding disk misses the wave's
+    # points are skipped; labels and counts must equal the dense ones
+    dense_l, dense_c = labs.clone(), cnts.clone()
+    P.set_option(P.PIP_OPT_ALLPAIRS_CULL, 1)
+    try:
+        ms_c = _time(torch, stream, allpairs, reps=10)
+        same = bool(torch.equal(labs, dense_l) and torch.equal(cnts, dense_c))
+    finally:
+        P.set_option(P.PIP_OPT_ALLPAIRS_CULL, 0)
+    out["allpairs_culled"] = {"ms": round(ms_c, 4), "speedup_vs_dense": round(ms / ms_c, 2),
+                              "dense_equivalent_gtests_per_s": round(nt / ms_c / 1e6, 1),
+                              "labels_and_counts_equal_dense": same}
     print("[bench] all pairs done", file=sys.stderr, flush=True)
 
     # differentiable cost: 1024 trajectories x 64 poses x 65,536 points

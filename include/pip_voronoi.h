@@ -93,8 +93,15 @@ int pip_version(void);
  *     evaluate the margins of polygons with at least this many edges as dense
  *     products on the matrix cores (v_mfma_f32_32x32x2f32) and those with fewer
  *     with two vector fma per edge; 0 disables the matrix-core path.
- *     Default 25 (measured crossover of the two screens). */
-typedef enum { PIP_OPT_MFMA_MIN_EDGES = 1 } pip_option;
+ *     Default 25 (measured crossover of the two screens).
+ *   PIP_OPT_ALLPAIRS_CULL: 1 lets pip_voronoi_allpairs skip every (polygon,
+ *     64 x 8-point wave) pair whose bounding disk (centre p_0, radius the
+ *     largest vertex distance, rounded up) misses the box or the range of
+ *     distances from the origin of the wave's points; their labels are 0 and
+ *     add 0 to the counts, exactly the dense result (a convex polygon lies in
+ *     that disk).  Default 0 (dense: every pair evaluated).  Not from the
+ *     paper: a culling layer in front of its test. */
+typedef enum { PIP_OPT_MFMA_MIN_EDGES = 1, PIP_OPT_ALLPAIRS_CULL = 2 } pip_option;
 pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value);
 pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);
 

@@ -61,6 +61,16 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
     __builtin_amdgcn_wave_barrier();
     prepare_polygon(L, K_VORONOI, lane, /*global_frame=*/true);
     __builtin_amdgcn_wave_barrier();
+    // disk containing the polygon: centre p_0 rounded to float32, radius =
+    // largest vertex distance from p_0 plus the centre's rounding, inflated
+    // and rounded up (every point of a convex polygon is within it)
+    const double g0x = L.gen[0].x, g0y = L.gen[0].y;
+    double dv = 0.0;
+    if (lane < n) {
+        const double dx = L.vtx[lane].x - g0x, dy = L.vtx[lane].y - g0y;
+        dv = sqrt(dx * dx + dy * dy);
+    }
+    const double rmax = wave_max(dv);
     const int n4 = L.n4;
     if (lane < n4) coef[k * n4 + lane] = L.coef[lane];
     for (int i = lane; i <= n; i += kWave) gen[k * (n + 1) + i] = L.gen[i];
@@ -75,6 +85,11 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
         H.n = n;
         H.n4 = n4;
         H.status = L.status;
+        H.cx = (float)g0x;
+        H.cy = (float)g0y;
+        const double ce = fabs((double)H.cx - g0x) + fabs((double)H.cy - g0y);
+        H.rad = round_up_f32((rmax + ce) * (1.0 + 1.0 / 65536.0) + 1e-30);  // NaN -> +inf
+        for (int i = 0; i < 4; ++i) H.pad[i] = 0;
         hdr[k] = H;
         if (status) status[k] = L.status;
         if (counts) counts[k] = 0;  // k_allpairs accumulates into it
@@ -87,7 +102,9 @@ __device__ __forceinline__ float wave_max_f(float v) {
     return v;
 }
 
-// grid: x = point tiles of 2048, y = polygon groups of PG (<= 16).
+// grid: x = point tiles of 2048, y = polygon groups of PG (<= 16).  CULL:
+// skip (polygon, wave) pairs whose bounding disk misses the wave's points.
+template <bool CULL>
 __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__ hdr,
                                                    const float4* __restrict__ coef,
                                                    const double2* __restrict__ gen, int64_t P,
@@ -97,6 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
     extern __shared__ float4 coef_s[];  // [PG][n4]
     __shared__ int32_t cnt_s[kMaxGroup];
     __shared__ float band_s[kWavesPerBlock][kMaxGroup];  // per (wave, polygon)
+    __shared__ int skip_s[kWavesPerBlock][kMaxGroup];    // polygon's disk misses the wave's points
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -116,6 +134,10 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
     float x[kP32], y[kP32];
     uint64_t live[kP32];
     float xm = 0.f, ym = 0.f;
+    // box and distance range (from the origin) of the wave's live points
+    float xlo = __builtin_huge_valf(), xhi = -__builtin_huge_valf();
+    float ylo = __builtin_huge_valf(), yhi = -__builtin_huge_valf();
+    float r2lo = __builtin_huge_valf(), r2hi = 0.f;
     if (rem > 0) {
 #pragma unroll
         for (int j = 0; j < kP32; ++j) {
@@ -128,10 +150,27 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
             if (ok) {
                 xm = fmaxf(xm, fabsf(p.x));
                 ym = fmaxf(ym, fabsf(p.y));
+                if constexpr (CULL) {
+                    xlo = fminf(xlo, p.x);
+                    xhi = fmaxf(xhi, p.x);
+                    ylo = fminf(ylo, p.y);
+                    yhi = fmaxf(yhi, p.y);
+                    const float r2 = fmaf(p.x, p.x, p.y * p.y);
+                    r2lo = fminf(r2lo, r2);
+                    r2hi = fmaxf(r2hi, r2);
+                }
             }
         }
         xm = wave_max_f(xm);
         ym = wave_max_f(ym);
+        if constexpr (CULL) {
+            xlo = -wave_max_f(-xlo);
+            xhi = wave_max_f(xhi);
+            ylo = -wave_max_f(-ylo);
+            yhi = wave_max_f(yhi);
+            r2lo = -wave_max_f(-r2lo);
+            r2hi = wave_max_f(r2hi);
+        }
     }
     const float r2m = fmaf(xm, xm, ym * ym);
     // band for every point of this wave and polygon p of the group (monotone
@@ -139,6 +178,26 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
     if (lane < pg) {
         const PolyHdr& H = hdr[k0 + lane];
         band_s[wv][lane] = fmaf(H.KQ, r2m, fmaf(H.KA, xm, fmaf(H.KB, ym, H.KC)));
+        // Culling (optional): the polygon lies in the disk (c, R); when that
+        // disk misses the wave's box or its distance range from the origin,
+        // no point of the wave is inside.  The disk is widened by
+        // 2^-16 (|c_x| + |c_y| + R) and the squared distances carry a relative
+        // slack of 2^-16, far above the float32 rounding of every quantity
+        // compared; such a point is then also far outside in binary64.
+        bool skip = false;
+        if constexpr (CULL) {
+            const float R = H.rad, cx = H.cx, cy = H.cy;
+            const float sl = 1.0f / 65536.0f;
+            const float Rs = R + (fabsf(cx) + fabsf(cy) + R) * sl;
+            skip = cx + Rs < xlo || cx - Rs > xhi || cy + Rs < ylo || cy - Rs > yhi;
+            const float dc = sqrtf(fmaf(cx, cx, cy * cy));
+            const float hi = dc + Rs, lo = dc - Rs;
+            skip = skip || hi * hi * (1.0f + sl) < r2lo * (1.0f - sl);
+            skip = skip || (lo > 0.f && lo * lo * (1.0f - sl) > r2hi * (1.0f + sl));
+            // no culling for a polygon without a finite disk (bad input)
+            skip = skip && R < __builtin_huge_valf() && cx == cx && cy == cy;
+        }
+        if constexpr (CULL) skip_s[wv][lane] = skip ? 1 : 0;
     }
     __syncthreads();
 
@@ -146,6 +205,10 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
         const int nw = (rem + 31) / 32;
         for (int p = 0; p < pg; ++p) {
             const int64_t k = k0 + p;
+            if (CULL && __builtin_amdgcn_readfirstlane(skip_s[wv][p])) {  // all outside
+                if (lane < nw) labels[k * words + base / 32 + lane] = 0u;
+                continue;
+            }
             const float E = band_s[wv][p];
             const float4* cf = coef_s + p * n4;
             float M[kP32];
@@ -240,7 +303,7 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
 }
 
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
-                           uint32_t* labels, int32_t* counts, int32_t* status, void* ws,
+                           uint32_t* labels, int32_t* counts, int32_t* status, void* ws, int cull,
                            hipStream_t stream) {
     AllpairsLayout L;
     allpairs_workspace_layout(P, n, &L);
@@ -257,8 +320,14 @@ hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, in
     const int pg = allpairs_group(n);
     const int n4 = (n + 3) & ~3;
     dim3 grid((unsigned)((m + kTilePoints - 1) / kTilePoints), (unsigned)((P + pg - 1) / pg));
-    hipLaunchKernelGGL(k_allpairs, grid, dim3(kBlock), (size_t)pg * n4 * 16, stream, hdr, coef,
-                       gen, P, n, pg, reinterpret_cast<const float2*>(Q), m, labels, counts);
+    if (cull)
+        hipLaunchKernelGGL(k_allpairs<true>, grid, dim3(kBlock), (size_t)pg * n4 * 16, stream, hdr,
+                           coef, gen, P, n, pg, reinterpret_cast<const float2*>(Q), m, labels,
+                           counts);
+    else
+        hipLaunchKernelGGL(k_allpairs<false>, grid, dim3(kBlock), (size_t)pg * n4 * 16, stream,
+                           hdr, coef, gen, P, n, pg, reinterpret_cast<const float2*>(Q), m, labels,
+                           counts);
     return hipGetLastError();
 }
 

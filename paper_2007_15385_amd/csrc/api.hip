@@ -17,6 +17,7 @@ struct pip_ctx_s {
     int mfma_blocks[2][4] = {};    // same for the matrix-core screen (kind, edge bucket)
     int batched_blocks_per_cu = 0;
     int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
+    int allpairs_cull = 0;         // skip (polygon, wave) pairs whose bounding disk misses the points
 };
 
 // A plan: one batched request bound to its buffers, its own workspace, the
@@ -613,7 +614,8 @@ pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double*
     if (!aligned(workspace, 256)) return fail(PIP_EINVAL, "workspace is not 256-byte aligned");
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    hipError_t e = pipdev::launch_allpairs(P, n, V, Q, m, labels, counts, status, workspace, stream);
+    hipError_t e = pipdev::launch_allpairs(P, n, V, Q, m, labels, counts, status, workspace,
+                                           ctx->allpairs_cull, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -697,6 +699,11 @@ pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
                 return fail(PIP_EINVAL, "PIP_OPT_MFMA_MIN_EDGES must be in [0, %d]", PIP_MAX_EDGES + 1);
             ctx->mfma_min_edges = (int)value;
             return PIP_OK;
+        case PIP_OPT_ALLPAIRS_CULL:
+            if (value != 0 && value != 1)
+                return fail(PIP_EINVAL, "PIP_OPT_ALLPAIRS_CULL must be 0 or 1");
+            ctx->allpairs_cull = (int)value;
+            return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
@@ -706,6 +713,9 @@ pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
     switch (opt) {
         case PIP_OPT_MFMA_MIN_EDGES:
             *value = ctx->mfma_min_edges;
+            return PIP_OK;
+        case PIP_OPT_ALLPAIRS_CULL:
+            *value = ctx->allpairs_cull;
             return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);

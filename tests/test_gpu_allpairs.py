@@ -116,3 +116,56 @@ def test_allpairs_full_size(P, oracle):
     say(f"[stat] all pairs: {int(counts.sum())} inside pairs, {len(bad)} poses with mismatches")
     assert len(bad) == 0
     assert np.array_equal(cnt, counts)
+
+
+def _allpairs_cull(P, F, poses, cs, Q, cull):
+    P.set_option(P.PIP_OPT_ALLPAIRS_CULL, cull)
+    try:
+        return run_allpairs(P, F, poses, cs, Q)
+    finally:
+        P.set_option(P.PIP_OPT_ALLPAIRS_CULL, 0)
+
+
+def test_allpairs_cull_full_size_identical(P):
+    """The culled launch returns exactly the dense labels and counts on the
+    2048-pose x 131,072-point lidar configuration."""
+    F = W.car_footprint()
+    Q = W.lidar_cloud()
+    poses, cs = W.random_poses()
+    _, lab0, cnt0, _ = _allpairs_cull(P, F, poses, cs, Q, 0)
+    _, lab1, cnt1, _ = _allpairs_cull(P, F, poses, cs, Q, 1)
+    assert np.array_equal(lab0, lab1)
+    assert np.array_equal(cnt0, cnt1)
+    say(f"[stat] cull: {int(cnt0.sum())} inside pairs, identical to dense")
+
+
+def test_allpairs_cull_adversarial_identical(P, oracle):
+    """Poses whose disk just touches a ring (ring radius = pose distance +- the
+    footprint radius), a cloud far from the origin (|c| >> R, where float32
+    rounding of the centre matters) and points on placed edges: culled ==
+    dense == oracle."""
+    rng = np.random.default_rng(77)
+    F = W.car_footprint()
+    R0 = float(np.sqrt((F ** 2).sum(1)).max())
+    # rings at radii r, poses at distances r - R0 - s for tiny s (tangent from inside)
+    rings = []
+    for r in (3.0, 10.0, 25.0):
+        az = rng.uniform(0, 2 * np.pi, 512)
+        rings.append(np.stack([r * np.cos(az), r * np.sin(az)], 1))
+    far = 1.0e5 + rng.uniform(-5, 5, size=(512, 2))  # a cluster far from the origin
+    Q = np.concatenate(rings + [far]).astype(np.float32)
+    K = 96
+    th = rng.uniform(-np.pi, np.pi, K).astype(np.float32)
+    d = np.concatenate([np.array([3.0, 10.0, 25.0])[rng.integers(0, 3, K - 16)]
+                        - R0 * rng.choice([-1.0, 1.0], K - 16) * (1 + rng.uniform(-1e-3, 1e-3, K - 16)),
+                        np.full(16, 1.0e5 * np.sqrt(2.0))])
+    ang = rng.uniform(0, 2 * np.pi, K)
+    ang[-16:] = np.pi / 4
+    poses = np.stack([d * np.cos(ang), d * np.sin(ang), th], 1).astype(np.float32)
+    cs = np.stack([np.cos(poses[:, 2].astype(np.float64)), np.sin(poses[:, 2].astype(np.float64))], 1)
+    _, lab0, cnt0, _ = _allpairs_cull(P, F, poses, cs, Q, 0)
+    _, lab1, cnt1, _ = _allpairs_cull(P, F, poses, cs, Q, 1)
+    bits, counts = oracle.allpairs(F, poses[:, :2].astype(np.float64), cs, Q.astype(np.float64))
+    assert np.array_equal(lab0, bits) and np.array_equal(cnt0, counts)
+    assert np.array_equal(lab1, bits) and np.array_equal(cnt1, counts)
+    say(f"[stat] adversarial cull: {int(counts.sum())} inside pairs of {K * len(Q)}")
