@@ -238,6 +238,24 @@ def run_extras(P, W, torch, stream, check):
     fwd_ms = _time(torch, stream, lambda: P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws), reps=3)
     bwd_ms = _time(torch, stream, lambda: P.pip_cost_bwd(F32t, trt, Qdt, ones, workspace=ws),
                    reps=3)
+    # culled variant (reported apart): results must be bit-identical
+    c_dense = P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws).clone()
+    g_dense = [g.clone() for g in P.pip_cost_bwd(F32t, trt, Qdt, ones, workspace=ws)[:2]]
+    P.set_option(P.PIP_OPT_COST_CULL, 1)
+    try:
+        fwd_c = _time(torch, stream, lambda: P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws), reps=3)
+        bwd_c = _time(torch, stream, lambda: P.pip_cost_bwd(F32t, trt, Qdt, ones, workspace=ws),
+                      reps=3)
+        c_cull = P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws)
+        g_cull = P.pip_cost_bwd(F32t, trt, Qdt, ones, workspace=ws)[:2]
+        cull_same = bool(torch.equal(c_dense, c_cull) and torch.equal(g_dense[0], g_cull[0])
+                         and torch.equal(g_dense[1], g_cull[1]))
+    finally:
+        P.set_option(P.PIP_OPT_COST_CULL, 0)
+    out["cost_culled"] = {"fwd_ms": round(fwd_c, 4), "bwd_ms": round(bwd_c, 4),
+                          "fwd_speedup_vs_dense": round(fwd_ms / fwd_c, 2),
+                          "bwd_speedup_vs_dense": round(bwd_ms / bwd_c, 2),
+                          "bit_identical_to_dense": cull_same}
     pairs = len(tr) * len(Qd)
     entry = {"poses": len(tr), "points": len(Qd), "pairs": pairs, "fwd_ms": round(fwd_ms, 3),
              "bwd_ms": round(bwd_ms, 3), "fwd_gpairs_per_s": round(pairs / fwd_ms / 1e6, 1),

@@ -100,8 +100,17 @@ int pip_version(void);
  *     distances from the origin of the wave's points; their labels are 0 and
  *     add 0 to the counts, exactly the dense result (a convex polygon lies in
  *     that disk).  Default 0 (dense: every pair evaluated).  Not from the
- *     paper: a culling layer in front of its test. */
-typedef enum { PIP_OPT_MFMA_MIN_EDGES = 1, PIP_OPT_ALLPAIRS_CULL = 2 } pip_option;
+ *     paper: a culling layer in front of its test.
+ *   PIP_OPT_COST_CULL: 1 lets pip_cost_fwd / pip_cost_bwd skip (pose, wave of
+ *     256 points) pairs whose footprint disk, widened by 2^-12 of the
+ *     coordinate scale, misses the wave's points: every such term is exactly
+ *     zero, so costs and gradients are bit-identical to the dense ones.
+ *     Default 0. */
+typedef enum {
+    PIP_OPT_MFMA_MIN_EDGES = 1,
+    PIP_OPT_ALLPAIRS_CULL = 2,
+    PIP_OPT_COST_CULL = 3
+} pip_option;
 pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value);
 pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);
 

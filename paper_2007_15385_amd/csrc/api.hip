@@ -18,6 +18,7 @@ struct pip_ctx_s {
     int batched_blocks_per_cu = 0;
     int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
     int allpairs_cull = 0;         // skip (polygon, wave) pairs whose bounding disk misses the points
+    int cost_cull = 0;             // skip (pose, wave) pairs of the collision cost likewise
 };
 
 // A plan: one batched request bound to its buffers, its own workspace, the
@@ -664,7 +665,7 @@ pip_status pip_cost_fwd(pip_ctx ctx, const float* footprint, int32_t n, const fl
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_cost(false, footprint, n, pose, K, Q, m, nullptr, cost, nullptr,
-                                       nullptr, nullptr, workspace, stream);
+                                       nullptr, nullptr, workspace, ctx->cost_cull, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -685,7 +686,7 @@ pip_status pip_cost_bwd(pip_ctx ctx, const float* footprint, int32_t n, const fl
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_cost(true, footprint, n, pose, K, Q, m, grad_cost, nullptr, grad_pose,
-                                       grad_footprint, residual, workspace, stream);
+                                       grad_footprint, residual, workspace, ctx->cost_cull, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -704,6 +705,10 @@ pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
                 return fail(PIP_EINVAL, "PIP_OPT_ALLPAIRS_CULL must be 0 or 1");
             ctx->allpairs_cull = (int)value;
             return PIP_OK;
+        case PIP_OPT_COST_CULL:
+            if (value != 0 && value != 1) return fail(PIP_EINVAL, "PIP_OPT_COST_CULL must be 0 or 1");
+            ctx->cost_cull = (int)value;
+            return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
@@ -716,6 +721,9 @@ pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
             return PIP_OK;
         case PIP_OPT_ALLPAIRS_CULL:
             *value = ctx->allpairs_cull;
+            return PIP_OK;
+        case PIP_OPT_COST_CULL:
+            *value = ctx->cost_cull;
             return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);

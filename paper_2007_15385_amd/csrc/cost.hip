@@ -41,6 +41,7 @@ struct CostTab {
     float4 line[kMaxEdges];  // (-n_x, -n_y, k, |h|)
     float2 g0;
     int n, n4, status;
+    float rad;  // largest vertex distance from p_0, rounded up (the footprint's disk)
 };
 
 __global__ __launch_bounds__(kWave) void k_cost_prepare(const float* __restrict__ F, int n,
@@ -59,7 +60,14 @@ __global__ __launch_bounds__(kWave) void k_cost_prepare(const float* __restrict_
     const double nx = hx / L, ny = hy / L;
     const double k = (nx * g0.x + ny * g0.y) + 0.5 * L;
     tab->line[lane] = make_float4((float)(-nx), (float)(-ny), (float)k, (float)L);
+    double dv = 0.0;
+    if (lane < n) {
+        const double dx = S.vtx[lane].x - g0.x, dy = S.vtx[lane].y - g0.y;
+        dv = sqrt(dx * dx + dy * dy);
+    }
+    const double rmax = wave_max(dv);
     if (lane == 0) {
+        tab->rad = round_up_f32(rmax * (1.0 + 1.0 / 65536.0) + 1e-30);  // NaN -> +inf
         tab->g0 = make_float2((float)g0.x, (float)g0.y);
         tab->n = n;
         tab->n4 = (n + 3) & ~3;
@@ -69,7 +77,19 @@ __global__ __launch_bounds__(kWave) void k_cost_prepare(const float* __restrict_
 
 struct PoseCS {
     float c, s, tx, ty;
+    float wx, wy;  // world position of p_0 (centre of the footprint's disk)
 };
+
+__global__ void k_fill_zero(float* __restrict__ p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0.f;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -77,8 +97,10 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// grid: x = point tiles, y = pose groups of kPG.
-template <bool BWD>
+// grid: x = point tiles, y = pose groups of kPG.  CULL: a (pose, wave) pair
+// whose footprint disk misses the wave's points contributes exactly zero
+// (no point inside, relu of a non-positive minimum) and is skipped.
+template <bool BWD, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab,
                                                const float* __restrict__ pose, int64_t K,
                                                const float2* __restrict__ Q, int64_t m,
@@ -110,6 +132,8 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
         P.s = (float)sin(th);
         P.tx = pp[0];
         P.ty = pp[1];
+        P.wx = P.tx + (P.c * g0.x - P.s * g0.y);
+        P.wy = P.ty + (P.s * g0.x + P.c * g0.y);
         pose_s[tid] = P;
     }
     const int ncomp = 2 * (n + 1);
@@ -129,10 +153,64 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
         y[j] = p.y;
         valid[j] = valid[j] && isfinite(p.x) && isfinite(p.y);  // contributes nothing otherwise
     }
+    // box, distance range from the origin and coordinate scale of the wave's points
+    float xlo = __builtin_huge_valf(), xhi = -__builtin_huge_valf();
+    float ylo = __builtin_huge_valf(), yhi = -__builtin_huge_valf();
+    float r2lo = __builtin_huge_valf(), r2hi = 0.f, amax = 0.f;
+    if constexpr (CULL) {
+#pragma unroll
+        for (int j = 0; j < kPPL; ++j) {
+            if (valid[j]) {
+                xlo = fminf(xlo, x[j]);
+                xhi = fmaxf(xhi, x[j]);
+                ylo = fminf(ylo, y[j]);
+                yhi = fmaxf(yhi, y[j]);
+                const float r2 = fmaf(x[j], x[j], y[j] * y[j]);
+                r2lo = fminf(r2lo, r2);
+                r2hi = fmaxf(r2hi, r2);
+                amax = fmaxf(amax, fmaxf(fabsf(x[j]), fabsf(y[j])));
+            }
+        }
+        xlo = -wave_max_f(-xlo);
+        xhi = wave_max_f(xhi);
+        ylo = -wave_max_f(-ylo);
+        yhi = wave_max_f(yhi);
+        r2lo = -wave_max_f(-r2lo);
+        r2hi = wave_max_f(r2hi);
+        amax = wave_max_f(amax);
+    }
     __syncthreads();
 
     for (int p = 0; p < pg; ++p) {
         const PoseCS P = pose_s[p];
+        if constexpr (CULL) {
+            // The footprint lies in the disk (p_0 world position, rad).  A
+            // point the float32 evaluation counts inside is within a few ulps
+            // of the footprint, far less than the slack 2^-12 x (coordinate
+            // scale + disk), so a disk that misses the wave's box or distance
+            // range (widened by the slack) means every term is exactly zero.
+            const float R = tab->rad;
+            const float Rs =
+                R + (fabsf(P.wx) + fabsf(P.wy) + fabsf(P.tx) + fabsf(P.ty) + amax + R) *
+                        (1.0f / 4096.0f);
+            bool skip = P.wx + Rs < xlo || P.wx - Rs > xhi || P.wy + Rs < ylo || P.wy - Rs > yhi;
+            const float dc = sqrtf(fmaf(P.wx, P.wx, P.wy * P.wy));
+            const float hi = dc + Rs, lo = dc - Rs;
+            const float sl = 1.0f / 65536.0f;
+            skip = skip || hi * hi * (1.0f + sl) < r2lo * (1.0f - sl);
+            skip = skip || (lo > 0.f && lo * lo * (1.0f - sl) > r2hi * (1.0f + sl));
+            skip = skip && R < __builtin_huge_valf() && P.wx == P.wx && P.wy == P.wy;
+            if (skip) {
+                if (lane == 0) {
+                    red_s[p][wv][0] = 0.f;
+                    if constexpr (BWD) {
+                        red_s[p][wv][1] = 0.f;
+                        red_s[p][wv][2] = 0.f;
+                    }
+                }
+                continue;
+            }
+        }
         float bx[kPPL], by[kPPL], dmin[kPPL];
         int arg[kPPL];
 #pragma unroll
@@ -400,7 +478,7 @@ size_t cost_workspace_layout(int n, int64_t K, int64_t m, CostLayout* L) {
 
 hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, int64_t K,
                        const float* Q, int64_t m, const float* grad_cost, float* cost,
-                       float* grad_pose, float* grad_F, float* residual, void* ws,
+                       float* grad_pose, float* grad_F, float* residual, void* ws, int cull,
                        hipStream_t stream) {
     CostLayout L;
     cost_workspace_layout(n, K, m, &L);
@@ -415,22 +493,31 @@ hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, 
     const int T = L.T > 0 ? L.T : 1;
     if (L.T > 0 && K > 0) {
         dim3 grid((unsigned)L.T, (unsigned)L.G);
-        if (!backward)
-            hipLaunchKernelGGL(k_cost<false>, grid, dim3(kBlock), 0, stream, tab, pose, K,
-                               reinterpret_cast<const float2*>(Q), m, grad_cost, pc, pp, pgn, T);
+        const float2* Q2 = reinterpret_cast<const float2*>(Q);
+        const size_t lds = (size_t)kWavesPerBlock * 2 * (n + 1) * kWave * sizeof(float);
+        if (!backward && !cull)
+            hipLaunchKernelGGL((k_cost<false, false>), grid, dim3(kBlock), 0, stream, tab, pose, K,
+                               Q2, m, grad_cost, pc, pp, pgn, T);
+        else if (!backward)
+            hipLaunchKernelGGL((k_cost<false, true>), grid, dim3(kBlock), 0, stream, tab, pose, K,
+                               Q2, m, grad_cost, pc, pp, pgn, T);
+        else if (!cull)
+            hipLaunchKernelGGL((k_cost<true, false>), grid, dim3(kBlock), lds, stream, tab, pose, K,
+                               Q2, m, grad_cost, pc, pp, pgn, T);
         else
-            hipLaunchKernelGGL(k_cost<true>, grid, dim3(kBlock),
-                               (size_t)kWavesPerBlock * 2 * (n + 1) * kWave * sizeof(float), stream,
-                               tab, pose, K, reinterpret_cast<const float2*>(Q), m, grad_cost, pc,
-                               pp, pgn, T);
+            hipLaunchKernelGGL((k_cost<true, true>), grid, dim3(kBlock), lds, stream, tab, pose, K,
+                               Q2, m, grad_cost, pc, pp, pgn, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
-        // no points: every partial is zero
-        const size_t nb = backward ? (size_t)L.G * T * 2 * (kMaxEdges + 1) * 4 : (size_t)K * T * 4;
-        if ((e = hipMemsetAsync(backward ? (void*)pgn : (void*)pc, 0, nb, stream)) != hipSuccess)
-            return e;
-        if (backward && (e = hipMemsetAsync(pp, 0, (size_t)K * T * 12, stream)) != hipSuccess)
-            return e;
+        // no points: every partial is zero (a fill kernel, safe under graph capture)
+        const int64_t nf = backward ? (int64_t)L.G * T * 2 * (kMaxEdges + 1) : (int64_t)K * T;
+        if (nf > 0)
+            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, stream,
+                               backward ? pgn : pc, nf);
+        if (backward && K > 0)
+            hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((K * T * 3 + 255) / 256)), dim3(256), 0,
+                               stream, pp, K * T * 3);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     const unsigned kb = (unsigned)((K + 255) / 256);
     if (!backward) {

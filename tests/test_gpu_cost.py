@@ -181,3 +181,51 @@ def test_cost_full_size_timing(P, oracle):
     got = c.cpu().numpy()[idx]
     assert np.all(np.abs(got - want) <= 1e-4 * np.abs(want) + 1e-6)
     assert torch.isfinite(gp).all() and torch.isfinite(gF).all()
+
+
+def _cost_both(P, F, poses, Q, w, cull):
+    P.set_option(P.PIP_OPT_COST_CULL, cull)
+    try:
+        c = gpu_cost(P, F, poses, Q)
+        gp, gF, res = gpu_grad(P, F, poses, Q, w)
+    finally:
+        P.set_option(P.PIP_OPT_COST_CULL, 0)
+    return c, gp, gF
+
+
+def test_cost_cull_bit_identical(P):
+    """Culled forward and backward equal the dense ones bit for bit: on the
+    full 65,536-pose x 65,536-point configuration, and on poses whose
+    footprint disk is tangent to a ring or that sit in a cloud far from the
+    origin."""
+    F = W.car_footprint().astype(np.float32)
+    Q = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)
+    poses = W.trajectories().reshape(-1, 3)
+    w = np.ones(len(poses), np.float32)
+    a = _cost_both(P, F, poses, Q, w, 0)
+    b = _cost_both(P, F, poses, Q, w, 1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    say(f"[stat] cull: {int((a[0] > 0).sum())} of {len(poses)} poses with cost > 0, identical")
+
+    rng = np.random.default_rng(91)
+    R0 = float(np.sqrt((F.astype(np.float64) ** 2).sum(1)).max())
+    rings = []
+    for r in (3.0, 10.0, 25.0):
+        az = rng.uniform(0, 2 * np.pi, 1024)
+        rings.append(np.stack([r * np.cos(az), r * np.sin(az)], 1))
+    far = 1.0e5 + rng.uniform(-5, 5, size=(1024, 2))
+    Q2 = np.concatenate(rings + [far]).astype(np.float32)
+    K = 128
+    d = np.concatenate([np.array([3.0, 10.0, 25.0])[rng.integers(0, 3, K - 16)]
+                        - R0 * rng.choice([-1.0, 1.0], K - 16) * (1 + rng.uniform(-1e-3, 1e-3, K - 16)),
+                        np.full(16, 1.0e5 * np.sqrt(2.0))])
+    ang = rng.uniform(0, 2 * np.pi, K)
+    ang[-16:] = np.pi / 4
+    poses2 = np.stack([d * np.cos(ang), d * np.sin(ang), rng.uniform(-np.pi, np.pi, K)], 1).astype(np.float32)
+    w2 = rng.uniform(0.5, 2.0, K).astype(np.float32)
+    a = _cost_both(P, F, poses2, Q2, w2, 0)
+    b = _cost_both(P, F, poses2, Q2, w2, 1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert (a[0] > 0).sum() > 8
