@@ -37,8 +37,7 @@ NS = (3, 4, 8, 16, 32, 64)
 
 # sources of the single-polygon streaming path (the kernels whose HBM traffic
 # profiles/hbm_traffic.json records)
-STREAM_SOURCES = ("api.hip", "device.hpp", "kernels.hpp", "stream.hip", "stream32.hpp",
-                  "stream_mfma.hip")
+STREAM_SOURCES = ("device.hpp", "kernels.hpp", "stream.hip", "stream32.hpp", "stream_mfma.hip")
 
 
 def kernel_source_hash() -> str:

@@ -500,10 +500,8 @@ pip_status pip_plan_autotune(pip_plan p, int32_t reps, hipStream_t stream) {
                     have_ref = true;
                 } else {
                     unsigned long long diff = 0;
-                    e = hipMemsetAsync(p->d_diff, 0, sizeof(unsigned long long), stream);
-                    if (e == hipSuccess)
-                        e = pipdev::launch_count_diff(p->ref_labels, p->D.labels, p->label_words,
-                                                      p->d_diff, stream);
+                    e = pipdev::launch_count_diff(p->ref_labels, p->D.labels, p->label_words,
+                                                  p->d_diff, stream);
                     if (e == hipSuccess)
                         e = hipMemcpyAsync(&diff, p->d_diff, sizeof diff, hipMemcpyDeviceToHost, stream);
                     if (e == hipSuccess) e = hipStreamSynchronize(stream);

@@ -469,6 +469,8 @@ hipError_t batched_max_blocks_per_cu(int* out) {
 }  // namespace pipdev
 
 namespace {
+__global__ void k_zero_u64(unsigned long long* out) { *out = 0ull; }
+
 __global__ void k_count_diff(const uint32_t* a, const uint32_t* b, int64_t nwords,
                              unsigned long long* out) {
     unsigned long long local = 0;
@@ -480,8 +482,10 @@ __global__ void k_count_diff(const uint32_t* a, const uint32_t* b, int64_t nword
 }  // namespace
 
 namespace pipdev {
+// *out = number of differing words (the counter is cleared first, in-stream).
 hipError_t launch_count_diff(const uint32_t* a, const uint32_t* b, int64_t nwords,
                              unsigned long long* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, stream, out);
     hipLaunchKernelGGL(k_count_diff, dim3(1024), dim3(256), 0, stream, a, b, nwords, out);
     return hipGetLastError();
 }
