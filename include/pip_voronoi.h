@@ -96,7 +96,7 @@ int pip_version(void);
  *     Default 25 (measured crossover of the two screens).
  *   PIP_OPT_ALLPAIRS_CULL: 1 lets pip_voronoi_allpairs skip every (polygon,
  *     64 x 8-point wave) pair whose bounding disk (centre p_0, radius the
- *     largest vertex distance, rounded up) misses the box or the range of
+ *     largest vertex distance, rounded up) misses the bounding box or the range of
  *     distances from the origin of the wave's points; their labels are 0 and
  *     add 0 to the counts, exactly the dense result (a convex polygon lies in
  *     that disk).  Default 0 (dense: every pair evaluated).  Not from the
