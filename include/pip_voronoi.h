@@ -132,7 +132,10 @@ pip_status polygon_to_generators(pip_ctx ctx, const double *V, int32_t n, double
  * one convex polygon.  Q is [m][2] of type qdt; labels [ceil(m/32)] words;
  * status optional [1].  The polygon's generators are derived on the device
  * in binary64; margins are screened in float32 with a proven error band and
- * the undecided points are re-decided in binary64.
+ * the undecided points are re-decided in binary64.  For float32 points one
+ * launch handles fewer than 2^23 chunks of 512 points per wave of the grid
+ * (about 2^44 points on a full device); beyond that the call returns
+ * PIP_EUNSUPPORTED and the points must be split over several calls.
  */
 pip_status pip_voronoi(pip_ctx ctx, const double *V, int32_t n, const void *Q, pip_dtype qdt,
                        int64_t m, uint32_t *labels, int32_t *status, hipStream_t stream);

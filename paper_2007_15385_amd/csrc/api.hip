@@ -155,6 +155,17 @@ pip_status run_stream(pip_ctx ctx, int kind, const double* V, int32_t n, const v
                  : 0;
     L.max_blocks = L.mfma ? mfma_blocks(ctx, kind, n) : persistent_blocks(ctx, kind, (int)qdt);
     L.stream = stream;
+    if (qdt == PIP_F32 && kind != pipdev::K_RAY && kind != pipdev::K_MARGIN) {
+        // the recheck queues code a point as (chunk iteration << 9 | point):
+        // every wave must walk fewer than 2^23 chunks of 512 points
+        const int64_t nchunks = (m + 511) / 512;
+        const int64_t want = (nchunks + 3) / 4;
+        const int64_t grid = want < L.max_blocks ? want : L.max_blocks;
+        const int64_t waves = 4 * (grid > 0 ? grid : 1);
+        if ((nchunks + waves - 1) / waves >= (int64_t(1) << 23))
+            return fail(PIP_EUNSUPPORTED, "m = %lld points is too large for one launch on this device; "
+                        "split the point array", (long long)m);
+    }
     hipError_t e = pipdev::launch_stream(L);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
