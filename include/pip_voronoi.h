@@ -188,8 +188,9 @@ pip_status pip_voronoi_max_margin(pip_ctx ctx, const double *V, int32_t n, const
  *                 >= ceil(set size / 32)).  Bits past a set's last point in its
  *                 last word are written as 0.
  *   status        optional [P] int32 device status per polygon; a polygon
- *                 with n < 3 gets PIP_EINVAL, n > 64 PIP_EUNSUPPORTED, and its
- *                 points are all labelled 0; offsets outside
+ *                 with n < 3 gets PIP_EINVAL, n > 64 or a point set of 2^32 or
+ *                 more points PIP_EUNSUPPORTED, and its points are all
+ *                 labelled 0; offsets outside
  *                 [0, total_vertices] / [0, total_points] give PIP_EINVAL and
  *                 leave that polygon's labels untouched.
  *   workspace     device buffer of pip_voronoi_batched_workspace_bytes(P,

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
     int bad = ST_OK;
     if (range_bad || nn < 3) bad = ST_INVAL;
     else if (nn > kMaxEdges) bad = 6;  // PIP_EUNSUPPORTED
+    else if (p1 - p0 > 0xffffffffll) bad = 6;  // recheck queue holds 32-bit point indices
     // an unusable polygon with a valid point range gets all-zero labels
     const int64_t s = range_bad ? 0 : p1 - p0;
     const int64_t chunks = (s + kChunk32 - 1) / kChunk32;
