@@ -1,7 +1,10 @@
 // Single-polygon streaming kernels: one polygon, a very large point array.
 //
 // Each workgroup first derives the polygon's generators (Section 3) into LDS,
-// then every wave walks its own chunks of 256 points (4 per lane, lane l
+// then every wave walks its own chunks of points.  float32 points for the
+// Voronoi, sign-of-offset and plain tests take k_stream32 (512-point chunks,
+// see stream32.hpp); binary64 points, ray crossing and the largest-margin
+// output take k_stream, whose chunks are 256 points (4 per lane, lane l
 // holding points l, l+64, l+128, l+192 of the chunk, so each 8- or 16-byte
 // load of a wave covers one contiguous span of memory).  Results are packed
 // with wave ballots: the mask of slot j covers points [64 j, 64 j + 64) of
