@@ -363,7 +363,8 @@ def main() -> int:
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(end)
     ms_per_step = total_ms / args.steps
-    per_n_ms = {n: float(np.mean([a.elapsed_time(b) for a, b in ev[n]])) for n in NS}
+    per_n_all = {n: np.array([a.elapsed_time(b) for a, b in ev[n]]) for n in NS}
+    per_n_ms = {n: float(per_n_all[n].mean()) for n in NS}
     tests_per_step = m * len(NS)
     value = tests_per_step / (ms_per_step * 1e-3) / 1e9
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
@@ -373,7 +374,11 @@ def main() -> int:
         t = per_n_ms[n] * 1e-3
         gbs = BYTES_PER_TEST * m / t / 1e9
         tfl = 4.0 * n * m / t / 1e12
-        kernels.append({"n": n, "ms": round(per_n_ms[n], 4), "gtests_per_s": round(m / t / 1e9, 2),
+        kernels.append({"n": n, "ms": round(per_n_ms[n], 4),
+                        "ms_min": round(float(per_n_all[n].min()), 4),
+                        "ms_median": round(float(np.median(per_n_all[n])), 4),
+                        "ms_p90": round(float(np.percentile(per_n_all[n], 90)), 4),
+                        "gtests_per_s": round(m / t / 1e9, 2),
                         "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                         "fp32_tflops": round(tfl, 2),
                         "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)})
@@ -414,11 +419,14 @@ def main() -> int:
 
     soo = {n: time_fn(P.pip_sign_of_offset, n) for n in NS}
     plain = {n: time_fn(P.pip_voronoi_fp32_plain, n) for n in NS}
+    ray = {n: time_fn(P.pip_ray_crossing, n, reps=1) for n in NS}
     comparisons = {
         "sign_of_offset_gtests_per_s": round(tests_per_step / (sum(soo.values()) * 1e-3) / 1e9, 2),
         "sign_of_offset_ms": {str(n): round(v, 4) for n, v in soo.items()},
         "fp32_plain_gtests_per_s": round(tests_per_step / (sum(plain.values()) * 1e-3) / 1e9, 2),
         "fp32_plain_ms": {str(n): round(v, 4) for n, v in plain.items()},
+        "ray_crossing_gtests_per_s": round(tests_per_step / (sum(ray.values()) * 1e-3) / 1e9, 2),
+        "ray_crossing_ms": {str(n): round(v, 4) for n, v in ray.items()},
     }
 
     # ---- parity on a sample + oracle baseline ------------------------------
@@ -444,11 +452,31 @@ def main() -> int:
             P.pip_voronoi_fp32_plain(polys[n], pts[n], labels[n])
             got = labels[n][: (S + 31) // 32].cpu().numpy().view(np.uint32)
             plain_mismatches += int(np.unpackbits((got ^ pack_bits(want)).view(np.uint8)).sum())
+        threads = o.num_threads()
+        # one thread on 1/64 of the sample
+        s1 = max(S // 64, 1)
+        o.set_num_threads(1)
+        c0 = time.perf_counter()
+        for n in NS:
+            V, Qs = host_q[n]
+            o.voronoi(V, Qs[:s1].astype(np.float64))
+        t1 = time.perf_counter() - c0
+        o.set_num_threads(threads)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": round(S * len(NS) / cpu_t / 1e9, 5), "unit": "G tests/s",
-               "cores": o.num_threads(), "kind": "oracle",
+               "cores": threads, "kind": "oracle",
                "sample": f"first {S} points of each of the 6 polygons' arrays "
                          f"({S * len(NS)} tests), FP64 C oracle, OpenMP over points",
-               "seconds": round(cpu_t, 2)}
+               "seconds": round(cpu_t, 2),
+               "per_core_gtests_per_s": round(S * len(NS) / cpu_t / 1e9 / threads, 5),
+               "single_thread_gtests_per_s": round(s1 * len(NS) / t1 / 1e9, 5),
+               "single_thread_sample": f"first {s1} points of each polygon",
+               "cpu_model": model, "host_cpus": os.cpu_count()}
         comparisons["fp32_plain_mismatches_on_sample"] = plain_mismatches
 
     extras = {} if args.no_extras else run_extras(P, W, torch, stream, not args.no_cpu)
