@@ -297,3 +297,26 @@ def test_streaming_full_size_sampled(P, oracle, n):
         f"inside fraction {got.mean():.4f}")
     assert len(bad) == 0
     assert labels.size == W.STREAM_M // 32
+
+
+@pytest.mark.parametrize("qdt", [np.float32, np.float64])
+def test_ray_crossing_nonconvex(P, oracle, qdt):
+    """Ray crossing (Algorithm 1) handles simple non-convex polygons: a
+    10-point star and a U shape, 200k points plus every vertex and edge
+    midpoint, bit-identical to the binary64 oracle."""
+    rng = np.random.default_rng(44)
+    t = np.arange(10) * (2 * np.pi / 10)
+    r = np.where(np.arange(10) % 2 == 0, 1.0, 0.38)
+    star = np.stack([r * np.cos(t), r * np.sin(t)], 1)
+    ushape = np.array([[0, 0], [3, 0], [3, 3], [2, 3], [2, 1], [1, 1], [1, 3], [0, 3]], float)
+    for V in (star, ushape):
+        lo, hi = V.min(0) - 0.3, V.max(0) + 0.3
+        Q = rng.uniform(lo, hi, size=(200_000, 2))
+        mids = 0.5 * (V + np.roll(V, 1, axis=0))
+        Q = np.concatenate([Q, V, mids]).astype(qdt)
+        st = []
+        got = run_gpu(P, "pip_ray_crossing", V, Q, status=st)
+        assert st == [0]
+        want = oracle.ray_crossing(V, Q.astype(np.float64))
+        assert_same(got, pack_bits(want), len(Q), "ray_crossing")
+        assert 0.2 < want.mean() < 0.8
