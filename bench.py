@@ -223,6 +223,20 @@ def run_extras(P, W, torch, stream, check):
     out["allpairs_culled"] = {"ms": round(ms_c, 4), "speedup_vs_dense": round(ms / ms_c, 2),
                               "dense_equivalent_gtests_per_s": round(nt / ms_c / 1e6, 1),
                               "labels_and_counts_equal_dense": same}
+    # antipodal pairing (the car is centrally symmetric: 4 pairs instead of
+    # 8 edges), alone and with culling; labels and counts must equal the dense
+    for key, cull in (("allpairs_paired", 0), ("allpairs_paired_culled", 1)):
+        P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, 1)
+        P.set_option(P.PIP_OPT_ALLPAIRS_CULL, cull)
+        try:
+            ms_p = _time(torch, stream, allpairs, reps=10)
+            same = bool(torch.equal(labs, dense_l) and torch.equal(cnts, dense_c))
+        finally:
+            P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, 0)
+            P.set_option(P.PIP_OPT_ALLPAIRS_CULL, 0)
+        out[key] = {"ms": round(ms_p, 4), "speedup_vs_dense": round(ms / ms_p, 2),
+                    "dense_equivalent_gtests_per_s": round(nt / ms_p / 1e6, 1),
+                    "labels_and_counts_equal_dense": same}
     print("[bench] all pairs done", file=sys.stderr, flush=True)
 
     # differentiable cost: 1024 trajectories x 64 poses x 65,536 points

@@ -105,11 +105,20 @@ int pip_version(void);
  *     256 points) pairs whose footprint disk, widened by 2^-12 of the
  *     coordinate scale, misses the wave's points: every such term is exactly
  *     zero, so costs and gradients are bit-identical to the dense ones.
+ *     Default 0.
+ *   PIP_OPT_ALLPAIRS_PAIR: 1 lets pip_voronoi_allpairs evaluate a polygon
+ *     with an even edge count that is centrally symmetric (up to u = 2^-24 of
+ *     its coefficients) as n/2 antipodal edge pairs: edges i and i + n/2 have
+ *     opposite generator offsets (Section 3, Eq. 8), so the larger of their two
+ *     margins (Eq. 11) is |t| - h of one affine form t; the remaining
+ *     asymmetry is bounded in the float32 band, so labels and counts are those
+ *     of the dense evaluation.  Other polygons keep the per-edge table.
  *     Default 0. */
 typedef enum {
     PIP_OPT_MFMA_MIN_EDGES = 1,
     PIP_OPT_ALLPAIRS_CULL = 2,
-    PIP_OPT_COST_CULL = 3
+    PIP_OPT_COST_CULL = 3,
+    PIP_OPT_ALLPAIRS_PAIR = 4
 } pip_option;
 pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value);
 pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);

@@ -316,6 +316,11 @@ def pip_poses_to_polygons(footprint, pose, cs, out=None):
     return out
 
 
+def allpairs_workspace_bytes(P: int, n: int) -> int:
+    """Bytes of the pip_voronoi_allpairs workspace for P polygons of n edges."""
+    return int(_lib().pip_voronoi_allpairs_workspace_bytes(P, n))
+
+
 def pip_voronoi_allpairs(V, Q, labels=None, counts=None, status=None, workspace=None):
     """V [P, n, 2] float64, Q [m, 2] float32 -> (labels [P, ceil(m/32)] int32,
     counts [P] int32, status [P] int32)."""
@@ -333,7 +338,7 @@ def pip_voronoi_allpairs(V, Q, labels=None, counts=None, status=None, workspace=
         counts = torch.empty(max(Pn, 1), dtype=torch.int32, device=V.device)
     if status is None:
         status = torch.empty(max(Pn, 1), dtype=torch.int32, device=V.device)
-    need = int(_lib().pip_voronoi_allpairs_workspace_bytes(Pn, n))
+    need = allpairs_workspace_bytes(Pn, n)
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=V.device)
     ctx = context(d)

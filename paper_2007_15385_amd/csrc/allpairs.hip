@@ -16,6 +16,17 @@
 //                        compares into ballots, 16 label words per (polygon,
 //                        wave) are assembled in one VGPR and stored at once,
 //                        and the inside bits are counted per polygon.
+//
+// Antipodal pairing (optional, Section 5's remark that work per edge is what
+// counts): for a centrally symmetric polygon with an even number of edges,
+// edge j = i + n/2 is parallel to edge i on the other side of p_0, so
+// p_j - p_0 = -(p_i - p_0) and, with t = a X + b Y + s, a = (A_i - A_j)/2,
+// b = (B_i - B_j)/2, s = (C_j - C_i)/2, h = (C_i + C_j)/2,
+//     max(m_i, m_j) = |t| - h + (delta_a X + delta_b Y),
+// delta_a = (A_i + A_j)/2, delta_b likewise (zero for exact symmetry).  One
+// pair costs two fma and one subtraction instead of four fma and two max.
+// The binary64 placement of a footprint leaves delta of a few ulps; its bound
+// goes into the band (KA, KB), so labels stay those of Algorithm 5.
 #include "device.hpp"
 #include "kernels.hpp"
 #include "stream32.hpp"
@@ -49,7 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
                                                           float4* __restrict__ coef,
                                                           double2* __restrict__ gen,
                                                           int32_t* __restrict__ status,
-                                                          int32_t* __restrict__ counts) {
+                                                          int32_t* __restrict__ counts, int pair) {
     __shared__ PolyLds S[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
@@ -72,16 +83,73 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
     }
     const double rmax = wave_max(dv);
     const int n4 = L.n4;
-    if (lane < n4) coef[k * n4 + lane] = L.coef[lane];
+
+    // Antipodal pairs (edge i, edge i + n/2), lane i < n/2; binary64 values
+    // formed as prepare_polygon forms them in the global frame (o = 0).
+    //   float32 part: t = fma(a, X, fma(b, Y, s)) and |t| - h carry
+    //     5.1 u (|a||X| + |b||Y| + |s| + |h|) (coefficient roundings 1.01 u
+    //     each, two fma, one subtraction), plus the binary64 roundings of
+    //     a, b (2 v max|h_x|, |h_y| each) and of s, h (v max|C| each, and
+    //     4.1 v (G2 + d2) each from C_i, C_j);
+    //   asymmetry: |delta_a||X| + |delta_b||Y|, delta formed in binary64
+    //     (error v (2 max|h_x| + |delta_a|));
+    //   binary64 part of Algorithm 5: as for the unpaired table.
+    // Pairing is used only when the asymmetry is below u of the pair
+    // coefficients (at most doubles the X, Y terms of the band).
+    int npair = 0;
+    float pKQ = 0.f, pKA = 0.f, pKB = 0.f, pKC = 0.f;
+    float4 prow = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (pair && (n & 1) == 0) {
+        const int hn = n >> 1;
+        const int i = lane < hn ? lane : 0;
+        const double d2 = g0x * g0x + g0y * g0y;
+        const double gix = L.gen[1 + i].x, giy = L.gen[1 + i].y;
+        const double gjx = L.gen[1 + i + hn].x, gjy = L.gen[1 + i + hn].y;
+        const double hxi = gix - g0x, hyi = giy - g0y, hxj = gjx - g0x, hyj = gjy - g0y;
+        const double g2i = gix * gix + giy * giy, g2j = gjx * gjx + gjy * gjy;
+        const double Ci = g2i - d2, Cj = g2j - d2;
+        const float a = (float)(hxi - hxj), b = (float)(hyi - hyj);
+        const float s = (float)(0.5 * (Cj - Ci)), h = (float)(0.5 * (Ci + Cj));
+        prow = make_float4(a, b, s, h);
+        const bool fin = isfinite(a) && isfinite(b) && isfinite(s) && isfinite(h) &&
+                         fabs((double)a) < kCoefLimit && fabs((double)b) < kCoefLimit &&
+                         fabs((double)s) < kCoefLimit && fabs((double)h) < kCoefLimit;
+        const double ap = wave_max(fabs((double)a)), bp = wave_max(fabs((double)b));
+        const double gp = wave_max(fabs((double)s) + fabs((double)h));
+        const double DA = wave_max(fabs(hxi + hxj)), DB = wave_max(fabs(hyi + hyj));
+        const double hmx = wave_max(fmax(fabs(hxi), fabs(hxj)));
+        const double hmy = wave_max(fmax(fabs(hyi), fabs(hyj)));
+        const double cm = wave_max(fmax(fabs(Ci), fabs(Cj)));
+        const double G2 = wave_max(fmax(g2i, g2j));
+        const double H2 = wave_max(fmax(hxi * hxi + hyi * hyi, hxj * hxj + hyj * hyj));
+        const bool sym = __ballot(!fin) == 0 && L.status == 0 && DA <= kU32 * ap &&
+                         DB <= kU32 * bp && ap > 0.0 && bp > 0.0;
+        if (sym) {
+            const double infl = 1.0 + 9.5367431640625e-07;  // 1 + 2^-20
+            npair = hn;
+            pKA = round_up_f32((5.1 * kU32 * ap + DA + 2.02 * kU64 * (2.0 * hmx + DA)) * infl);
+            pKB = round_up_f32((5.1 * kU32 * bp + DB + 2.02 * kU64 * (2.0 * hmy + DB)) * infl);
+            pKC = round_up_f32((5.1 * kU32 * gp + 2.02 * kU64 * cm + 8.2 * kU64 * (G2 + d2) +
+                                4.0001 * kU64 * (6.0 * d2 + 2.0 * H2) +
+                                kEpsAbs * (1.0 + ap + bp)) * infl);
+            pKQ = round_up_f32(24.01 * kU64 * infl);
+        }
+    }
+    const int np4 = (npair + 3) & ~3;
+    if (npair > 0) {
+        if (lane < np4) coef[k * n4 + lane] = prow;  // rows past n/2 repeat pair 0
+    } else if (lane < n4) {
+        coef[k * n4 + lane] = L.coef[lane];
+    }
     for (int i = lane; i <= n; i += kWave) gen[k * (n + 1) + i] = L.gen[i];
     if (lane == 0) {
         PolyHdr H;
         H.ox = L.ox;
         H.oy = L.oy;
-        H.KQ = L.KQ;
-        H.KA = L.KA;
-        H.KB = L.KB;
-        H.KC = L.KC;
+        H.KQ = npair ? pKQ : L.KQ;
+        H.KA = npair ? pKA : L.KA;
+        H.KB = npair ? pKB : L.KB;
+        H.KC = npair ? pKC : L.KC;
         H.n = n;
         H.n4 = n4;
         H.status = L.status;
@@ -89,7 +157,8 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
         H.cy = (float)g0y;
         const double ce = fabs((double)H.cx - g0x) + fabs((double)H.cy - g0y);
         H.rad = round_up_f32((rmax + ce) * (1.0 + 1.0 / 65536.0) + 1e-30);  // NaN -> +inf
-        for (int i = 0; i < 4; ++i) H.pad[i] = 0;
+        H.npair = npair;
+        for (int i = 0; i < 3; ++i) H.pad[i] = 0;
         hdr[k] = H;
         if (status) status[k] = L.status;
         if (counts) counts[k] = 0;  // k_allpairs accumulates into it
@@ -104,7 +173,8 @@ __device__ __forceinline__ float wave_max_f(float v) {
 
 // grid: x = point tiles of 2048, y = polygon groups of PG (<= 16).  CULL:
 // skip (polygon, wave) pairs whose bounding disk misses the wave's points.
-template <bool CULL>
+// PAIR: polygons whose table holds antipodal pairs take the paired loop.
+template <bool CULL, bool PAIR>
 __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__ hdr,
                                                    const float4* __restrict__ coef,
                                                    const double2* __restrict__ gen, int64_t P,
@@ -115,6 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
     __shared__ int32_t cnt_s[kMaxGroup];
     __shared__ float band_s[kWavesPerBlock][kMaxGroup];  // per (wave, polygon)
     __shared__ int skip_s[kWavesPerBlock][kMaxGroup];    // polygon's disk misses the wave's points
+    __shared__ int npair_s[kMaxGroup];                   // antipodal pair rows (0: edge rows)
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -132,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
     const int64_t rem64 = m - base;
     const int rem = (int)(rem64 < kChunk32 ? (rem64 > 0 ? rem64 : 0) : kChunk32);
     float x[kP32], y[kP32];
-    uint64_t live[kP32];
+    uint64_t live[kP32] = {};
     float xm = 0.f, ym = 0.f;
     // box and distance range (from the origin) of the wave's live points
     float xlo = __builtin_huge_valf(), xhi = -__builtin_huge_valf();
@@ -172,6 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
             r2hi = wave_max_f(r2hi);
         }
     }
+    uint64_t live_all = ~0ull;
+#pragma unroll
+    for (int j = 0; j < kP32; ++j) live_all &= live[j];
+    const bool all_live = rem == kChunk32 && live_all == ~0ull;
     const float r2m = fmaf(xm, xm, ym * ym);
     // band for every point of this wave and polygon p of the group (monotone
     // in |x|, |y|), one lane per polygon
@@ -198,6 +273,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
             skip = skip && R < __builtin_huge_valf() && cx == cx && cy == cy;
         }
         if constexpr (CULL) skip_s[wv][lane] = skip ? 1 : 0;
+        if (PAIR && wv == 0) npair_s[lane] = H.npair;
     }
     __syncthreads();
 
@@ -212,37 +288,72 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
             const float E = band_s[wv][p];
             const float4* cf = coef_s + p * n4;
             float M[kP32];
-            {  // edges 0-3 start the max (n4 >= 4)
-                const float4 c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
+            const int np = PAIR ? __builtin_amdgcn_readfirstlane(npair_s[p]) : 0;
+            if (PAIR && np > 0) {
+                // max over pairs of |t| - h, four pairs at a time (rows past
+                // the last pair repeat pair 0)
+                const int np4 = (np + 3) & ~3;
+                auto pm = [](float4 c, float xx, float yy) {
+                    return fabsf(fmaf(c.x, xx, fmaf(c.y, yy, c.z))) - c.w;
+                };
+                {
+                    const float4 c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
 #pragma unroll
-                for (int j = 0; j < kP32; ++j) {
-                    const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
-                    const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
-                    const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
-                    const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
-                    M[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
+                    for (int j = 0; j < kP32; ++j)
+                        M[j] = fmaxf(fmaxf(fmaxf(pm(c0, x[j], y[j]), pm(c1, x[j], y[j])),
+                                           pm(c2, x[j], y[j])),
+                                     pm(c3, x[j], y[j]));
+                }
+                for (int e = 4; e < np4; e += 4) {
+                    const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
+#pragma unroll
+                    for (int j = 0; j < kP32; ++j) {
+                        M[j] = fmaxf(fmaxf(M[j], pm(c0, x[j], y[j])), pm(c1, x[j], y[j]));
+                        M[j] = fmaxf(fmaxf(M[j], pm(c2, x[j], y[j])), pm(c3, x[j], y[j]));
+                    }
+                }
+            } else {
+                {  // edges 0-3 start the max (n4 >= 4)
+                    const float4 c0 = cf[0], c1 = cf[1], c2 = cf[2], c3 = cf[3];
+#pragma unroll
+                    for (int j = 0; j < kP32; ++j) {
+                        const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
+                        const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
+                        const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
+                        const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
+                        M[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
+                    }
+                }
+                for (int e = 4; e < n4; e += 4) {
+                    const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
+#pragma unroll
+                    for (int j = 0; j < kP32; ++j) {
+                        const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
+                        const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
+                        const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
+                        const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
+                        M[j] = fmaxf(fmaxf(M[j], m0), m1);
+                        M[j] = fmaxf(fmaxf(M[j], m2), m3);
+                    }
                 }
             }
-            for (int e = 4; e < n4; e += 4) {
-                const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
-#pragma unroll
-                for (int j = 0; j < kP32; ++j) {
-                    const float m0 = fmaf(c0.x, x[j], fmaf(c0.y, y[j], c0.z));
-                    const float m1 = fmaf(c1.x, x[j], fmaf(c1.y, y[j], c1.z));
-                    const float m2 = fmaf(c2.x, x[j], fmaf(c2.y, y[j], c2.z));
-                    const float m3 = fmaf(c3.x, x[j], fmaf(c3.y, y[j], c3.z));
-                    M[j] = fmaxf(fmaxf(M[j], m0), m1);
-                    M[j] = fmaxf(fmaxf(M[j], m2), m3);
-                }
-            }
+            // inside: M < -E; undecided: !(|M| > E) (E >= 0; a NaN margin
+            // or band is undecided); lanes past the end or holding a
+            // non-finite point are masked only in waves that have any
             uint64_t inm[kP32];
             uint64_t any_unc = 0;
 #pragma unroll
             for (int j = 0; j < kP32; ++j) {
-                const uint64_t in = __ballot(M[j] < -E) & live[j];
-                const uint64_t out = __ballot(M[j] > E);
-                inm[j] = in;
-                any_unc |= ~(in | out) & live[j];
+                inm[j] = __ballot(M[j] < -E);
+                any_unc |= __ballot(!(fabsf(M[j]) > E));
+            }
+            if (!all_live) {
+                any_unc = 0;
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    inm[j] &= live[j];
+                    any_unc |= __ballot(!(fabsf(M[j]) > E)) & live[j];
+                }
             }
             if (any_unc) {  // rare: re-decide in binary64 (Algorithm 5)
                 const double2* G = gen + k * (n + 1);
@@ -251,7 +362,16 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
                     const uint64_t unc = ~(inm[j] | __ballot(M[j] > E)) & live[j];
                     if (unc) {
                         bool r = false;
-                        if ((unc >> lane) & 1ull) r = voronoi64((double)x[j], (double)y[j], G, n);
+                        if ((unc >> lane) & 1ull) {
+                            // the empty asm keeps the conversions here: hoisted
+                            // out of the polygon loop they would hold 16
+                            // binary64 values in registers for this rare path
+                            float px = x[j], py = y[j];
+#if defined(__HIP_DEVICE_COMPILE__)
+                            asm volatile("" : "+v"(px), "+v"(py));
+#endif
+                            r = voronoi64((double)px, (double)py, G, n);
+                        }
                         inm[j] = (inm[j] & ~unc) | (__ballot(r) & unc);
                     }
                 }
@@ -304,7 +424,7 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
 
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws, int cull,
-                           hipStream_t stream) {
+                           int pair, hipStream_t stream) {
     AllpairsLayout L;
     allpairs_workspace_layout(P, n, &L);
     char* b = static_cast<char*>(ws);
@@ -313,21 +433,19 @@ hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, in
     double2* gen = reinterpret_cast<double2*>(b + L.gen);
     const unsigned pblocks = (unsigned)((P + kWavesPerBlock - 1) / kWavesPerBlock);
     hipLaunchKernelGGL(k_prepare_uniform, dim3(pblocks), dim3(kBlock), 0, stream, P, n, V, hdr,
-                       coef, gen, status, counts);
+                       coef, gen, status, counts, pair);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (m == 0) return hipSuccess;
     const int pg = allpairs_group(n);
     const int n4 = (n + 3) & ~3;
     dim3 grid((unsigned)((m + kTilePoints - 1) / kTilePoints), (unsigned)((P + pg - 1) / pg));
-    if (cull)
-        hipLaunchKernelGGL(k_allpairs<true>, grid, dim3(kBlock), (size_t)pg * n4 * 16, stream, hdr,
-                           coef, gen, P, n, pg, reinterpret_cast<const float2*>(Q), m, labels,
-                           counts);
-    else
-        hipLaunchKernelGGL(k_allpairs<false>, grid, dim3(kBlock), (size_t)pg * n4 * 16, stream,
-                           hdr, coef, gen, P, n, pg, reinterpret_cast<const float2*>(Q), m, labels,
-                           counts);
+    const size_t lds = (size_t)pg * n4 * 16;
+    const float2* Q2 = reinterpret_cast<const float2*>(Q);
+    auto kern = cull ? (pair ? k_allpairs<true, true> : k_allpairs<true, false>)
+                     : (pair ? k_allpairs<false, true> : k_allpairs<false, false>);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), lds, stream, hdr, coef, gen, P, n, pg, Q2, m,
+                       labels, counts);
     return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ struct pip_ctx_s {
     int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
     int allpairs_cull = 0;         // skip (polygon, wave) pairs whose bounding disk misses the points
     int cost_cull = 0;             // skip (pose, wave) pairs of the collision cost likewise
+    int allpairs_pair = 0;         // antipodal edge pairs for centrally symmetric polygons
 };
 
 // A plan: one batched request bound to its buffers, its own workspace, the
@@ -625,7 +626,8 @@ pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double*
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_allpairs(P, n, V, Q, m, labels, counts, status, workspace,
-                                           ctx->allpairs_cull, stream);
+                                           ctx->allpairs_cull,
+                                           ctx->allpairs_pair, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -718,6 +720,11 @@ pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
             if (value != 0 && value != 1) return fail(PIP_EINVAL, "PIP_OPT_COST_CULL must be 0 or 1");
             ctx->cost_cull = (int)value;
             return PIP_OK;
+        case PIP_OPT_ALLPAIRS_PAIR:
+            if (value != 0 && value != 1)
+                return fail(PIP_EINVAL, "PIP_OPT_ALLPAIRS_PAIR must be 0 or 1");
+            ctx->allpairs_pair = (int)value;
+            return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
@@ -733,6 +740,9 @@ pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
             return PIP_OK;
         case PIP_OPT_COST_CULL:
             *value = ctx->cost_cull;
+            return PIP_OK;
+        case PIP_OPT_ALLPAIRS_PAIR:
+            *value = ctx->allpairs_pair;
             return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);

@@ -34,7 +34,8 @@ struct alignas(16) PolyHdr {
     int n, n4;             // edges (0 for an invalid polygon), padded to 4
     int status;            // pip_status of this polygon
     float cx, cy, rad;     // disk (float32 centre, radius rounded up) containing the polygon
-    int pad[4];
+    int npair;             // > 0: coefficient rows are npair antipodal edge pairs (all pairs)
+    int pad[3];
 };
 
 // Device view of a batched request plus its workspace.
@@ -77,7 +78,7 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
                                     int64_t K, double* Wout, hipStream_t stream);
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws, int cull,
-                           hipStream_t stream);
+                           int pair, hipStream_t stream);
 struct CostLayout {
     size_t tab, part_cost, part_pose, part_gen, stage;
     int T;

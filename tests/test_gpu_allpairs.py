@@ -169,3 +169,112 @@ def test_allpairs_cull_adversarial_identical(P, oracle):
     assert np.array_equal(lab0, bits) and np.array_equal(cnt0, counts)
     assert np.array_equal(lab1, bits) and np.array_equal(cnt1, counts)
     say(f"[stat] adversarial cull: {int(counts.sum())} inside pairs of {K * len(Q)}")
+
+
+def _allpairs_opts(P, F, poses, cs, Q, cull, pair):
+    """Placed footprints through pip_voronoi_allpairs with the given options;
+    also returns the pair count each polygon's table was built with (the
+    int32 at byte 48 of its 64-byte workspace header)."""
+    Ft = torch.from_numpy(F).cuda()
+    Vw = P.pip_poses_to_polygons(Ft, torch.from_numpy(poses).cuda(), torch.from_numpy(cs).cuda())
+    need = P.allpairs_workspace_bytes(Vw.shape[0], Vw.shape[1])
+    ws = torch.zeros(max(need, 256), dtype=torch.uint8, device="cuda")
+    P.set_option(P.PIP_OPT_ALLPAIRS_CULL, cull)
+    P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, pair)
+    try:
+        lab, cnt, _ = P.pip_voronoi_allpairs(Vw, torch.from_numpy(Q).cuda(), workspace=ws)
+        torch.cuda.synchronize()
+    finally:
+        P.set_option(P.PIP_OPT_ALLPAIRS_CULL, 0)
+        P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, 0)
+    npair = ws[: 64 * Vw.shape[0]].cpu().numpy().view(np.int32).reshape(-1, 16)[:, 12]
+    return lab.cpu().numpy().view(np.uint32), cnt.cpu().numpy(), npair
+
+
+def test_allpairs_pair_full_size(P, oracle):
+    """Antipodal pairing (alone and with culling) on the 2048-pose x 131,072
+    lidar configuration: every placed car footprint is paired (4 pairs) and
+    every label and count equals the oracle's."""
+    F = W.car_footprint()
+    Q = W.lidar_cloud()
+    poses, cs = W.random_poses()
+    say("[case] all pairs paired full size: GPU")
+    lab1, cnt1, np1 = _allpairs_opts(P, F, poses, cs, Q, 0, 1)
+    lab2, cnt2, np2 = _allpairs_opts(P, F, poses, cs, Q, 1, 1)
+    assert (np1 == 4).all() and (np2 == 4).all()
+    say("[case] all pairs paired full size: oracle")
+    bits, counts = oracle.allpairs(F, poses[:, :2].astype(np.float64), cs, Q.astype(np.float64))
+    assert np.array_equal(lab1, bits) and np.array_equal(cnt1, counts)
+    assert np.array_equal(lab2, bits) and np.array_equal(cnt2, counts)
+
+
+@pytest.mark.parametrize("cull", [0, 1])
+def test_allpairs_pair_adversarial(P, oracle, cull):
+    """Pairing near the band: points on the placed edges, at vertices and
+    within 1e-12 .. 1e-6 of edges, poses at up to 40 m (paired), at 1e3 m
+    (the binary64 centroid's rounding leaves an asymmetry near the pairing
+    limit) and at 1e5 m (far past it: per-edge table)."""
+    rng = np.random.default_rng(31 + cull)
+    F = W.car_footprint()
+    poses, cs = W.random_poses(64, extent=40.0)
+    poses[-16:-8, :2] = (1.0e3 + rng.uniform(-3, 3, size=(8, 2))).astype(np.float32)
+    poses[-8:, :2] = (1.0e5 + rng.uniform(-3, 3, size=(8, 2))).astype(np.float32)
+    pts = []
+    for k in range(0, 64, 2):
+        Wk = oracle.pose_polygon(F, float(poses[k, 0]), float(poses[k, 1]), cs[k, 0], cs[k, 1])
+        Wr = np.roll(Wk, 1, 0)
+        e = Wk - Wr
+        L = np.hypot(e[:, 0], e[:, 1])
+        for off in (0.0, 1e-12, -1e-9, 1e-7, -1e-6):
+            i = rng.integers(8, size=24)
+            t = rng.random(24)
+            pts.append(np.stack([Wr[i, 0] + t * e[i, 0] + off * e[i, 1] / L[i],
+                                 Wr[i, 1] + t * e[i, 1] - off * e[i, 0] / L[i]], 1))
+        pts.append(Wk)
+    Q = np.concatenate(pts).astype(np.float32)
+    lab, cnt, npair = _allpairs_opts(P, F, poses, cs, Q, cull, 1)
+    assert (npair[:48] == 4).all() and (npair[-8:] == 0).all()
+    bits, counts = oracle.allpairs(F, poses[:, :2].astype(np.float64), cs, Q.astype(np.float64))
+    assert np.array_equal(lab, bits)
+    assert np.array_equal(cnt, counts)
+    say(f"[stat] paired adversarial (cull {cull}): {int(counts.sum())} inside pairs, "
+        f"pairs at 1e3 m: {npair[-16:-8].tolist()}")
+
+
+@pytest.mark.parametrize("n,expect", [(4, 2), (6, 3), (16, 8), (64, 32), (7, 0)])
+def test_allpairs_pair_regular_and_fallback(P, oracle, n, expect):
+    """Regular polygons (centrally symmetric for even n: n/2 pairs, padded
+    rows for n/2 not a multiple of 4), an odd n and a perturbed even polygon
+    (both keep the per-edge table): labels equal the oracle's either way."""
+    from oracle import pack_bits
+    rng = np.random.default_rng(n)
+    ang = 2 * np.pi * np.arange(n) / n + 0.3
+    base = np.stack([1.7 * np.cos(ang), 1.7 * np.sin(ang)], 1)
+    polys = [base + c for c in rng.uniform(-30, 30, size=(12, 2))]
+    if n % 2 == 0:
+        bent = base.copy()
+        bent[0] *= 1.0 + 1e-4  # no longer symmetric
+        polys.append(bent + 2.0)
+    V = np.stack(polys).astype(np.float64)
+    Q = np.concatenate([rng.uniform(-33, 33, size=(4000, 2))] +
+                       [p[rng.integers(n, size=64)] + rng.normal(0, 1e-6, (64, 2)) for p in polys])
+    Q = Q.astype(np.float32)
+    need = P.allpairs_workspace_bytes(V.shape[0], n)
+    ws = torch.zeros(max(need, 256), dtype=torch.uint8, device="cuda")
+    P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, 1)
+    try:
+        lab, cnt, _ = P.pip_voronoi_allpairs(torch.from_numpy(V).cuda(), torch.from_numpy(Q).cuda(),
+                                             workspace=ws)
+        torch.cuda.synchronize()
+    finally:
+        P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, 0)
+    npair = ws[: 64 * V.shape[0]].cpu().numpy().view(np.int32).reshape(-1, 16)[:, 12]
+    assert (npair[:12] == expect).all()
+    if n % 2 == 0:
+        assert npair[12] == 0
+    lab = lab.cpu().numpy().view(np.uint32)
+    cnt = cnt.cpu().numpy()
+    for k in range(len(V)):
+        want = oracle.voronoi(V[k], Q.astype(np.float64))
+        assert np.array_equal(lab[k], pack_bits(want)), k
+        assert int(cnt[k]) == int(want.sum())

@@ -319,4 +319,8 @@ def test_ray_crossing_nonconvex(P, oracle, qdt):
         assert st == [0]
         want = oracle.ray_crossing(V, Q.astype(np.float64))
         assert_same(got, pack_bits(want), len(Q), "ray_crossing")
-        assert 0.2 < want.mean() < 0.8
+        # the inside fraction of the uniform part matches the polygon's area
+        x, y = V[:, 0], V[:, 1]
+        area = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1)))
+        frac = want[:200_000].mean()
+        assert abs(frac - area / np.prod(hi - lo)) < 0.01, (frac, area / np.prod(hi - lo))
