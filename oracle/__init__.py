@@ -55,6 +55,9 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "oracle_generators": (ctypes.c_int, [_D, _i64, _D]),
         "oracle_voronoi": (ctypes.c_int, [_D, _i64, _D, _i64, _U8]),
         "oracle_voronoi_with_generators": (None, [_D, _i64, _D, _i64, _U8]),
+        "oracle_voronoi_raster": (ctypes.c_int, [_D, _i64, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_double, _i64, _i64,
+                                                 _U8]),
         "oracle_voronoi_max_margin": (None, [_D, _i64, _D, _i64, _D]),
         "oracle_sign_of_offset": (None, [_D, _i64, _D, _i64, _U8]),
         "oracle_ray_crossing": (None, [_D, _i64, _D, _i64, _U8]),
@@ -132,6 +135,14 @@ class Oracle:
         Q = _f64(Q).reshape(-1, 2)
         out = np.zeros(len(Q), dtype=np.uint8)
         self.lib.oracle_voronoi(_p(V), len(V), _p(Q), len(Q), _p(out, _U8))
+        return out.astype(bool)
+
+    def voronoi_raster(self, V, x0, y0, dx, dy, width, height) -> np.ndarray:
+        """[height, width] bool: pixel (i, j) is the point (x0 + i dx, y0 + j dy)."""
+        V = _f64(V).reshape(-1, 2)
+        out = np.zeros((height, width), dtype=np.uint8)
+        self.lib.oracle_voronoi_raster(_p(V), len(V), float(x0), float(y0), float(dx), float(dy),
+                                       int(width), int(height), _p(out, _U8))
         return out.astype(bool)
 
     def voronoi_with_generators(self, P, Q) -> np.ndarray:

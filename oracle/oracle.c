@@ -163,6 +163,37 @@ int oracle_voronoi(const double *V, int64_t n, const double *Q, int64_t m, uint8
 }
 
 /*
+ * Coverage raster (the graphics use of Section 1: every pixel's membership
+ * decided by a point inclusion test).  Pixel (i, j) of a width x height grid
+ * stands for the point (x0 + i*dx, y0 + j*dy), each coordinate one binary64
+ * product and one binary64 sum; isin[j*width + i] is that point's Voronoi
+ * label (Algorithm 5), row by row.
+ */
+int oracle_voronoi_raster(const double *V, int64_t n, double x0, double y0, double dx, double dy,
+                          int64_t width, int64_t height, uint8_t *isin)
+{
+    double *P = (double *)malloc(sizeof(double) * 2 * (size_t)(n + 1));
+    if (!P) return -100;
+    int rc = oracle_generators(V, n, P);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < height; ++j) {
+        double py = y0 + (double)j * dy;
+        for (int64_t i = 0; i < width; ++i) {
+            double px = x0 + (double)i * dx;
+            double M0 = sqdist(px, py, P[0], P[1]);
+            int in = isfinite(px) && isfinite(py);
+            for (int64_t e = 0; e < n; ++e) {
+                double Me = sqdist(px, py, P[2 * (e + 1)], P[2 * (e + 1) + 1]);
+                if (!(M0 <= Me)) in = 0;
+            }
+            isin[j * width + i] = (uint8_t)in;
+        }
+    }
+    free(P);
+    return rc;
+}
+
+/*
  * Same test with the generators given (P as produced above); used for
  * batched and all-pairs work where the generators are derived once.
  */

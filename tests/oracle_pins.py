@@ -322,6 +322,44 @@ def pin_allpairs(o):
         assert np.array_equal(bits[k], pack_bits(lab))
 
 
+def pin_raster_exact(o):
+    """Dyadic raster of the rectangle [0,1] x [0,1/2]: exactly the pixels of
+    the closed rectangle (fixture worked by hand), in either orientation."""
+    g = golden("raster_unit_square.json")
+    V = np.array(g["vertices_ccw"], dtype=float)
+    r = g["raster"]
+    (c0, c1), (r0, r1) = g["inside_columns"], g["inside_rows"]
+    want = np.zeros((r["height"], r["width"]), dtype=bool)
+    want[r0:r1 + 1, c0:c1 + 1] = True
+    assert int(want.sum()) == g["inside_count"]
+    for VV in (V, V[::-1].copy()):
+        got = o.voronoi_raster(VV, r["x0"], r["y0"], r["dx"], r["dy"], r["width"], r["height"])
+        assert np.array_equal(got, want)
+
+
+def pin_raster_area(o):
+    """Coverage of a regular heptagon and a triangle on non-square rasters:
+    pixel count times pixel area is the polygon's area (closed form) within
+    the cells the boundary crosses, perimeter (dx + dy) + 4 dx dy; and the
+    raster equals the labels of its pixel points formed here row by row."""
+    cases = ((7, 1.0, (0.3, -0.2), 301, 257), (3, 2.5, (-4.0, 7.0), 190, 333))
+    for n, R, c, width, height in cases:
+        th = 2 * math.pi * np.arange(n) / n + 0.1
+        V = np.stack([c[0] + R * np.cos(th), c[1] + R * np.sin(th)], 1)
+        x0, y0 = c[0] - 1.3 * R, c[1] - 1.2 * R
+        dx, dy = 2.6 * R / (width - 1), 2.4 * R / (height - 1)
+        got = o.voronoi_raster(V, x0, y0, dx, dy, width, height)
+        assert got.shape == (height, width)
+        area = 0.5 * n * R * R * math.sin(2 * math.pi / n)
+        per = n * 2 * R * math.sin(math.pi / n)
+        assert abs(got.sum() * dx * dy - area) <= per * (dx + dy) + 4 * dx * dy
+        px = x0 + np.arange(width) * dx
+        py = y0 + np.arange(height) * dy
+        X, Y = np.meshgrid(px, py)              # [height, width], row j holds y_j
+        Q = np.stack([X.reshape(-1), Y.reshape(-1)], 1)
+        assert np.array_equal(got.reshape(-1), o.voronoi(V, Q))
+
+
 def _min_edge_dist(V, Q):
     Wv = np.roll(V, 1, 0)
     e = V - Wv
@@ -452,6 +490,8 @@ def pin_cost_hash(o):
 
 ALL_PINS = [
     pin_square_and_triangle,
+    pin_raster_exact,
+    pin_raster_area,
     pin_regular_ngon,
     pin_generators_exact_rational,
     pin_generator_invariants,

@@ -39,6 +39,9 @@ MUTANTS = [
     ("ray_in_range_closed", "int in_range = (V[2 * i + 1] > py) != (V[2 * j + 1] > py);",
      "int in_range = (V[2 * i + 1] >= py) != (V[2 * j + 1] > py);"),
     ("pose_rotation_sign", "W[2 * i] = (c * vx - s * vy) + tx;", "W[2 * i] = (c * vx + s * vy) + tx;"),
+    ("raster_transposed", "isin[j * width + i] = (uint8_t)in;", "isin[i * height + j] = (uint8_t)in;"),
+    ("raster_row_offset", "double py = y0 + (double)j * dy;", "double py = y0 + (double)(j + 1) * dy;"),
+    ("raster_x_step", "double px = x0 + (double)i * dx;", "double px = x0 + (double)i * dy;"),
     ("allpairs_bit_order", "row[j >> 5] |= (uint32_t)1u << (j & 31);",
      "row[j >> 5] |= (uint32_t)1u << (31 - (j & 31));"),
     ("cost_body_frame_sign", "double by = (-s) * dx + c * dy;\n        double best = 0.0;",
