@@ -239,6 +239,31 @@ def run_extras(P, W, torch, stream, check):
                     "labels_and_counts_equal_dense": same}
     print("[bench] all pairs done", file=sys.stderr, flush=True)
 
+    # coverage raster: 16384 x 16384 pixel points generated in the kernel
+    # (no point array read: bound by the vector units)
+    N = 16384
+    rast = {"width": N, "height": N, "extent": [-1.5, 1.5]}
+    for n in (8, 64):
+        rr = np.random.default_rng(2007153852 + n)
+        Vr = W.circle_polygon(n, 1.0, rr.uniform(-0.1, 0.1, 2), rr)
+        Vrt = torch.from_numpy(Vr).to(dev)
+        lab_r = P.pip_voronoi_raster(Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N)
+        ms_r = _time(torch, stream, lambda: P.pip_voronoi_raster(
+            Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N, labels=lab_r), reps=10)
+        tfl = 4.0 * n * N * N / (ms_r * 1e-3) / 1e12
+        e = {"ms": round(ms_r, 4), "gpixels_per_s": round(N * N / ms_r / 1e6, 1),
+             "fp32_tflops": round(tfl, 2), "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)}
+        if check:
+            rows = np.sort(rr.choice(N, 64, replace=False))
+            got = lab_r.cpu().numpy().view(np.uint32)[rows]
+            want = np.stack([np.packbits(o.voronoi_raster(Vr, -1.5, -1.5 + int(j) * (3.0 / N),
+                                                          3.0 / N, 3.0 / N, N, 1)[0],
+                                         bitorder="little").view(np.uint32) for j in rows])
+            e["mismatches_64_rows"] = int(np.unpackbits((got ^ want).view(np.uint8)).sum())
+        rast[f"n{n}"] = e
+    out["raster"] = rast
+    print("[bench] raster done", file=sys.stderr, flush=True)
+
     # differentiable cost: 1024 trajectories x 64 poses x 65,536 points
     F32 = F.astype(np.float32)
     Qd = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)

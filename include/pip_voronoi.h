@@ -178,6 +178,22 @@ pip_status pip_voronoi_max_margin(pip_ctx ctx, const double *V, int32_t n, const
                                   pip_dtype qdt, int64_t m, float *max_margin, int32_t *status,
                                   hipStream_t stream);
 
+/* Coverage raster (Section 1's graphics use: every pixel's membership by a
+ * point inclusion test; Section 4, Algorithm 5 per pixel).  Pixel (i, j),
+ * 0 <= i < width, 0 <= j < height, is the binary64 point
+ * (x0 + i*dx, y0 + j*dy), each coordinate one product and one sum, rounded to
+ * nearest; no point array is read.  labels (device, caller-owned) holds
+ * height rows of ceil(width / 32) uint32 words: bit i % 32 of word
+ * j * ceil(width / 32) + i / 32 is 1 iff pixel (i, j) is inside, equal to the
+ * plain binary64 algorithm; bits past width are 0.  status as in
+ * pip_voronoi.  Errors: PIP_EINVAL for a bad polygon argument, a non-finite
+ * x0, y0, dx or dy, a negative size, a NULL or misaligned labels;
+ * PIP_EUNSUPPORTED for width > 2^24 or height > 2^31.  width or height 0
+ * writes no label (status is still written when given). */
+pip_status pip_voronoi_raster(pip_ctx ctx, const double *V, int32_t n, double x0, double y0,
+                              double dx, double dy, int64_t width, int64_t height,
+                              uint32_t *labels, int32_t *status, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Batched Voronoi inclusion: P convex polygons, each against its own point
  * set, in one persistent launch (Section 4, Algorithm 5 per polygon; the

@@ -159,6 +159,27 @@ def pip_voronoi_max_margin(V, Q, out=None, status=None):
     return out[:m]
 
 
+def pip_voronoi_raster(V, x0, y0, dx, dy, width, height, labels=None, status=None):
+    """Coverage raster of one convex polygon: pixel (i, j) is the binary64
+    point (x0 + i dx, y0 + j dy).  Returns labels [height, ceil(width/32)]
+    int32, bit i % 32 of word i // 32 of row j = pixel (i, j) inside."""
+    V = _polygon(V)
+    d = _dev(V)
+    width, height = int(width), int(height)
+    rw = num_label_words(width)
+    if labels is None:
+        labels = torch.empty((max(height, 1), max(rw, 1)), dtype=torch.int32, device=V.device)
+    elif labels.numel() < height * rw or not labels.is_contiguous():
+        raise ValueError(f"labels must be a contiguous int32 tensor of >= {height * rw} words")
+    st = _status_buf(status, d)
+    ctx = context(d)
+    s = _lib().pip_voronoi_raster(ctx, V.data_ptr(), V.shape[0], float(x0), float(y0), float(dx),
+                                  float(dy), width, height, labels.data_ptr(),
+                                  st.data_ptr() if st is not None else None, _stream(d))
+    _check(s, "pip_voronoi_raster", ctx)
+    return labels[:height, :rw] if labels.dim() == 2 else labels
+
+
 def unpack_labels(words: torch.Tensor, m: int) -> torch.Tensor:
     """Packed int32 words -> bool tensor of m labels (same device)."""
     w = words.contiguous().view(torch.uint8)

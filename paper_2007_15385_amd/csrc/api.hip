@@ -3,6 +3,7 @@
 // a label; every step of the test runs in the HIP kernels.
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <mutex>
 #include <string>
 
@@ -15,6 +16,7 @@ struct pip_ctx_s {
     std::mutex mu;
     int stream_blocks[8][2] = {};  // cached persistent grid per (kind, dtype); 0 = unknown
     int mfma_blocks[2][4] = {};    // same for the matrix-core screen (kind, edge bucket)
+    int raster_blocks = 0;         // persistent grid of the raster kernel
     int batched_blocks_per_cu = 0;
     int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
     int allpairs_cull = 0;         // skip (polygon, wave) pairs whose bounding disk misses the points
@@ -256,6 +258,43 @@ pip_status pip_voronoi_max_margin(pip_ctx ctx, const double* V, int32_t n, const
                                   pip_dtype qdt, int64_t m, float* max_margin, int32_t* status,
                                   hipStream_t stream) {
     return run_stream(ctx, pipdev::K_MARGIN, V, n, Q, qdt, m, nullptr, max_margin, status, stream);
+}
+
+pip_status pip_voronoi_raster(pip_ctx ctx, const double* V, int32_t n, double x0, double y0,
+                              double dx, double dy, int64_t width, int64_t height,
+                              uint32_t* labels, int32_t* status, hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    pip_status s = check_polygon(V, n);
+    if (s != PIP_OK) return s;
+    if (!std::isfinite(x0) || !std::isfinite(y0) || !std::isfinite(dx) || !std::isfinite(dy))
+        return fail(PIP_EINVAL, "x0, y0, dx and dy must be finite");
+    if (width < 0 || height < 0)
+        return fail(PIP_EINVAL, "width = %lld, height = %lld: negative size", (long long)width,
+                    (long long)height);
+    if (width > (int64_t(1) << 24) || height > (int64_t(1) << 31))
+        return fail(PIP_EUNSUPPORTED, "raster %lld x %lld exceeds 2^24 columns or 2^31 rows",
+                    (long long)width, (long long)height);
+    const bool empty = width == 0 || height == 0;
+    if (!empty && !labels) return fail(PIP_EINVAL, "labels is NULL");
+    if (!empty && !aligned(labels, 4)) return fail(PIP_EINVAL, "labels is not 4-byte aligned");
+    if (status && !aligned(status, 4)) return fail(PIP_EINVAL, "status is not 4-byte aligned");
+    if (empty && !status) return PIP_OK;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    int blocks;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (ctx->raster_blocks == 0) {
+            int per_cu = 0;
+            if (pipdev::raster_max_blocks_per_cu(&per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+            ctx->raster_blocks = per_cu * ctx->cu_count;
+        }
+        blocks = ctx->raster_blocks;
+    }
+    pipdev::RasterGrid G{x0, y0, dx, dy, empty ? 0 : width, empty ? 0 : height};
+    hipError_t e = pipdev::launch_raster(V, n, G, labels, status, blocks, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
 }
 
 

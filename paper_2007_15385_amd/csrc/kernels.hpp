@@ -79,6 +79,14 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws, int cull,
                            int pair, hipStream_t stream);
+// Coverage raster: pixel (i, j) = (x0 + i dx, y0 + j dy), binary64.
+struct RasterGrid {
+    double x0, y0, dx, dy;
+    int64_t width, height;
+};
+hipError_t launch_raster(const double* V, int n, const RasterGrid& G, uint32_t* labels,
+                         int32_t* status, int max_blocks, hipStream_t stream);
+hipError_t raster_max_blocks_per_cu(int* out);
 struct CostLayout {
     size_t tab, part_cost, part_pose, part_gen, stage;
     int T;

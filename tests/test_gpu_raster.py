@@ -1,0 +1,137 @@
+"""GPU parity of the coverage raster against the FP64 oracle: every pixel
+label bit-identical, on ragged widths, pixel points exactly on edges and
+vertices, rasters far from the origin, degenerate polygons and the full
+16384 x 16384 raster."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import pack_bits
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_15385_amd as P
+    P.load_library()
+    return P
+
+
+def raster_gpu(P, V, x0, y0, dx, dy, width, height, status=None):
+    Vt = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64)).cuda()
+    st = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    lab = P.pip_voronoi_raster(Vt, x0, y0, dx, dy, width, height, status=st)
+    torch.cuda.synchronize()
+    if status is not None:
+        status.append(int(st.item()))
+    return lab.cpu().numpy().view(np.uint32)
+
+
+def raster_want(oracle, V, x0, y0, dx, dy, width, height):
+    img = oracle.voronoi_raster(V, x0, y0, dx, dy, width, height)
+    return np.stack([pack_bits(r) for r in img]) if height else np.zeros((0, (width + 31) // 32),
+                                                                           np.uint32)
+
+
+def check(P, oracle, V, x0, y0, dx, dy, width, height, tag=""):
+    say(f"[case] raster {tag} n={len(V)} {width}x{height}")
+    got = raster_gpu(P, V, x0, y0, dx, dy, width, height)
+    want = raster_want(oracle, V, x0, y0, dx, dy, width, height)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    bad = np.nonzero(got != want)
+    assert len(bad[0]) == 0, f"{tag}: {len(bad[0])} words differ, first at {bad[0][:5]}, {bad[1][:5]}"
+    return want
+
+
+def test_raster_hand_worked(P, oracle):
+    """The dyadic raster of the rectangle [0,1] x [0,1/2]: 45 pixels, both
+    orientations."""
+    V = np.array([[0, 0], [1, 0], [1, 0.5], [0, 0.5]], float)
+    for VV in (V, V[::-1].copy()):
+        want = check(P, oracle, VV, -0.5, -0.5, 0.125, 0.125, 17, 9, "hand-worked")
+        assert int(np.unpackbits(want.view(np.uint8)).sum()) == 45
+
+
+@pytest.mark.parametrize("n", [3, 8, 17, 64])
+def test_raster_ragged_widths(P, oracle, n):
+    rng = np.random.default_rng(100 + n)
+    V = W.circle_polygon(n, 1.0, rng.uniform(-0.1, 0.1, 2), rng)
+    for width in (1, 31, 32, 33, 511, 512, 513, 1000, 1537):
+        height = int(rng.integers(1, 8))
+        dx, dy = 3.0 / width, 3.0 / height
+        check(P, oracle, V, -1.5, -1.5, dx, dy, width, height, f"ragged w={width}")
+
+
+def test_raster_points_on_edges_and_vertices(P, oracle):
+    """Pixels exactly on edges and vertices: a grid-aligned rectangle and
+    triangle whose vertices are pixel points (whole rows and columns lie on
+    edges, so the binary64 recheck decides them), and a mirrored raster
+    (negative steps)."""
+    V = np.array([[1.0, 1.0], [6.0, 1.0], [6.0, 4.0], [1.0, 4.0]])
+    check(P, oracle, V, 0.0, 0.0, 0.25, 0.25, 40, 24, "aligned rectangle")
+    check(P, oracle, V, 8.0, 6.0, -0.25, -0.25, 40, 24, "mirrored")
+    T = np.array([[0.0, 0.0], [8.0, 0.0], [0.0, 6.0]])
+    check(P, oracle, T, -1.0, -1.0, 0.125, 0.125, 1100, 70, "aligned triangle")
+
+
+@pytest.mark.parametrize("centre", [1000.0, -1.0e5])
+def test_raster_far_from_origin(P, oracle, centre):
+    rng = np.random.default_rng(7)
+    for n in (4, 9, 32):
+        V = W.circle_polygon(n, 7.5, (centre, 0.5 * centre), rng)
+        x0, y0 = centre - 9.0, 0.5 * centre - 9.0
+        check(P, oracle, V, x0, y0, 18.0 / 777, 18.0 / 61, 777, 61, f"far {centre}")
+
+
+def test_raster_degenerate_and_status(P, oracle):
+    cases = [
+        (np.array([[0, 0], [1, 0], [2, 0]], float), 2),            # zero area
+        (np.array([[0, 0], [2, 0], [1, 0.2], [1, 2]], float), 3),  # non-convex
+    ]
+    for V, code in cases:
+        st = []
+        got = raster_gpu(P, V, -0.5, -0.5, 0.05, 0.05, 70, 50, status=st)
+        assert st == [code]
+        assert np.array_equal(got, raster_want(oracle, V, -0.5, -0.5, 0.05, 0.05, 70, 50))
+
+
+def test_raster_empty_and_errors(P):
+    V = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+    st = []
+    lab = raster_gpu(P, V, 0.0, 0.0, 0.1, 0.1, 0, 5, status=st)
+    assert lab.size == 0 and st == [0]
+    lab = raster_gpu(P, V, 0.0, 0.0, 0.1, 0.1, 10, 0, status=st)
+    assert lab.size == 0
+    Vt = torch.from_numpy(V).cuda()
+    with pytest.raises(P.PipError):
+        P.pip_voronoi_raster(Vt, float("nan"), 0.0, 0.1, 0.1, 8, 8)
+    with pytest.raises(P.PipError):
+        P.pip_voronoi_raster(Vt, 0.0, 0.0, 0.1, 0.1, (1 << 24) + 1, 1)
+
+
+def test_raster_full_size(P, oracle):
+    """16384 x 16384 pixels over [-1.5, 1.5)^2 against an 8-gon of radius 1
+    (the streaming workload's polygon shape): every label word."""
+    rng = np.random.default_rng(2007153852)
+    V = W.circle_polygon(8, 1.0, rng.uniform(-0.1, 0.1, 2), rng)
+    N = 16384
+    say("[case] raster full size: GPU")
+    got = raster_gpu(P, V, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N)
+    say("[case] raster full size: oracle")
+    img = oracle.voronoi_raster(V, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N)
+    want = np.packbits(img, axis=1, bitorder="little").view(np.uint32)
+    bad = int((got != want).sum())
+    say(f"[stat] raster: {int(img.sum())} inside pixels, {bad} words differ")
+    assert bad == 0
