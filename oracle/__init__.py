@@ -55,6 +55,7 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "oracle_generators": (ctypes.c_int, [_D, _i64, _D]),
         "oracle_voronoi": (ctypes.c_int, [_D, _i64, _D, _i64, _U8]),
         "oracle_voronoi_with_generators": (None, [_D, _i64, _D, _i64, _U8]),
+        "oracle_locate": (ctypes.c_int, [_I64, _i64, _D, _D, _i64, _I32]),
         "oracle_voronoi_raster": (ctypes.c_int, [_D, _i64, ctypes.c_double, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_double, _i64, _i64,
                                                  _U8]),
@@ -144,6 +145,19 @@ class Oracle:
         self.lib.oracle_voronoi_raster(_p(V), len(V), float(x0), float(y0), float(dx), float(dy),
                                        int(width), int(height), _p(out, _U8))
         return out.astype(bool)
+
+    def locate(self, vtx_off, V, Q) -> np.ndarray:
+        """[m] int32: smallest k whose polygon V[vtx_off[k]:vtx_off[k+1]]
+        contains point j (Voronoi test), or -1."""
+        off = np.ascontiguousarray(vtx_off, dtype=np.int64)
+        V = _f64(V).reshape(-1, 2)
+        Q = _f64(Q).reshape(-1, 2)
+        ids = np.zeros(len(Q), dtype=np.int32)
+        rc = self.lib.oracle_locate(_p(off, _I64), len(off) - 1, _p(V), _p(Q), len(Q),
+                                    _p(ids, _I32))
+        if rc != 0:
+            raise MemoryError("oracle_locate")
+        return ids
 
     def voronoi_with_generators(self, P, Q) -> np.ndarray:
         P = _f64(P).reshape(-1, 2)

@@ -194,6 +194,45 @@ int oracle_voronoi_raster(const double *V, int64_t n, double x0, double y0, doub
 }
 
 /*
+ * Point location in a stored set of polygons (the GIS use of Section 1, with
+ * the generators of constant polygons derived once and kept beside the
+ * vertices, Section 7).  Polygon k has vertices V[vtx_off[k] .. vtx_off[k+1]);
+ * ids[j] is the smallest k whose Voronoi test (Algorithm 5) puts point j
+ * inside, or -1.  Polygons with fewer than 3 vertices contain no point.
+ */
+int oracle_locate(const int64_t *vtx_off, int64_t P, const double *V, const double *Q, int64_t m,
+                  int32_t *ids)
+{
+    int64_t total = vtx_off[P];
+    double *G = (double *)malloc(sizeof(double) * 2 * (size_t)(total + P + 1));
+    if (!G) return -100;
+    for (int64_t k = 0; k < P; ++k) {
+        int64_t n = vtx_off[k + 1] - vtx_off[k];
+        if (n >= 3) oracle_generators(V + 2 * vtx_off[k], n, G + 2 * (vtx_off[k] + k));
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < m; ++j) {
+        double px = Q[2 * j], py = Q[2 * j + 1];
+        int32_t id = -1;
+        for (int64_t k = 0; k < P && id < 0; ++k) {
+            int64_t n = vtx_off[k + 1] - vtx_off[k];
+            if (n < 3) continue;
+            const double *Pk = G + 2 * (vtx_off[k] + k);
+            double M0 = sqdist(px, py, Pk[0], Pk[1]);
+            int in = isfinite(px) && isfinite(py);
+            for (int64_t i = 0; i < n; ++i) {
+                double Mi = sqdist(px, py, Pk[2 * (i + 1)], Pk[2 * (i + 1) + 1]);
+                if (!(M0 <= Mi)) in = 0;
+            }
+            if (in) id = (int32_t)k;
+        }
+        ids[j] = id;
+    }
+    free(G);
+    return 0;
+}
+
+/*
  * Same test with the generators given (P as produced above); used for
  * batched and all-pairs work where the generators are derived once.
  */

@@ -360,6 +360,56 @@ def pin_raster_area(o):
         assert np.array_equal(got.reshape(-1), o.voronoi(V, Q))
 
 
+def pin_locate_hand_worked(o):
+    """Four unit squares (fixture worked by hand): shared corners and edges go
+    to the smallest containing index, points outside to -1."""
+    g = golden("locate_2x2.json")
+    polys = [np.array(p, dtype=float) for p in g["polygons"]]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])])
+    ids = o.locate(off, np.concatenate(polys), np.array(g["points"], dtype=float))
+    assert ids.tolist() == g["ids"]
+    bad = o.locate(off, np.concatenate(polys), np.array([[np.nan, 1.0], [1.0, np.inf]]))
+    assert bad.tolist() == [-1, -1]
+
+
+def pin_locate_partition(o):
+    """A jittered partition into convex quads and triangles: points strictly
+    inside cell k (convex combinations of its vertices with weights >= 1e-3,
+    so at least ~1e-4 from every edge) locate to k, since cells have disjoint
+    interiors; points outside the domain locate to -1."""
+    rng = _rng(31)
+    part = W.jittered_partition(9, 7, cell=0.5, origin=(-3.0, 1.0), seed_salt=3)
+    off, V = part.vtx_off, part.V
+    pts, want = [], []
+    for k in range(len(off) - 1):
+        Pk = V[off[k]:off[k + 1]]
+        w = rng.uniform(1e-3, 1.0, size=(6, len(Pk)))
+        w /= w.sum(1, keepdims=True)
+        pts.append(w @ Pk)
+        want += [k] * 6
+    out = np.array([[part.lo[0] - 0.01, 2.0], [part.hi[0] + 0.3, 2.0], [0.0, part.hi[1] + 1.0],
+                    [0.0, part.lo[1] - 1e-3]])
+    ids = o.locate(off, V, np.concatenate(pts + [out]))
+    assert ids[:len(want)].tolist() == want
+    assert (ids[len(want):] == -1).all()
+
+
+def pin_locate_overlapping(o):
+    """Nested and overlapping polygons: the id is the smallest index whose
+    polygon contains the point (exact rational membership, points away from
+    edges), in either listing order."""
+    rng = _rng(32)
+    polys = [small_int_convex(rng, int(rng.integers(3, 9)), scale=12) for _ in range(14)]
+    Q = rng.uniform(-13, 13, size=(3000, 2))
+    ok = np.min([_min_edge_dist(p, Q) for p in polys], axis=0) > 1e-6
+    for order in (polys, polys[::-1]):
+        off = np.concatenate([[0], np.cumsum([len(p) for p in order])])
+        ids = o.locate(off, np.concatenate(order).astype(float), Q)
+        for j in np.nonzero(ok)[0][:600]:
+            inside = [k for k, p in enumerate(order) if exact.convex_contains(p.tolist(), Q[j].tolist())]
+            assert ids[j] == (inside[0] if inside else -1), j
+
+
 def _min_edge_dist(V, Q):
     Wv = np.roll(V, 1, 0)
     e = V - Wv
@@ -492,6 +542,9 @@ ALL_PINS = [
     pin_square_and_triangle,
     pin_raster_exact,
     pin_raster_area,
+    pin_locate_hand_worked,
+    pin_locate_partition,
+    pin_locate_overlapping,
     pin_regular_ngon,
     pin_generators_exact_rational,
     pin_generator_invariants,

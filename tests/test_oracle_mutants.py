@@ -42,6 +42,9 @@ MUTANTS = [
     ("raster_transposed", "isin[j * width + i] = (uint8_t)in;", "isin[i * height + j] = (uint8_t)in;"),
     ("raster_row_offset", "double py = y0 + (double)j * dy;", "double py = y0 + (double)(j + 1) * dy;"),
     ("raster_x_step", "double px = x0 + (double)i * dx;", "double px = x0 + (double)i * dy;"),
+    ("locate_last_wins", "for (int64_t k = 0; k < P && id < 0; ++k) {", "for (int64_t k = 0; k < P; ++k) {"),
+    ("locate_generator_offset", "const double *Pk = G + 2 * (vtx_off[k] + k);",
+     "const double *Pk = G + 2 * vtx_off[k];"),
     ("allpairs_bit_order", "row[j >> 5] |= (uint32_t)1u << (j & 31);",
      "row[j >> 5] |= (uint32_t)1u << (31 - (j & 31));"),
     ("cost_body_frame_sign", "double by = (-s) * dx + c * dy;\n        double best = 0.0;",

@@ -220,3 +220,63 @@ def dyadic_grid(lo: float = -0.5, hi: float = 1.5, k: int = 17) -> np.ndarray:
     g = np.linspace(lo, hi, k)
     X, Y = np.meshgrid(g, g, indexing="xy")
     return np.stack([X.ravel(), Y.ravel()], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# polygon database for point location (GIS use, Section 1)
+# ---------------------------------------------------------------------------
+@dataclass
+class Partition:
+    vtx_off: np.ndarray   # [P+1] int64
+    V: np.ndarray         # [total, 2] float64
+    cell_of: np.ndarray   # [P] int64: grid cell (row-major) each polygon came from
+    lo: tuple             # domain corner
+    hi: tuple             # opposite corner
+
+
+def jittered_partition(gx: int, gy: int, cell: float = 1.0, jitter: float = 0.2,
+                       split: float = 0.5, origin=(0.0, 0.0), config: int = 6,
+                       seed_salt: int = 0) -> Partition:
+    """A planar partition of [origin, origin + (gx, gy) * cell] into convex
+    cells: grid vertices moved by up to `jitter` * cell in each coordinate
+    (multiples of 2^-10 cell, so shared vertices are exactly equal), each
+    quad kept (counter-clockwise) or, with probability `split`, cut along its
+    diagonal into two triangles.  Cells are listed row by row.  A jitter of
+    at most 0.25 keeps every quad convex."""
+    rng = rng_for(config, seed_salt)
+    q = 1024.0
+    jx = np.rint(rng.uniform(-jitter, jitter, size=(gy + 1, gx + 1)) * q) / q
+    jy = np.rint(rng.uniform(-jitter, jitter, size=(gy + 1, gx + 1)) * q) / q
+    I, J = np.meshgrid(np.arange(gx + 1), np.arange(gy + 1))
+    X = origin[0] + (I + jx) * cell
+    Y = origin[1] + (J + jy) * cell
+    cut = rng.random((gy, gx)) < split
+    polys, cells = [], []
+    for j in range(gy):
+        for i in range(gx):
+            a = (X[j, i], Y[j, i])
+            b = (X[j, i + 1], Y[j, i + 1])
+            c = (X[j + 1, i + 1], Y[j + 1, i + 1])
+            d = (X[j + 1, i], Y[j + 1, i])
+            if cut[j, i]:
+                polys += [np.array([a, b, c]), np.array([a, c, d])]
+                cells += [j * gx + i, j * gx + i]
+            else:
+                polys.append(np.array([a, b, c, d]))
+                cells.append(j * gx + i)
+    ns = np.array([len(p) for p in polys])
+    vtx_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    lo = (origin[0] - jitter * cell, origin[1] - jitter * cell)
+    hi = (origin[0] + (gx + jitter) * cell, origin[1] + (gy + jitter) * cell)
+    return Partition(vtx_off, np.concatenate(polys).astype(np.float64), np.array(cells), lo, hi)
+
+
+def locate_points(part: Partition, m: int, margin: float = 0.02, config: int = 6,
+                  seed_salt: int = 1) -> np.ndarray:
+    """m float32 query points uniform over the partition's domain widened by
+    `margin` of its size on each side (a few fall outside every cell)."""
+    rng = rng_for(config, seed_salt)
+    w = (part.hi[0] - part.lo[0], part.hi[1] - part.lo[1])
+    x = rng.uniform(part.lo[0] - margin * w[0], part.hi[0] + margin * w[0], m)
+    y = rng.uniform(part.lo[1] - margin * w[1], part.hi[1] + margin * w[1], m)
+    return np.stack([x, y], 1).astype(np.float32)
