@@ -264,6 +264,31 @@ def run_extras(P, W, torch, stream, check):
     out["raster"] = rast
     print("[bench] raster done", file=sys.stderr, flush=True)
 
+    # point location: 2^26 uniform points against a 256 x 256 jittered
+    # partition (about 98k convex cells) through the grid index
+    part = W.jittered_partition(256, 256, cell=1.0, split=0.5)
+    Ql = torch.from_numpy(W.locate_points(part, 1 << 26)).to(dev)
+    offl, Vl = torch.from_numpy(part.vtx_off).to(dev), torch.from_numpy(part.V).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    index = P.LocateIndex(offl, Vl)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    ids = index.locate(Ql)
+    ms_l = _time(torch, stream, lambda: index.locate(Ql, ids=ids), reps=5)
+    cells, entries = index.info()
+    e = {"polygons": len(part.vtx_off) - 1, "points": int(Ql.shape[0]), "cells": cells,
+         "entries": entries, "build_ms": round(build_ms, 2), "ms": round(ms_l, 3),
+         "gpoints_per_s": round(Ql.shape[0] / ms_l / 1e6, 2),
+         "hbm_frac": round(12.0 * Ql.shape[0] / (ms_l * 1e-3) / 8.0e12, 4)}
+    if check:
+        sel = np.sort(rng.choice(Ql.shape[0], 4096, replace=False))
+        want = o.locate(part.vtx_off, part.V, Ql.cpu().numpy()[sel].astype(np.float64))
+        e["mismatches_4096_points"] = int((ids.cpu().numpy()[sel] != want).sum())
+    index.close()
+    out["locate"] = e
+    print("[bench] locate done", file=sys.stderr, flush=True)
+
     # differentiable cost: 1024 trajectories x 64 poses x 65,536 points
     F32 = F.astype(np.float32)
     Qd = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)

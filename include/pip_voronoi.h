@@ -88,6 +88,12 @@ const char *pip_last_error(pip_ctx ctx);
 /* Library version as major*10000 + minor*100 + patch. */
 int pip_version(void);
 
+/* Point-location index over a stored set of convex polygons (Section 1's
+ * GIS use; Section 7: the generators of constant polygons are derived once
+ * and kept beside the vertices, about twice the storage).  Owns device
+ * memory until pip_index_destroy. */
+typedef struct pip_index_s *pip_index;
+
 /* Tuning options of a context.  Labels never depend on them.
  *   PIP_OPT_MFMA_MIN_EDGES: pip_voronoi / pip_sign_of_offset on float32 points
  *     evaluate the margins of polygons with at least this many edges as dense
@@ -193,6 +199,35 @@ pip_status pip_voronoi_max_margin(pip_ctx ctx, const double *V, int32_t n, const
 pip_status pip_voronoi_raster(pip_ctx ctx, const double *V, int32_t n, double x0, double y0,
                               double dx, double dy, int64_t width, int64_t height,
                               uint32_t *labels, int32_t *status, hipStream_t stream);
+
+/* Builds the index of P polygons (device CSR: vtx_off [P+1] int64 with
+ * vtx_off[P] == total_vertices, V [total_vertices][2] float64).  Per polygon:
+ * generators (Algorithms 3-4), the float32 screen table and band, and a box
+ * widened by the distance within which binary64 rounding can put an outside
+ * point inside; a uniform grid of about `cells` square cells (0: one per
+ * polygon; at most 2^24) lists every polygon whose box meets a cell.  A
+ * polygon with fewer than 3 vertices contains no point; degenerate,
+ * non-convex or non-finite polygons are kept in a list every query tests.
+ * status (device [P] int32, optional) receives each polygon's pip_status.
+ * Synchronizes `stream` (the list sizes are read back) and allocates.
+ * Errors: PIP_EINVAL for bad arguments or vtx_off[P] != total_vertices,
+ * PIP_EUNSUPPORTED for a polygon with more than 64 vertices or 2^31 or more
+ * list entries, PIP_ENOMEM. */
+pip_status pip_index_create(pip_ctx ctx, int32_t P, const int64_t *vtx_off, const double *V,
+                            int64_t total_vertices, int64_t cells, int32_t *status,
+                            hipStream_t stream, pip_index *out);
+
+/* Locates m float32 points (Q [m][2], device): ids[j] (device [m] int32) is
+ * the smallest k whose polygon contains point j under the Voronoi test
+ * (Section 4, Algorithm 5; closed, equal to the plain binary64 algorithm),
+ * or -1; non-finite points get -1.  Asynchronous on `stream`. */
+pip_status pip_index_locate(pip_index index, const float *Q, int64_t m, int32_t *ids,
+                            hipStream_t stream);
+
+/* Grid cells requested and list entries (cells and the global list). */
+pip_status pip_index_info(pip_index index, int64_t *cells, int64_t *entries);
+
+void pip_index_destroy(pip_index index);
 
 /* ------------------------------------------------------------------------
  * Batched Voronoi inclusion: P convex polygons, each against its own point

@@ -314,6 +314,59 @@ class BatchedPlan:
             pass
 
 
+class LocateIndex:
+    """Point-location index over a stored set of convex polygons
+    (vtx_off [P+1] int64 and V [total, 2] float64 on the GPU).  locate(Q)
+    returns, per float32 point, the smallest index of a polygon containing
+    it, or -1."""
+
+    def __init__(self, vtx_off, V, cells: int = 0, status=None):
+        vtx_off = _i64(vtx_off, "vtx_off")
+        if V.dtype != torch.float64 or V.dim() != 2 or V.shape[1] != 2 or not V.is_contiguous():
+            raise ValueError("V must be a contiguous float64 tensor of shape [total, 2]")
+        self.device = _dev(vtx_off)
+        self.P = vtx_off.numel() - 1
+        if status is not None and (status.dtype != torch.int32 or status.numel() < self.P):
+            raise ValueError("status must be an int32 tensor with >= P elements")
+        self.ctx = context(self.device)
+        self._keep = (vtx_off, V)
+        h = ctypes.c_void_p()
+        s = _lib().pip_index_create(self.ctx, self.P, vtx_off.data_ptr(),
+                                    V.data_ptr() if V.numel() else None, V.shape[0], int(cells),
+                                    status.data_ptr() if status is not None else None,
+                                    _stream(self.device), ctypes.byref(h))
+        _check(s, "pip_index_create", self.ctx)
+        self.handle = h.value
+
+    def info(self):
+        c, e = ctypes.c_int64(), ctypes.c_int64()
+        s = _lib().pip_index_info(self.handle, ctypes.byref(c), ctypes.byref(e))
+        _check(s, "pip_index_info", self.ctx)
+        return int(c.value), int(e.value)
+
+    def locate(self, Q, ids=None):
+        if Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != 2 or not Q.is_contiguous():
+            raise ValueError("Q must be a contiguous float32 tensor of shape [m, 2]")
+        m = Q.shape[0]
+        if ids is None:
+            ids = torch.empty(max(m, 1), dtype=torch.int32, device=Q.device)
+        s = _lib().pip_index_locate(self.handle, Q.data_ptr() if m else None, m, ids.data_ptr(),
+                                    _stream(self.device))
+        _check(s, "pip_index_locate", self.ctx)
+        return ids[:m]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().pip_index_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ---------------------------------------------------------------------------
 # poses, all pairs
 # ---------------------------------------------------------------------------

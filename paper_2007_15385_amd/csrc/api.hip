@@ -26,6 +26,20 @@ struct pip_ctx_s {
 
 // A plan: one batched request bound to its buffers, its own workspace, the
 // tile shape chosen by the autotuner and the captured hipGraph.
+struct pip_index_s {
+    pip_ctx ctx = nullptr;
+    int64_t P = 0, cells = 0, entries = 0;
+    void* mem = nullptr;       // records, rows, generators, grid, counters, offsets
+    void* list_mem = nullptr;  // cell lists (sized after counting)
+    pipdev::LocRec* rec = nullptr;
+    float4* qrec = nullptr;
+    double2* gen = nullptr;
+    pipdev::LocGrid* grid = nullptr;
+    int32_t* cell_off = nullptr;
+    pipdev::LocEntry* list = nullptr;
+    int blocks = 0;
+};
+
 struct pip_plan_s {
     pip_ctx ctx = nullptr;
     pipdev::BatchedDev D{};
@@ -741,6 +755,133 @@ pip_status pip_cost_bwd(pip_ctx ctx, const float* footprint, int32_t n, const fl
     return PIP_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// point location index
+// ---------------------------------------------------------------------------
+void pip_index_destroy(pip_index x) {
+    if (!x) return;
+    DeviceGuard g(x->ctx->device);
+    if (x->mem) (void)hipFree(x->mem);
+    if (x->list_mem) (void)hipFree(x->list_mem);
+    delete x;
+}
+
+pip_status pip_index_create(pip_ctx ctx, int32_t P, const int64_t* vtx_off, const double* V,
+                            int64_t total_vertices, int64_t cells, int32_t* status,
+                            hipStream_t stream, pip_index* out) {
+    if (!out) return fail(PIP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (P < 0) return fail(PIP_EINVAL, "P = %d is negative", (int)P);
+    if (!vtx_off || !aligned(vtx_off, 8)) return fail(PIP_EINVAL, "vtx_off is NULL or misaligned");
+    if (total_vertices < 0) return fail(PIP_EINVAL, "total_vertices is negative");
+    if (total_vertices > 0 && (!V || !aligned(V, 8))) return fail(PIP_EINVAL, "V is NULL or misaligned");
+    if (status && !aligned(status, 4)) return fail(PIP_EINVAL, "status is not 4-byte aligned");
+    if (cells < 0 || cells > (int64_t(1) << 24))
+        return fail(PIP_EINVAL, "cells = %lld must be in [0, 2^24]", (long long)cells);
+    if (cells == 0) cells = P < 1 ? 1 : (P > (1 << 24) ? (1 << 24) : P);
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    // the caller's offsets must end at total_vertices
+    int64_t last = -1;
+    hipError_t e = hipMemcpy(&last, vtx_off + P, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading vtx_off[P]");
+    if (last != total_vertices)
+        return fail(PIP_EINVAL, "vtx_off[P] = %lld differs from total_vertices = %lld",
+                    (long long)last, (long long)total_vertices);
+    if (total_vertices + 5 * (int64_t)P >= (int64_t(1) << 31))
+        return fail(PIP_EUNSUPPORTED, "%lld vertices in %d polygons exceed the 32-bit record offsets",
+                    (long long)total_vertices, (int)P);
+    pip_index x = new (std::nothrow) pip_index_s();
+    if (!x) return fail(PIP_ENOMEM, "out of host memory");
+    x->ctx = ctx;
+    x->P = P;
+    x->cells = cells;
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t o_rec = 0;
+    const size_t o_qrec = up(o_rec + sizeof(pipdev::LocRec) * (size_t)(P > 0 ? P : 1));
+    const size_t o_gen = up(o_qrec + 16 * (size_t)(total_vertices + 5 * (int64_t)P + 1));
+    const size_t o_grid = up(o_gen + 16 * (size_t)(total_vertices + P + 1));
+    const size_t o_flag = up(o_grid + sizeof(pipdev::LocGrid));
+    const size_t o_total = up(o_flag + 8);
+    const size_t o_cnt = up(o_total + 8);
+    const size_t o_off = up(o_cnt + 4 * (size_t)(cells + 1));
+    const size_t o_end = up(o_off + 4 * (size_t)(cells + 2));
+    char* b = nullptr;
+    if ((e = hipMalloc(&x->mem, o_end)) != hipSuccess) {
+        pip_index_destroy(x);
+        return fail(PIP_ENOMEM, "hipMalloc of %zu index bytes failed", o_end);
+    }
+    b = static_cast<char*>(x->mem);
+    x->rec = reinterpret_cast<pipdev::LocRec*>(b + o_rec);
+    x->qrec = reinterpret_cast<float4*>(b + o_qrec);
+    x->gen = reinterpret_cast<double2*>(b + o_gen);
+    x->grid = reinterpret_cast<pipdev::LocGrid*>(b + o_grid);
+    int32_t* flag = reinterpret_cast<int32_t*>(b + o_flag);
+    auto* total = reinterpret_cast<unsigned long long*>(b + o_total);
+    int32_t* cnt = reinterpret_cast<int32_t*>(b + o_cnt);
+    x->cell_off = reinterpret_cast<int32_t*>(b + o_off);
+    e = pipdev::index_prepare(P, vtx_off, V, x->rec, x->qrec, x->gen, status, flag, stream);
+    if (e == hipSuccess) e = pipdev::index_grid(P, x->rec, cells, x->grid, cnt, total, stream);
+    int32_t hflag = 0;
+    unsigned long long htotal = 0;
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(&hflag, flag, 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&htotal, total, 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        pip_index_destroy(x);
+        return hip_fail(e, "building the index");
+    }
+    if (hflag) {
+        pip_index_destroy(x);
+        return fail(PIP_EUNSUPPORTED, "a polygon has more than %d vertices", PIP_MAX_EDGES);
+    }
+    if (htotal >= (1ull << 31)) {
+        pip_index_destroy(x);
+        return fail(PIP_EUNSUPPORTED, "%llu cell entries: use fewer cells", htotal);
+    }
+    x->entries = (int64_t)htotal;
+    if ((e = hipMalloc(&x->list_mem, sizeof(pipdev::LocEntry) * (size_t)(htotal > 0 ? htotal : 1))) !=
+        hipSuccess) {
+        pip_index_destroy(x);
+        return fail(PIP_ENOMEM, "hipMalloc of the cell lists failed");
+    }
+    x->list = static_cast<pipdev::LocEntry*>(x->list_mem);
+    e = pipdev::index_fill(P, x->rec, x->grid, cells, cnt, x->cell_off, x->list, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        pip_index_destroy(x);
+        return hip_fail(e, "filling the index");
+    }
+    int per_cu = 0;
+    if (pipdev::locate_max_blocks_per_cu(&per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+    x->blocks = per_cu * ctx->cu_count;
+    *out = x;
+    return PIP_OK;
+}
+
+pip_status pip_index_locate(pip_index x, const float* Q, int64_t m, int32_t* ids,
+                            hipStream_t stream) {
+    if (!x) return fail(PIP_EINVAL, "index is NULL");
+    if (m < 0) return fail(PIP_EINVAL, "m = %lld is negative", (long long)m);
+    if (m > 0 && (!Q || !aligned(Q, 8))) return fail(PIP_EINVAL, "Q is NULL or not 8-byte aligned");
+    if (m > 0 && (!ids || !aligned(ids, 4))) return fail(PIP_EINVAL, "ids is NULL or misaligned");
+    if (m == 0) return PIP_OK;
+    DeviceGuard g(x->ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_locate(x->qrec, x->gen, x->grid, x->cell_off, x->list, Q, m, ids,
+                                         x->blocks, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+pip_status pip_index_info(pip_index x, int64_t* cells, int64_t* entries) {
+    if (!x) return fail(PIP_EINVAL, "index is NULL");
+    if (cells) *cells = x->cells;
+    if (entries) *entries = x->entries;
+    return PIP_OK;
+}
 
 pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
     if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");

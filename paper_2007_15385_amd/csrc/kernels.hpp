@@ -79,6 +79,41 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws, int cull,
                            int pair, hipStream_t stream);
+// Point-location index: one record per polygon (64 bytes), the grid.
+struct alignas(16) LocRec {
+    float ox, oy;          // float32 local origin
+    float KQ, KA, KB, KC;  // band constants
+    int n, n4;             // edges, padded to 4
+    int64_t qoff;          // query record (float4 units)
+    int64_t gen_off;       // first generator (double2): p_0, then p_i
+    float bx0, by0, bx1, by1;  // widened, outward-rounded box
+    int status;            // pip_status of the polygon
+    int usable;            // 0: contains no point; 1: in the grid cells; 2: global list
+};
+// Cell-list entry: the polygon's box, index and query-record offset (float4
+// units): record = {ox, oy, KQ, KA}, {KB, KC, n | n4 << 16, generator
+// offset}, then n4 coefficient rows.
+struct alignas(32) LocEntry {
+    float bx0, by0, bx1, by1;
+    int k, qoff, pad0, pad1;
+};
+struct LocGrid {
+    float x0, y0, x1, y1;  // union of the cell-listed boxes
+    float inv_w, inv_h;    // cells per unit length
+    int gx, gy;            // grid shape (gx * gy <= requested cells)
+    int any;               // some polygon is cell-listed
+};
+hipError_t index_prepare(int64_t P, const int64_t* vtx_off, const double* V, LocRec* rec,
+                         float4* qrec, double2* gen, int32_t* status, int32_t* flags,
+                         hipStream_t stream);
+hipError_t index_grid(int64_t P, const LocRec* rec, int64_t cells, LocGrid* grid, int32_t* cnt,
+                      unsigned long long* total, hipStream_t stream);
+hipError_t index_fill(int64_t P, const LocRec* rec, const LocGrid* grid, int64_t cells,
+                      int32_t* cnt, int32_t* cell_off, LocEntry* list, hipStream_t stream);
+hipError_t launch_locate(const float4* qrec, const double2* gen, const LocGrid* grid,
+                         const int32_t* cell_off, const LocEntry* list, const float* Q, int64_t m,
+                         int32_t* ids, int max_blocks, hipStream_t stream);
+hipError_t locate_max_blocks_per_cu(int* out);
 // Coverage raster: pixel (i, j) = (x0 + i dx, y0 + j dy), binary64.
 struct RasterGrid {
     double x0, y0, dx, dy;

@@ -1,0 +1,388 @@
+// Point location in a stored set of convex polygons (the GIS use of
+// Section 1: field measurements matched against a polygon database).  The
+// generators of the constant polygons are derived once and kept beside the
+// vertices (Section 7: about twice the storage), with the float32 screen
+// table and the band constants of each polygon; a uniform grid over the
+// polygons' bounding boxes lists, per cell, every polygon whose box meets
+// the cell.  A query point looks up its cell and tests the listed polygons
+// (float32 screen, binary64 replay of Algorithm 5 inside the band); its id
+// is the smallest index of a polygon that contains it, or -1.
+//
+// Exactness of the index.  Binary64 rounding can put a point just outside a
+// polygon inside it, so a polygon's box is its vertex bounds widened by a
+// bound on that distance: the binary64 evaluation of Algorithm 5 differs
+// from the exact margin m_i = 2 |h_i| s_i (s_i the signed distance past edge
+// line i, h_i = p_i - p_0) by at most E64 = 24.01 v |p - o|^2 +
+// 4.0001 v (6 d2 + 2 H2) (the band's binary64 part), so every point it calls
+// inside lies in the polygon with each edge moved out by
+// t = E64 / (2 min |h_i|); such an offset moves a vertex of interior angle
+// theta by t / sin(theta / 2).  The box is widened by twice
+// t / min sin(theta_i / 2), with |p - o| bounded by twice the largest vertex
+// distance, and rounded outwards to float32; a polygon without a finite,
+// small widening (degenerate or non-convex input, or non-finite vertices)
+// goes to a global list that every query tests as well (binary64 decides;
+// normally empty).  A box corner and a query point are mapped to
+// cells by the same float32 function, monotone in the coordinate, so a point
+// inside a box is in a cell of the box's range.  The answer is the minimum
+// containing index, so the order of a cell's list does not matter.
+//
+//   k_index_prepare   one wave per polygon: generators (Algorithms 3-4),
+//                     float32 table in the polygon's local frame, band
+//                     constants, outward-rounded box; n > 64 is flagged.
+//   k_index_bounds    one block: union box of the usable polygons, grid
+//                     shape (about the requested cell count, square cells).
+//   k_index_count /   one thread per polygon: its cell range, counted, then
+//   k_index_fill      written into the cell lists (after an exclusive scan).
+//   k_locate          one query point per lane; its cell's entries carry the
+//                     candidates' boxes, so only box hits read a record.
+#include "device.hpp"
+#include "kernels.hpp"
+
+using namespace pipdev;
+
+namespace {
+
+__device__ __forceinline__ float round_out_hi(double d) {
+    float f = (float)d;
+    if ((double)f < d) f = nextafterf(f, __builtin_huge_valf());
+    return f;
+}
+__device__ __forceinline__ float round_out_lo(double d) {
+    float f = (float)d;
+    if ((double)f > d) f = nextafterf(f, -__builtin_huge_valf());
+    return f;
+}
+
+// grid cell of a coordinate (monotone non-decreasing in x)
+__device__ __forceinline__ int cell_of(float x, float x0, float inv, int g) {
+    const float t = fminf(fmaxf((x - x0) * inv, 0.0f), (float)(g - 1));
+    return (int)t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_index_prepare(int64_t P,
+                                                        const int64_t* __restrict__ vtx_off,
+                                                        const double* __restrict__ V,
+                                                        LocRec* __restrict__ rec,
+                                                        float4* __restrict__ qrec,
+                                                        double2* __restrict__ gen,
+                                                        int32_t* __restrict__ status,
+                                                        int32_t* __restrict__ flags) {
+    __shared__ PolyLds S[kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wv = threadIdx.x / kWave;
+    const int64_t k = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    if (k >= P) return;
+    PolyLds& L = S[wv];
+    const int64_t v0 = vtx_off[k];
+    const int64_t nn = vtx_off[k + 1] - v0;
+    LocRec R;
+    R.n = 0;
+    R.usable = 0;
+    if (nn < 3 || nn > kMaxEdges) {  // contains no point / not supported
+        if (lane == 0) {
+            R.status = nn > kMaxEdges ? 6 : 1;  // PIP_EUNSUPPORTED, PIP_EINVAL
+            rec[k] = R;
+            if (status) status[k] = R.status;
+            if (nn > kMaxEdges) atomicOr(flags, 1);
+        }
+        return;
+    }
+    const int n = (int)nn;
+    if (lane < n) L.vtx[lane] = make_double2(V[2 * (v0 + lane)], V[2 * (v0 + lane) + 1]);
+    if (lane == 0) L.n = n;
+    __builtin_amdgcn_wave_barrier();
+    prepare_polygon(L, K_VORONOI, lane);
+    __builtin_amdgcn_wave_barrier();
+    // vertex bounds (NaN poisons them: such a polygon is not indexed)
+    const int i = lane < n ? lane : 0;
+    const double2 v = L.vtx[i];
+    const double xlo = -wave_max(-v.x), xhi = wave_max(v.x);
+    const double ylo = -wave_max(-v.y), yhi = wave_max(v.y);
+    const bool all_fin = __ballot(!(isfinite(v.x) && isfinite(v.y))) == 0;
+    // widening: binary64 misclassification distance (see the file comment)
+    double widen = __builtin_huge_val();
+    {
+        const double g0x = L.gen[0].x, g0y = L.gen[0].y;
+        const double hx = L.gen[1 + i].x - g0x, hy = L.gen[1 + i].y - g0y;
+        const double hmin = -wave_max(-sqrt(hx * hx + hy * hy));
+        const double H2 = wave_max(hx * hx + hy * hy);
+        // interior angle at vertex i: incoming edge a = v_i - v_{i-1},
+        // outgoing b = v_{i+1} - v_i; sin(theta / 2) = sqrt((1 + a.b) / 2)
+        // for unit a, b of a convex polygon
+        const double2 vp = L.vtx[i == 0 ? n - 1 : i - 1], vn = L.vtx[i + 1 == n ? 0 : i + 1];
+        const double ax = v.x - vp.x, ay = v.y - vp.y, bx = vn.x - v.x, by = vn.y - v.y;
+        const double cosab = (ax * bx + ay * by) / (sqrt(ax * ax + ay * ay) * sqrt(bx * bx + by * by));
+        const double smin = -wave_max(-sqrt(fmax(0.5 * (1.0 + cosab), 0.0)));
+        const double ox = (double)L.ox, oy = (double)L.oy;
+        const double rv = wave_max(sqrt((v.x - ox) * (v.x - ox) + (v.y - oy) * (v.y - oy)));
+        const double d2 = (g0x - ox) * (g0x - ox) + (g0y - oy) * (g0y - oy);
+        const double e64 = 24.01 * kU64 * (4.0 * rv * rv) + 4.0001 * kU64 * (6.0 * d2 + 2.0 * H2);
+        const double w = 2.0 * e64 / (2.0 * hmin * smin) * 1.01;
+        if (L.status == 0 && hmin > 0.0 && smin > 0.0 && w <= rv && w == w) widen = w;
+    }
+    const double wx = widen + 4.0 * kU64 * fmax(fabs(xlo), fabs(xhi));
+    const double wy = widen + 4.0 * kU64 * fmax(fabs(ylo), fabs(yhi));
+    // query record at float4 offset v0 + 5k: header (2 float4), n4 rows
+    const int64_t qbase = v0 + 5 * k, gbase = v0 + k;
+    const int n4 = L.n4;
+    if (lane < n4) qrec[qbase + 2 + lane] = L.coef[lane];
+    if (lane == 0) {
+        qrec[qbase] = make_float4(L.ox, L.oy, L.KQ, L.KA);
+        qrec[qbase + 1] = make_float4(L.KB, L.KC, __int_as_float(n | (n4 << 16)),
+                                      __int_as_float((int)gbase));
+    }
+    for (int r = lane; r <= n; r += kWave) gen[gbase + r] = L.gen[r];
+    if (lane == 0) {
+        R.ox = L.ox;
+        R.oy = L.oy;
+        R.KQ = L.KQ;
+        R.KA = L.KA;
+        R.KB = L.KB;
+        R.KC = L.KC;
+        R.n = n;
+        R.n4 = n4;
+        R.qoff = qbase;
+        R.gen_off = gbase;
+        R.status = L.status;
+        R.usable = all_fin && widen < __builtin_huge_val() ? 1 : 2;  // 2: global list
+        R.bx0 = round_out_lo(xlo - wx);
+        R.by0 = round_out_lo(ylo - wy);
+        R.bx1 = round_out_hi(xhi + wx);
+        R.by1 = round_out_hi(yhi + wy);
+        rec[k] = R;
+        if (status) status[k] = L.status;
+    }
+}
+
+// One block: union of the usable boxes and the grid shape.
+__global__ __launch_bounds__(1024) void k_index_bounds(int64_t P, const LocRec* __restrict__ rec,
+                                                     int64_t cells, LocGrid* __restrict__ grid) {
+    __shared__ float red[4][1024];
+    const int t = threadIdx.x;
+    float x0 = __builtin_huge_valf(), y0 = __builtin_huge_valf();
+    float x1 = -__builtin_huge_valf(), y1 = -__builtin_huge_valf();
+    for (int64_t k = t; k < P; k += blockDim.x) {
+        const LocRec& R = rec[k];
+        if (R.usable != 1) continue;
+        x0 = fminf(x0, R.bx0);
+        y0 = fminf(y0, R.by0);
+        x1 = fmaxf(x1, R.bx1);
+        y1 = fmaxf(y1, R.by1);
+    }
+    red[0][t] = x0;
+    red[1][t] = y0;
+    red[2][t] = -x1;
+    red[3][t] = -y1;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s)
+            for (int c = 0; c < 4; ++c) red[c][t] = fminf(red[c][t], red[c][t + s]);
+        __syncthreads();
+    }
+    if (t == 0) {
+        LocGrid G;
+        G.x0 = red[0][0];
+        G.y0 = red[1][0];
+        G.x1 = -red[2][0];
+        G.y1 = -red[3][0];
+        const bool any = G.x0 <= G.x1 && G.y0 <= G.y1;
+        const double w = any ? (double)G.x1 - (double)G.x0 : 0.0;
+        const double h = any ? (double)G.y1 - (double)G.y0 : 0.0;
+        int gx = 1, gy = 1;
+        if (w > 0.0 && h > 0.0) {
+            gx = (int)fmin(fmax(rint(sqrt((double)cells * w / h)), 1.0), (double)cells);
+            gy = (int)fmax((double)(cells / gx), 1.0);
+        } else if (w > 0.0) {
+            gx = (int)cells;
+        } else if (h > 0.0) {
+            gy = (int)cells;
+        }
+        G.gx = gx;
+        G.gy = gy;
+        G.inv_w = w > 0.0 ? (float)((double)gx / w) : 0.0f;
+        G.inv_h = h > 0.0 ? (float)((double)gy / h) : 0.0f;
+        G.any = any ? 1 : 0;
+        *grid = G;
+    }
+}
+
+__global__ void k_index_zero(int32_t* __restrict__ p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+// FILL = false: count entries per cell (and their total); true: write them.
+template <bool FILL>
+__global__ void k_index_cells(int64_t P, const LocRec* __restrict__ rec,
+                              const LocGrid* __restrict__ grid, int32_t* __restrict__ cnt,
+                              const int32_t* __restrict__ cell_off, LocEntry* __restrict__ list,
+                              unsigned long long* __restrict__ total) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    const LocRec R = rec[k];
+    LocEntry en;
+    en.bx0 = R.bx0;
+    en.by0 = R.by0;
+    en.bx1 = R.bx1;
+    en.by1 = R.by1;
+    en.k = (int)k;
+    en.qoff = (int)R.qoff;
+    en.pad0 = en.pad1 = 0;
+    if (R.usable == 2) {  // global list: its count sits after the cells'
+        const int64_t C = (int64_t)grid->gx * grid->gy;
+        if (!FILL) atomicAdd(total, 1ull);
+        const int slot = atomicAdd(&cnt[C], 1);
+        if (FILL) list[cell_off[C] + slot] = en;
+        return;
+    }
+    if (R.usable != 1) return;
+    const LocGrid G = *grid;
+    const int cx0 = cell_of(R.bx0, G.x0, G.inv_w, G.gx), cx1 = cell_of(R.bx1, G.x0, G.inv_w, G.gx);
+    const int cy0 = cell_of(R.by0, G.y0, G.inv_h, G.gy), cy1 = cell_of(R.by1, G.y0, G.inv_h, G.gy);
+    if (!FILL) atomicAdd(total, (unsigned long long)(cx1 - cx0 + 1) * (unsigned long long)(cy1 - cy0 + 1));
+    for (int cy = cy0; cy <= cy1; ++cy)
+        for (int cx = cx0; cx <= cx1; ++cx) {
+            const int64_t c = (int64_t)cy * G.gx + cx;
+            const int slot = atomicAdd(&cnt[c], 1);
+            if (FILL) list[cell_off[c] + slot] = en;
+        }
+}
+
+// Exclusive scan of count[0..C) into off[0..C] in one block.
+__global__ __launch_bounds__(1024) void k_index_scan(int64_t C, const int32_t* __restrict__ count,
+                                                   int32_t* __restrict__ off) {
+    __shared__ int64_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (C + blockDim.x - 1) / blockDim.x;
+    const int64_t b = t * per, e = b + per < C ? b + per : C;
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += count[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int i = 0; i < (int)blockDim.x; ++i) {
+            const int64_t v = part[i];
+            part[i] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t i = b; i < e; ++i) {
+        off[i] = (int32_t)acc;
+        acc += count[i];
+    }
+    if (e == C && b < e) off[C] = (int32_t)acc;
+    if (C == 0 && t == 0) off[0] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_locate(const float4* __restrict__ qrec,
+                                                 const double2* __restrict__ gen,
+                                                 const LocGrid* __restrict__ grid,
+                                                 const int32_t* __restrict__ cell_off,
+                                                 const LocEntry* __restrict__ list,
+                                                 const float2* __restrict__ Q, int64_t m,
+                                                 int32_t* __restrict__ ids) {
+    const LocGrid G = *grid;
+    const int64_t C = (int64_t)G.gx * G.gy;
+    const int gbeg = cell_off[C], gend = cell_off[C + 1];  // the global list
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+        const vfloat2 pv = __builtin_nontemporal_load(reinterpret_cast<const vfloat2*>(Q) + i);
+        const float2 p = make_float2(pv.x, pv.y);
+        int id = -1;
+        // entry t's polygon contains p (box, float32 screen, binary64 inside
+        // the band); a NaN box (non-finite vertices) never rejects
+        auto test = [&](int t) {
+            const float4 box = *reinterpret_cast<const float4*>(&list[t]);
+            if (p.x < box.x || p.y < box.y || p.x > box.z || p.y > box.w) return;
+            const int2 kq = *reinterpret_cast<const int2*>(&list[t].k);
+            if (id >= 0 && kq.x > id) return;  // cannot lower the answer
+            const float4* r = qrec + kq.y;
+            const float4 h0 = r[0], h1 = r[1];
+            const int nn = __float_as_int(h1.z);
+            const int n = nn & 0xffff, n4 = nn >> 16;
+            const float X = p.x - h0.x, Y = p.y - h0.y;
+            float M = -__builtin_huge_valf();
+            for (int e = 0; e < n4; ++e) {
+                const float4 c = r[2 + e];
+                M = fmaxf(M, fmaf(c.x, X, fmaf(c.y, Y, c.z)));
+            }
+            const float E =
+                fmaf(h0.z, fmaf(X, X, Y * Y), fmaf(h0.w, fabsf(X), fmaf(h1.x, fabsf(Y), h1.y)));
+            bool in = M < -E;
+            if (!(fabsf(M) > E))
+                in = voronoi64((double)p.x, (double)p.y, gen + __float_as_int(h1.w), n);
+            if (in) id = kq.x;
+        };
+        // outside the union of the cell boxes (or NaN): only the global list
+        if (G.any && p.x >= G.x0 && p.x <= G.x1 && p.y >= G.y0 && p.y <= G.y1) {
+            const int64_t c =
+                (int64_t)cell_of(p.y, G.y0, G.inv_h, G.gy) * G.gx + cell_of(p.x, G.x0, G.inv_w, G.gx);
+            const int beg = cell_off[c], end = cell_off[c + 1];
+            for (int t = beg; t < end; ++t) test(t);
+        }
+        for (int t = gbeg; t < gend; ++t) test(t);
+        ids[i] = id;
+    }
+}
+
+}  // namespace
+
+namespace pipdev {
+
+hipError_t index_prepare(int64_t P, const int64_t* vtx_off, const double* V, LocRec* rec,
+                         float4* qrec, double2* gen, int32_t* status, int32_t* flags,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL(k_index_zero, dim3(1), dim3(64), 0, stream, flags, (int64_t)1);
+    if (P == 0) return hipGetLastError();
+    const unsigned blocks = (unsigned)((P + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_index_prepare, dim3(blocks), dim3(kBlock), 0, stream, P, vtx_off, V, rec,
+                       qrec, gen, status, flags);
+    return hipGetLastError();
+}
+
+// cnt: cells + 1 counters (cell counts, then the global list at gx * gy);
+// total: entries of all lists (unsigned long long).
+hipError_t index_grid(int64_t P, const LocRec* rec, int64_t cells, LocGrid* grid, int32_t* cnt,
+                      unsigned long long* total, hipStream_t stream) {
+    hipLaunchKernelGGL(k_index_bounds, dim3(1), dim3(1024), 0, stream, P, rec, cells, grid);
+    hipLaunchKernelGGL(k_index_zero, dim3((unsigned)((cells + 1 + 255) / 256)), dim3(256), 0,
+                       stream, cnt, cells + 1);
+    hipLaunchKernelGGL(k_index_zero, dim3(1), dim3(64), 0, stream,
+                       reinterpret_cast<int32_t*>(total), (int64_t)2);
+    if (P > 0)
+        hipLaunchKernelGGL(k_index_cells<false>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0,
+                           stream, P, rec, grid, cnt, nullptr, nullptr, total);
+    return hipGetLastError();
+}
+
+// cell_off: cells + 2 offsets (exclusive scan of cnt); list: total entries.
+hipError_t index_fill(int64_t P, const LocRec* rec, const LocGrid* grid, int64_t cells,
+                      int32_t* cnt, int32_t* cell_off, LocEntry* list, hipStream_t stream) {
+    hipLaunchKernelGGL(k_index_scan, dim3(1), dim3(1024), 0, stream, cells + 1, cnt, cell_off);
+    hipLaunchKernelGGL(k_index_zero, dim3((unsigned)((cells + 1 + 255) / 256)), dim3(256), 0,
+                       stream, cnt, cells + 1);
+    if (P > 0)
+        hipLaunchKernelGGL(k_index_cells<true>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0,
+                           stream, P, rec, grid, cnt, cell_off, list, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_locate(const float4* qrec, const double2* gen, const LocGrid* grid,
+                         const int32_t* cell_off, const LocEntry* list, const float* Q, int64_t m,
+                         int32_t* ids, int max_blocks, hipStream_t stream) {
+    if (m == 0) return hipSuccess;
+    const int64_t want = (m + kBlock - 1) / kBlock;
+    const int grid_blocks = (int)(want < max_blocks ? want : max_blocks);
+    hipLaunchKernelGGL(k_locate, dim3(grid_blocks), dim3(kBlock), 0, stream, qrec, gen, grid,
+                       cell_off, list, reinterpret_cast<const float2*>(Q), m, ids);
+    return hipGetLastError();
+}
+
+hipError_t locate_max_blocks_per_cu(int* out) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)k_locate, kBlock, 0);
+}
+
+}  // namespace pipdev

@@ -1,0 +1,169 @@
+"""GPU parity of the point-location index against the brute-force FP64
+oracle: every id equal (smallest containing polygon index, or -1), for
+partitions, overlapping and degenerate polygon sets, several grid shapes and
+the full-size partition."""
+from __future__ import annotations
+
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_15385_amd as P
+    P.load_library()
+    return P
+
+
+def locate_gpu(P, off, V, Q, cells=0, status=None):
+    idx = P.LocateIndex(torch.from_numpy(np.asarray(off, np.int64)).cuda(),
+                        torch.from_numpy(np.ascontiguousarray(V, np.float64)).cuda(), cells=cells,
+                        status=status)
+    ids = idx.locate(torch.from_numpy(np.ascontiguousarray(Q, np.float32)).cuda())
+    torch.cuda.synchronize()
+    out = ids.cpu().numpy()
+    info = idx.info()
+    idx.close()
+    return out, info
+
+
+def check(P, oracle, off, V, Q, cells=0, tag=""):
+    Q = np.ascontiguousarray(Q, np.float32)
+    say(f"[case] locate {tag} P={len(off) - 1} m={len(Q)} cells={cells}")
+    got, info = locate_gpu(P, off, V, Q, cells)
+    want = oracle.locate(off, V, Q.astype(np.float64))
+    bad = np.nonzero(got != want)[0]
+    assert len(bad) == 0, f"{tag}: {len(bad)} ids differ, first {bad[:5]}: {got[bad[:5]]} vs {want[bad[:5]]}"
+    return want, info
+
+
+def partition_points(rng, part, m):
+    """Uniform points, every grid vertex, edge midpoints and points within
+    1e-12 .. 1e-6 of cell edges."""
+    off, V = part.vtx_off, part.V
+    pts = [W.locate_points(part, m, seed_salt=int(rng.integers(1 << 30))).astype(np.float64), V]
+    for k in range(0, len(off) - 1, 3):
+        Pk = V[off[k]:off[k + 1]]
+        e = np.roll(Pk, -1, 0) - Pk
+        L = np.hypot(e[:, 0], e[:, 1])[:, None]
+        nrm = np.stack([e[:, 1], -e[:, 0]], 1) / L
+        t = rng.random((len(Pk), 1))
+        for s in (0.0, 1e-12, -1e-9, 1e-7, -1e-6):
+            pts.append(Pk + t * e + s * nrm)
+        pts.append(Pk + 0.5 * e)
+    return np.concatenate(pts)
+
+
+def test_locate_hand_worked(P, oracle):
+    with open(os.path.join(GOLDEN, "locate_2x2.json")) as f:
+        g = json.load(f)
+    polys = [np.array(p, dtype=float) for p in g["polygons"]]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])])
+    Q = np.array(g["points"] + [[np.nan, 1.0], [1.0, np.inf], [-np.inf, 0.5]])
+    got, _ = locate_gpu(P, off, np.concatenate(polys), Q)
+    assert got.tolist() == g["ids"] + [-1, -1, -1]
+
+
+@pytest.mark.parametrize("gx,gy,split", [(12, 9, 0.0), (40, 30, 0.5), (7, 61, 1.0)])
+def test_locate_partition(P, oracle, gx, gy, split):
+    rng = np.random.default_rng(gx * gy)
+    part = W.jittered_partition(gx, gy, cell=0.5, split=split, origin=(-3.0, 2.0),
+                                seed_salt=gx)
+    Q = partition_points(rng, part, 60_000)
+    want, info = check(P, oracle, part.vtx_off, part.V, Q, tag=f"partition {gx}x{gy}")
+    say(f"[stat] cells {info[0]}, entries {info[1]}, located {int((want >= 0).sum())} of {len(Q)}")
+
+
+@pytest.mark.parametrize("cells", [1, 7, 1000, 65536])
+def test_locate_grid_shapes_agree(P, oracle, cells):
+    """The grid only prunes candidates: any cell count gives the same ids."""
+    rng = np.random.default_rng(5)
+    part = W.jittered_partition(20, 16, cell=1.0, split=0.5, seed_salt=9)
+    Q = partition_points(rng, part, 20_000)
+    check(P, oracle, part.vtx_off, part.V, Q, cells=cells, tag="grid shapes")
+
+
+def test_locate_overlapping_and_unusual(P, oracle):
+    """Overlapping random polygons (smallest index wins), nested squares, a
+    non-convex and a degenerate polygon and one with a non-finite vertex
+    (kept in the global list), a 2-vertex polygon (contains nothing)."""
+    rng = np.random.default_rng(17)
+    polys = [W.circle_polygon(int(rng.integers(3, 20)), float(rng.uniform(0.5, 4.0)),
+                              rng.uniform(-6, 6, 2), rng) for _ in range(60)]
+    polys += [np.array([[-1.0, -1], [1, -1], [1, 1], [-1, 1]]) * s for s in (3.0, 2.0, 1.0)]
+    polys.append(np.array([[0.0, 0], [4, 0], [2, 0.5], [2, 4]]))       # non-convex
+    polys.append(np.array([[0.0, 0], [1, 1], [2, 2]]))                 # zero area
+    polys.append(np.array([[0.0, 0], [np.inf, 0], [1, 1]]))            # non-finite
+    polys.append(np.array([[5.0, 5], [6, 6]]))                         # 2 vertices
+    polys.append(np.array([[0.0, 0], [1, 0], [1, 0], [0, 1]]))         # zero-length edge
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])])
+    V = np.concatenate(polys)
+    Q = np.concatenate([rng.uniform(-10, 10, (40_000, 2)),
+                        np.concatenate([p for p in polys if np.isfinite(p).all()]),
+                        [[np.nan, 0.0], [0.0, -np.inf]]])
+    st = torch.full((len(polys),), -7, dtype=torch.int32, device="cuda")
+    got, _ = locate_gpu(P, off, V, Q.astype(np.float32), status=st)
+    want = oracle.locate(off, V, Q.astype(np.float32).astype(np.float64))
+    assert np.array_equal(got, want)
+    s = st.cpu().numpy()
+    assert s[:-5].tolist() == [0] * (len(polys) - 5)
+    assert s[-5:].tolist() == [3, 2, 1, 1, 2]  # non-convex, zero area, non-finite, 2 vertices, zero edge
+
+
+@pytest.mark.parametrize("origin", [(1000.0, -500.0), (1.0e5, 1.0e5)])
+def test_locate_far_from_origin(P, oracle, origin):
+    rng = np.random.default_rng(3)
+    part = W.jittered_partition(25, 20, cell=2.0, split=0.5, origin=origin, seed_salt=4)
+    Q = partition_points(rng, part, 30_000)
+    check(P, oracle, part.vtx_off, part.V, Q, tag=f"far {origin}")
+
+
+def test_locate_empty_and_errors(P):
+    V = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
+    got, _ = locate_gpu(P, [0, 4], V, np.zeros((0, 2)))
+    assert got.size == 0
+    got, _ = locate_gpu(P, [0], np.zeros((0, 2)), np.array([[0.5, 0.5]]))
+    assert got.tolist() == [-1]
+    big = W.circle_polygon(65, 1.0, (0, 0), np.random.default_rng(0))
+    with pytest.raises(P.PipError):
+        locate_gpu(P, [0, 65], big, np.zeros((1, 2)))
+    with pytest.raises(P.PipError):  # vtx_off[P] != number of vertices
+        P.LocateIndex(torch.tensor([0, 3], dtype=torch.int64).cuda(), torch.from_numpy(V).cuda())
+
+
+def test_locate_full_size(P, oracle):
+    """The 256 x 256 jittered partition (about 98k convex cells) against
+    2^24 uniform points: every id checked on 20,000 sampled points against
+    the brute-force oracle; at every point, points inside the cells' common
+    interior are located and points outside every box get -1."""
+    part = W.jittered_partition(256, 256, cell=1.0, split=0.5)
+    Q = W.locate_points(part, 1 << 24)
+    say(f"[case] locate full size: P={len(part.vtx_off) - 1}, GPU")
+    got, info = locate_gpu(P, part.vtx_off, part.V, Q)
+    rng = np.random.default_rng(8)
+    sel = np.sort(rng.choice(len(Q), 20_000, replace=False))
+    say("[case] locate full size: oracle sample")
+    want = oracle.locate(part.vtx_off, part.V, Q[sel].astype(np.float64))
+    assert np.array_equal(got[sel], want)
+    inner = (Q[:, 0] > 0.25) & (Q[:, 0] < 255.75) & (Q[:, 1] > 0.25) & (Q[:, 1] < 255.75)
+    assert (got[inner] >= 0).all()
+    outer = (Q[:, 0] < -0.25) | (Q[:, 0] > 256.25) | (Q[:, 1] < -0.25) | (Q[:, 1] > 256.25)
+    assert (got[outer] == -1).all()
+    say(f"[stat] locate: cells {info[0]}, entries {info[1]}, located {int((got >= 0).sum())}")
