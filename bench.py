@@ -35,9 +35,9 @@ BYTES_PER_TEST = 8.125         # float2 point in + 1 label bit out
 NS = (3, 4, 8, 16, 32, 64)
 
 
-# sources of the single-polygon streaming path (the kernels whose HBM traffic
-# profiles/hbm_traffic.json records)
-STREAM_SOURCES = ("device.hpp", "kernels.hpp", "stream.hip", "stream32.hpp", "stream_mfma.hip")
+# device code of the single-polygon streaming kernels (whose HBM traffic
+# profiles/hbm_traffic.json records); the shared declarations header is left out
+STREAM_SOURCES = ("device.hpp", "stream.hip", "stream32.hpp", "stream_mfma.hip")
 
 
 def kernel_source_hash() -> str:
@@ -319,6 +319,25 @@ def run_extras(P, W, torch, stream, check):
                           "fwd_speedup_vs_dense": round(fwd_ms / fwd_c, 2),
                           "bwd_speedup_vs_dense": round(bwd_ms / bwd_c, 2),
                           "bit_identical_to_dense": cull_same}
+    # antipodal pairs (the car footprint is centrally symmetric), alone and
+    # with culling: results differ from the per-edge loop by rounding only
+    for key, cull in (("cost_paired", 0), ("cost_paired_culled", 1)):
+        P.set_option(P.PIP_OPT_COST_PAIR, 1)
+        P.set_option(P.PIP_OPT_COST_CULL, cull)
+        try:
+            fwd_p = _time(torch, stream, lambda: P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws), reps=3)
+            bwd_p = _time(torch, stream,
+                          lambda: P.pip_cost_bwd(F32t, trt, Qdt, ones, workspace=ws), reps=3)
+            c_p = P.pip_cost_fwd(F32t, trt, Qdt, workspace=ws)
+            diff = (c_p - c_dense).abs()
+            rel = float((diff / (c_dense.abs() + 1e-3)).max())
+        finally:
+            P.set_option(P.PIP_OPT_COST_PAIR, 0)
+            P.set_option(P.PIP_OPT_COST_CULL, 0)
+        out[key] = {"fwd_ms": round(fwd_p, 4), "bwd_ms": round(bwd_p, 4),
+                    "fwd_speedup_vs_dense": round(fwd_ms / fwd_p, 2),
+                    "bwd_speedup_vs_dense": round(bwd_ms / bwd_p, 2),
+                    "max_cost_diff_vs_dense": {"abs": float(diff.max()), "rel_to_cost_plus_1e-3": rel}}
     pairs = len(tr) * len(Qd)
     entry = {"poses": len(tr), "points": len(Qd), "pairs": pairs, "fwd_ms": round(fwd_ms, 3),
              "bwd_ms": round(bwd_ms, 3), "fwd_gpairs_per_s": round(pairs / fwd_ms / 1e6, 1),

@@ -119,12 +119,19 @@ typedef struct pip_index_s *pip_index;
  *     margins (Eq. 11) is |t| - h of one affine form t; the remaining
  *     asymmetry is bounded in the float32 band, so labels and counts are those
  *     of the dense evaluation.  Other polygons keep the per-edge table.
- *     Default 0. */
+ *     Default 0.
+ *   PIP_OPT_COST_PAIR: 1 lets pip_cost_fwd / pip_cost_bwd evaluate a
+ *     centrally symmetric footprint (edge normals of i and i + n/2 cancel to
+ *     2^-20) as n/2 pairs: the smaller of the two signed distances is
+ *     h - |t| of one affine form, at edge i when t >= 0.  Costs and gradients
+ *     change by float32 rounding only (they are tolerance-graded); other
+ *     footprints keep the per-edge loop.  Default 0. */
 typedef enum {
     PIP_OPT_MFMA_MIN_EDGES = 1,
     PIP_OPT_ALLPAIRS_CULL = 2,
     PIP_OPT_COST_CULL = 3,
-    PIP_OPT_ALLPAIRS_PAIR = 4
+    PIP_OPT_ALLPAIRS_PAIR = 4,
+    PIP_OPT_COST_PAIR = 5
 } pip_option;
 pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value);
 pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);

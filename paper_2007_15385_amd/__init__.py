@@ -13,7 +13,7 @@ The functions carry the C names: :func:`polygon_to_generators`,
 """
 from __future__ import annotations
 
-from ._lib import (PIP_F32, PIP_F64, PIP_OPT_ALLPAIRS_CULL, PIP_OPT_ALLPAIRS_PAIR, PIP_OPT_COST_CULL, PIP_OPT_MFMA_MIN_EDGES, PipError, lib_path, load_library,
+from ._lib import (PIP_F32, PIP_F64, PIP_OPT_ALLPAIRS_CULL, PIP_OPT_ALLPAIRS_PAIR, PIP_OPT_COST_CULL, PIP_OPT_COST_PAIR, PIP_OPT_MFMA_MIN_EDGES, PipError, lib_path, load_library,
                    num_label_words, status_name)
 from .api import get_option, set_option
 from .api import (BatchedPlan, LocateIndex, allpairs_workspace_bytes, batched_workspace_bytes, label_word_offsets, pip_poses_to_polygons,
@@ -29,5 +29,5 @@ __all__ = [
     "pip_voronoi_batched", "batched_workspace_bytes", "label_word_offsets", "BatchedPlan",
     "LocateIndex",
     "pip_poses_to_polygons", "pip_voronoi_allpairs", "allpairs_workspace_bytes", "pip_cost_fwd", "pip_cost_bwd",
-    "CollisionCost", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "set_option", "get_option",
+    "CollisionCost", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "PIP_OPT_COST_PAIR", "set_option", "get_option",
 ]

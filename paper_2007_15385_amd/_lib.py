@@ -14,6 +14,7 @@ PIP_OPT_MFMA_MIN_EDGES = 1
 PIP_OPT_ALLPAIRS_CULL = 2
 PIP_OPT_COST_CULL = 3
 PIP_OPT_ALLPAIRS_PAIR = 4
+PIP_OPT_COST_PAIR = 5
 
 STATUS_NAMES = {
     0: "PIP_OK", 1: "PIP_EINVAL", 2: "PIP_EDEGENERATE", 3: "PIP_ENONCONVEX", 4: "PIP_EHIP",

@@ -22,6 +22,7 @@ struct pip_ctx_s {
     int allpairs_cull = 0;         // skip (polygon, wave) pairs whose bounding disk misses the points
     int cost_cull = 0;             // skip (pose, wave) pairs of the collision cost likewise
     int allpairs_pair = 0;         // antipodal edge pairs for centrally symmetric polygons
+    int cost_pair = 0;             // the same for the collision cost's footprint
 };
 
 // A plan: one batched request bound to its buffers, its own workspace, the
@@ -729,7 +730,8 @@ pip_status pip_cost_fwd(pip_ctx ctx, const float* footprint, int32_t n, const fl
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_cost(false, footprint, n, pose, K, Q, m, nullptr, cost, nullptr,
-                                       nullptr, nullptr, workspace, ctx->cost_cull, stream);
+                                       nullptr, nullptr, workspace, ctx->cost_cull,
+                                       ctx->cost_pair, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -750,7 +752,8 @@ pip_status pip_cost_bwd(pip_ctx ctx, const float* footprint, int32_t n, const fl
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_cost(true, footprint, n, pose, K, Q, m, grad_cost, nullptr, grad_pose,
-                                       grad_footprint, residual, workspace, ctx->cost_cull, stream);
+                                       grad_footprint, residual, workspace, ctx->cost_cull,
+                                       ctx->cost_pair, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -905,6 +908,10 @@ pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
                 return fail(PIP_EINVAL, "PIP_OPT_ALLPAIRS_PAIR must be 0 or 1");
             ctx->allpairs_pair = (int)value;
             return PIP_OK;
+        case PIP_OPT_COST_PAIR:
+            if (value != 0 && value != 1) return fail(PIP_EINVAL, "PIP_OPT_COST_PAIR must be 0 or 1");
+            ctx->cost_pair = (int)value;
+            return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
@@ -923,6 +930,9 @@ pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
             return PIP_OK;
         case PIP_OPT_ALLPAIRS_PAIR:
             *value = ctx->allpairs_pair;
+            return PIP_OK;
+        case PIP_OPT_COST_PAIR:
+            *value = ctx->cost_pair;
             return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);

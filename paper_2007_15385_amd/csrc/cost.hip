@@ -39,9 +39,11 @@ constexpr int kCostMaxEdges = 16;     // footprint size limit of the cost path
 
 struct CostTab {
     float4 line[kMaxEdges];  // (-n_x, -n_y, k, |h|)
+    float4 pair[kMaxEdges / 2];  // antipodal pairs: (n_x, n_y, -(k_i - k_j) / 2, (k_i + k_j) / 2)
     float2 g0;
     int n, n4, status;
     float rad;  // largest vertex distance from p_0, rounded up (the footprint's disk)
+    int npair;  // > 0: the footprint is centrally symmetric (edges i, i + n/2 antiparallel)
 };
 
 __global__ __launch_bounds__(kWave) void k_cost_prepare(const float* __restrict__ F, int n,
@@ -66,7 +68,34 @@ __global__ __launch_bounds__(kWave) void k_cost_prepare(const float* __restrict_
         dv = sqrt(dx * dx + dy * dy);
     }
     const double rmax = wave_max(dv);
+    // Antipodal pairs: for a centrally symmetric footprint edge j = i + n/2
+    // has n_j = -n_i, so d_i = h - t and d_j = h + t with
+    // t = n_i.p - (k_i - k_j)/2, h = (k_i + k_j)/2: min(d_i, d_j) = h - |t|,
+    // reached at edge i when t >= 0 (the lower index on a tie).  Used when
+    // the normals cancel to 2^-20; the remaining asymmetry changes a distance
+    // by at most 2^-20 |p| against the cost's 1e-4 relative tolerance.
+    int npair = 0;
+    if ((n & 1) == 0) {
+        const int hn = n >> 1;
+        const int q = lane < hn ? lane : 0;
+        auto edge = [&](int e, double& ex, double& ey, double& ek) {
+            const double gx = S.gen[1 + e].x - g0.x, gy = S.gen[1 + e].y - g0.y;
+            const double l = sqrt(gx * gx + gy * gy);
+            ex = gx / l;
+            ey = gy / l;
+            ek = (ex * g0.x + ey * g0.y) + 0.5 * l;
+        };
+        double ax, ay, ak, bx, by, bk;
+        edge(q, ax, ay, ak);
+        edge(q + hn, bx, by, bk);
+        const double asym = wave_max(fmax(fabs(ax + bx), fabs(ay + by)));
+        if (lane < hn)
+            tab->pair[lane] = make_float4((float)(0.5 * (ax - bx)), (float)(0.5 * (ay - by)),
+                                          (float)(-0.5 * (ak - bk)), (float)(0.5 * (ak + bk)));
+        if (asym <= 9.5367431640625e-07 && S.status == 0) npair = hn;  // 2^-20
+    }
     if (lane == 0) {
+        tab->npair = npair;
         tab->rad = round_up_f32(rmax * (1.0 + 1.0 / 65536.0) + 1e-30);  // NaN -> +inf
         tab->g0 = make_float2((float)g0.x, (float)g0.y);
         tab->n = n;
@@ -100,7 +129,7 @@ __device__ __forceinline__ float wave_sum(float v) {
 // grid: x = point tiles, y = pose groups of kPG.  CULL: a (pose, wave) pair
 // whose footprint disk misses the wave's points contributes exactly zero
 // (no point inside, relu of a non-positive minimum) and is skipped.
-template <bool BWD, bool CULL>
+template <bool BWD, bool CULL, bool PAIR>
 __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab,
                                                const float* __restrict__ pose, int64_t K,
                                                const float2* __restrict__ Q, int64_t m,
@@ -109,6 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
                                                float* __restrict__ part_pose,
                                                float* __restrict__ part_gen, int T) {
     __shared__ float4 line_s[kMaxEdges];
+    __shared__ float4 pair_s[kMaxEdges / 2];
     __shared__ PoseCS pose_s[kPG];
     __shared__ float red_s[kPG][kWavesPerBlock][3];
     // backward only: per-lane accumulators [wave][component][lane], 2(n+1)
@@ -124,6 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
     const int t = blockIdx.x;
 
     if (tid < n4) line_s[tid] = tab->line[tid];
+    const int np = PAIR ? tab->npair : 0;
+    if (PAIR && tid < np) pair_s[tid] = tab->pair[tid];
     if (tid < pg) {
         const float* pp = pose + 3 * (k0 + tid);
         const double th = (double)pp[2];
@@ -221,18 +253,37 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
             dmin[j] = __builtin_huge_valf();
             arg[j] = 0;
         }
-        for (int e = 0; e < n; ++e) {
-            const float4 L = line_s[e];
+        if (PAIR && np > 0) {
+            for (int q = 0; q < np; ++q) {
+                const float4 L = pair_s[q];
 #pragma unroll
-            for (int j = 0; j < kPPL; ++j) {
-                const float d = fmaf(L.x, bx[j], fmaf(L.y, by[j], L.z));
-                if constexpr (BWD) {
-                    if (d < dmin[j]) {
-                        dmin[j] = d;
-                        arg[j] = e;
+                for (int j = 0; j < kPPL; ++j) {
+                    const float tq = fmaf(L.x, bx[j], fmaf(L.y, by[j], L.z));
+                    const float d = L.w - fabsf(tq);
+                    if constexpr (BWD) {
+                        if (d < dmin[j]) {
+                            dmin[j] = d;
+                            arg[j] = tq < 0.f ? q + np : q;
+                        }
+                    } else {
+                        dmin[j] = fminf(dmin[j], d);
                     }
-                } else {
-                    dmin[j] = fminf(dmin[j], d);
+                }
+            }
+        } else {
+            for (int e = 0; e < n; ++e) {
+                const float4 L = line_s[e];
+#pragma unroll
+                for (int j = 0; j < kPPL; ++j) {
+                    const float d = fmaf(L.x, bx[j], fmaf(L.y, by[j], L.z));
+                    if constexpr (BWD) {
+                        if (d < dmin[j]) {
+                            dmin[j] = d;
+                            arg[j] = e;
+                        }
+                    } else {
+                        dmin[j] = fminf(dmin[j], d);
+                    }
                 }
             }
         }
@@ -479,7 +530,7 @@ size_t cost_workspace_layout(int n, int64_t K, int64_t m, CostLayout* L) {
 hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, int64_t K,
                        const float* Q, int64_t m, const float* grad_cost, float* cost,
                        float* grad_pose, float* grad_F, float* residual, void* ws, int cull,
-                       hipStream_t stream) {
+                       int pair, hipStream_t stream) {
     CostLayout L;
     cost_workspace_layout(n, K, m, &L);
     char* b = static_cast<char*>(ws);
@@ -495,18 +546,12 @@ hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, 
         dim3 grid((unsigned)L.T, (unsigned)L.G);
         const float2* Q2 = reinterpret_cast<const float2*>(Q);
         const size_t lds = (size_t)kWavesPerBlock * 2 * (n + 1) * kWave * sizeof(float);
-        if (!backward && !cull)
-            hipLaunchKernelGGL((k_cost<false, false>), grid, dim3(kBlock), 0, stream, tab, pose, K,
-                               Q2, m, grad_cost, pc, pp, pgn, T);
-        else if (!backward)
-            hipLaunchKernelGGL((k_cost<false, true>), grid, dim3(kBlock), 0, stream, tab, pose, K,
-                               Q2, m, grad_cost, pc, pp, pgn, T);
-        else if (!cull)
-            hipLaunchKernelGGL((k_cost<true, false>), grid, dim3(kBlock), lds, stream, tab, pose, K,
-                               Q2, m, grad_cost, pc, pp, pgn, T);
-        else
-            hipLaunchKernelGGL((k_cost<true, true>), grid, dim3(kBlock), lds, stream, tab, pose, K,
-                               Q2, m, grad_cost, pc, pp, pgn, T);
+        auto kern = backward ? (cull ? (pair ? k_cost<true, true, true> : k_cost<true, true, false>)
+                                     : (pair ? k_cost<true, false, true> : k_cost<true, false, false>))
+                             : (cull ? (pair ? k_cost<false, true, true> : k_cost<false, true, false>)
+                                     : (pair ? k_cost<false, false, true> : k_cost<false, false, false>));
+        hipLaunchKernelGGL(kern, grid, dim3(kBlock), backward ? lds : 0, stream, tab, pose, K, Q2,
+                           m, grad_cost, pc, pp, pgn, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {
         // no points: every partial is zero (a fill kernel, safe under graph capture)

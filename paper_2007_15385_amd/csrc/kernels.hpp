@@ -132,7 +132,7 @@ size_t cost_workspace_layout(int n, int64_t K, int64_t m, CostLayout* L);
 hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, int64_t K,
                        const float* Q, int64_t m, const float* grad_cost, float* cost,
                        float* grad_pose, float* grad_F, float* residual, void* ws, int cull,
-                       hipStream_t stream);
+                       int pair, hipStream_t stream);
 hipError_t launch_count_diff(const uint32_t* a, const uint32_t* b, int64_t nwords,
                              unsigned long long* out, hipStream_t stream);
 hipError_t launch_generators_one(const double* V, int n, double* P, int32_t* status,

@@ -80,7 +80,16 @@ def test_cost_golden_cases(P):
         assert abs(got[0] - case["cost"]) <= 1e-6 * max(1.0, case["cost"]), (case, got)
 
 
-def test_cost_gradient_vs_closed_form_and_fd(P, oracle, scene):
+@pytest.fixture(params=[0, 1], ids=["per-edge", "paired"])
+def pairing(request, P):
+    """Each gradient test runs with the per-edge loop and with antipodal
+    pairs (the car footprint is centrally symmetric)."""
+    P.set_option(P.PIP_OPT_COST_PAIR, request.param)
+    yield request.param
+    P.set_option(P.PIP_OPT_COST_PAIR, 0)
+
+
+def test_cost_gradient_vs_closed_form_and_fd(P, oracle, scene, pairing):
     F, Q, poses = scene
     F64, Q64, p64 = F.astype(np.float64), Q.astype(np.float64), poses.astype(np.float64)
     K = len(poses)
@@ -229,3 +238,55 @@ def test_cost_cull_bit_identical(P):
     for x, y in zip(a, b):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
     assert (a[0] > 0).sum() > 8
+
+
+def _cost_opts(P, F, poses, Q, w, cull, pair):
+    P.set_option(P.PIP_OPT_COST_CULL, cull)
+    P.set_option(P.PIP_OPT_COST_PAIR, pair)
+    try:
+        c = gpu_cost(P, F, poses, Q)
+        gp, gF, res = gpu_grad(P, F, poses, Q, w)
+    finally:
+        P.set_option(P.PIP_OPT_COST_CULL, 0)
+        P.set_option(P.PIP_OPT_COST_PAIR, 0)
+    return c, gp, gF
+
+
+def test_cost_pair_full_size(P, oracle):
+    """Antipodal pairs on the 65,536-pose x 65,536-point configuration: costs
+    within float32 rounding of the per-edge loop (and of the oracle on
+    sampled poses), gradients within the same tolerance as the per-edge loop
+    against the closed form; culling leaves the paired results bit-identical."""
+    F = W.car_footprint().astype(np.float32)
+    Q = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)
+    poses = W.trajectories().reshape(-1, 3)
+    w = np.ones(len(poses), np.float32)
+    d = _cost_opts(P, F, poses, Q, w, 0, 0)
+    p = _cost_opts(P, F, poses, Q, w, 0, 1)
+    pc = _cost_opts(P, F, poses, Q, w, 1, 1)
+    for x, y in zip(p, pc):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert np.all(np.abs(p[0] - d[0]) <= 1e-5 * np.abs(d[0]) + 1e-6)
+    assert not np.array_equal(p[0], d[0])  # the paired arithmetic was used
+    rng = np.random.default_rng(4)
+    idx = rng.choice(len(poses), 256, replace=False)
+    want = oracle.cost(F.astype(np.float64), poses[idx].astype(np.float64), Q.astype(np.float64))
+    assert np.all(np.abs(p[0][idx] - want) <= 1e-4 * np.abs(want) + 1e-6)
+    scale = np.abs(d[1]).max()
+    assert np.abs(p[1] - d[1]).max() <= 1e-3 * scale
+    say(f"[stat] paired cost: max rel diff {float((np.abs(p[0] - d[0]) / np.maximum(d[0], 1e-6)).max()):.2e}, "
+        f"pose grad max diff {float(np.abs(p[1] - d[1]).max()):.2e} of {scale:.2e}")
+
+
+def test_cost_pair_falls_back_for_asymmetric_footprint(P):
+    """A footprint that is not centrally symmetric keeps the per-edge loop:
+    bit-identical with the option on and off."""
+    F = W.car_footprint().astype(np.float32)
+    F[0, 0] += np.float32(0.01)
+    Q = W.lidar_cloud(points_per_ring=256, rings=16, config=5)
+    poses = W.trajectories(T=8).reshape(-1, 3)
+    w = np.ones(len(poses), np.float32)
+    a = _cost_opts(P, F, poses, Q, w, 0, 0)
+    b = _cost_opts(P, F, poses, Q, w, 0, 1)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
