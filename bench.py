@@ -274,13 +274,19 @@ def run_extras(P, W, torch, stream, check):
     index = P.LocateIndex(offl, Vl)
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
-    ids = index.locate(Ql)
-    ms_l = _time(torch, stream, lambda: index.locate(Ql, ids=ids), reps=5)
+    wsl = torch.empty(index.workspace_bytes(Ql.shape[0]), dtype=torch.uint8, device=dev)
+    ids = index.locate(Ql, binned=False)
+    ms_l = _time(torch, stream, lambda: index.locate(Ql, ids=ids, binned=False), reps=5)
+    ids_b = index.locate(Ql, binned=True, workspace=wsl)
+    ms_b = _time(torch, stream, lambda: index.locate(Ql, ids=ids_b, binned=True, workspace=wsl),
+                 reps=5)
     cells, entries = index.info()
     e = {"polygons": len(part.vtx_off) - 1, "points": int(Ql.shape[0]), "cells": cells,
          "entries": entries, "build_ms": round(build_ms, 2), "ms": round(ms_l, 3),
          "gpoints_per_s": round(Ql.shape[0] / ms_l / 1e6, 2),
-         "hbm_frac": round(12.0 * Ql.shape[0] / (ms_l * 1e-3) / 8.0e12, 4)}
+         "binned_ms": round(ms_b, 3), "binned_gpoints_per_s": round(Ql.shape[0] / ms_b / 1e6, 2),
+         "binned_ids_equal": bool(torch.equal(ids, ids_b)),
+         "hbm_frac_binned": round(12.0 * Ql.shape[0] / (ms_b * 1e-3) / 8.0e12, 4)}
     if check:
         sel = np.sort(rng.choice(Ql.shape[0], 4096, replace=False))
         want = o.locate(part.vtx_off, part.V, Ql.cpu().numpy()[sel].astype(np.float64))

@@ -231,6 +231,19 @@ pip_status pip_index_create(pip_ctx ctx, int32_t P, const int64_t *vtx_off, cons
 pip_status pip_index_locate(pip_index index, const float *Q, int64_t m, int32_t *ids,
                             hipStream_t stream);
 
+/* The same query with the points first binned by super-cell (at most 1024
+ * blocks of grid cells, then sorted by cell within each 2048-point tile) so
+ * that neighbouring lanes test the same candidates:
+ * same ids as pip_index_locate.  workspace (device, caller-owned, 256-byte
+ * aligned) holds the bin counts and a 16-byte copy of every point:
+ * pip_index_locate_workspace_bytes(index, m) bytes (0 for a NULL index or
+ * negative m).  Allocates nothing; asynchronous on `stream`.  Errors:
+ * PIP_EINVAL for bad arguments or a short workspace, PIP_EUNSUPPORTED for
+ * m > 2^40. */
+size_t pip_index_locate_workspace_bytes(pip_index index, int64_t m);
+pip_status pip_index_locate_binned(pip_index index, const float *Q, int64_t m, int32_t *ids,
+                                   void *workspace, size_t ws_bytes, hipStream_t stream);
+
 /* Grid cells requested and list entries (cells and the global list). */
 pip_status pip_index_info(pip_index index, int64_t *cells, int64_t *entries);
 

@@ -60,6 +60,8 @@ SIGNATURES = {
     "pip_index_create": (_int, [_vp, _i32, _vp, _vp, _i64, _i64, _vp, _vp, _c.POINTER(_vp)]),
     "pip_index_locate": (_int, [_vp, _vp, _i64, _vp, _vp]),
     "pip_index_info": (_int, [_vp, _c.POINTER(_i64), _c.POINTER(_i64)]),
+    "pip_index_locate_workspace_bytes": (_c.c_size_t, [_vp, _i64]),
+    "pip_index_locate_binned": (_int, [_vp, _vp, _i64, _vp, _vp, _c.c_size_t, _vp]),
     "pip_index_destroy": (None, [_vp]),
     "pip_voronoi_raster": (_int, [_vp, _vp, _i32, _c.c_double, _c.c_double, _c.c_double,
                                   _c.c_double, _i64, _i64, _vp, _vp, _vp]),

@@ -344,15 +344,29 @@ class LocateIndex:
         _check(s, "pip_index_info", self.ctx)
         return int(c.value), int(e.value)
 
-    def locate(self, Q, ids=None):
+    def workspace_bytes(self, m: int) -> int:
+        return int(_lib().pip_index_locate_workspace_bytes(self.handle, int(m)))
+
+    def locate(self, Q, ids=None, binned: bool = True, workspace=None):
+        """ids of the points Q; binned=True sorts the points by super-cell
+        first (needs a workspace, allocated here unless given)."""
         if Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != 2 or not Q.is_contiguous():
             raise ValueError("Q must be a contiguous float32 tensor of shape [m, 2]")
         m = Q.shape[0]
         if ids is None:
             ids = torch.empty(max(m, 1), dtype=torch.int32, device=Q.device)
-        s = _lib().pip_index_locate(self.handle, Q.data_ptr() if m else None, m, ids.data_ptr(),
-                                    _stream(self.device))
-        _check(s, "pip_index_locate", self.ctx)
+        if binned and m > 0:
+            need = self.workspace_bytes(m)
+            if workspace is None:
+                workspace = torch.empty(need, dtype=torch.uint8, device=Q.device)
+            s = _lib().pip_index_locate_binned(self.handle, Q.data_ptr(), m, ids.data_ptr(),
+                                               workspace.data_ptr(), workspace.numel(),
+                                               _stream(self.device))
+            _check(s, "pip_index_locate_binned", self.ctx)
+        else:
+            s = _lib().pip_index_locate(self.handle, Q.data_ptr() if m else None, m,
+                                        ids.data_ptr(), _stream(self.device))
+            _check(s, "pip_index_locate", self.ctx)
         return ids[:m]
 
     def close(self):

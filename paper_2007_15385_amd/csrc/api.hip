@@ -32,6 +32,7 @@ struct pip_index_s {
     int64_t P = 0, cells = 0, entries = 0;
     void* mem = nullptr;       // records, rows, generators, grid, counters, offsets
     void* list_mem = nullptr;  // cell lists (sized after counting)
+    int sf = 1, sgx = 1, nbins = 1;  // super-cells of the binned query (sf x sf cells each)
     pipdev::LocRec* rec = nullptr;
     float4* qrec = nullptr;
     double2* gen = nullptr;
@@ -840,6 +841,18 @@ pip_status pip_index_create(pip_ctx ctx, int32_t P, const int64_t* vtx_off, cons
         pip_index_destroy(x);
         return fail(PIP_EUNSUPPORTED, "a polygon has more than %d vertices", PIP_MAX_EDGES);
     }
+    {  // super-cells for binned queries: at most 1024, about square in cells
+        pipdev::LocGrid hg;
+        if ((e = hipMemcpy(&hg, x->grid, sizeof(hg), hipMemcpyDeviceToHost)) != hipSuccess) {
+            pip_index_destroy(x);
+            return hip_fail(e, "reading the grid");
+        }
+        int sf = 1;
+        while ((int64_t)((hg.gx + sf - 1) / sf) * ((hg.gy + sf - 1) / sf) > 1024) ++sf;
+        x->sf = sf;
+        x->sgx = (hg.gx + sf - 1) / sf;
+        x->nbins = x->sgx * ((hg.gy + sf - 1) / sf);
+    }
     if (htotal >= (1ull << 31)) {
         pip_index_destroy(x);
         return fail(PIP_EUNSUPPORTED, "%llu cell entries: use fewer cells", htotal);
@@ -875,6 +888,32 @@ pip_status pip_index_locate(pip_index x, const float* Q, int64_t m, int32_t* ids
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_locate(x->qrec, x->gen, x->grid, x->cell_off, x->list, Q, m, ids,
                                          x->blocks, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+size_t pip_index_locate_workspace_bytes(pip_index x, int64_t m) {
+    if (!x || m < 0) return 0;
+    size_t a, b, c, d;
+    return pipdev::locate_binned_workspace(x->nbins, m, &a, &b, &c, &d);
+}
+
+pip_status pip_index_locate_binned(pip_index x, const float* Q, int64_t m, int32_t* ids,
+                                   void* workspace, size_t ws_bytes, hipStream_t stream) {
+    if (!x) return fail(PIP_EINVAL, "index is NULL");
+    if (m < 0) return fail(PIP_EINVAL, "m = %lld is negative", (long long)m);
+    if (m > (int64_t(1) << 40)) return fail(PIP_EUNSUPPORTED, "m = %lld is too large", (long long)m);
+    if (m > 0 && (!Q || !aligned(Q, 8))) return fail(PIP_EINVAL, "Q is NULL or not 8-byte aligned");
+    if (m > 0 && (!ids || !aligned(ids, 4))) return fail(PIP_EINVAL, "ids is NULL or misaligned");
+    if (m == 0) return PIP_OK;
+    const size_t need = pip_index_locate_workspace_bytes(x, m);
+    if (!workspace || !aligned(workspace, 256) || ws_bytes < need)
+        return fail(PIP_EINVAL, "workspace must be 256-byte aligned with >= %zu bytes", need);
+    DeviceGuard g(x->ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_locate_binned(x->qrec, x->gen, x->grid, x->cell_off, x->list, x->sf,
+                                                x->sgx, x->nbins, Q, m, ids, workspace,
+                                                x->ctx->cu_count, x->blocks, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }

@@ -114,6 +114,12 @@ hipError_t launch_locate(const float4* qrec, const double2* gen, const LocGrid* 
                          const int32_t* cell_off, const LocEntry* list, const float* Q, int64_t m,
                          int32_t* ids, int max_blocks, hipStream_t stream);
 hipError_t locate_max_blocks_per_cu(int* out);
+size_t locate_binned_workspace(int nbins, int64_t m, size_t* o_cnt, size_t* o_off, size_t* o_fill,
+                               size_t* o_pts);
+hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const LocGrid* grid,
+                                const int32_t* cell_off, const LocEntry* list, int sf, int sgx,
+                                int nbins, const float* Q, int64_t m, int32_t* ids, void* ws,
+                                int cus, int max_blocks, hipStream_t stream);
 // Coverage raster: pixel (i, j) = (x0 + i dx, y0 + j dy), binary64.
 struct RasterGrid {
     double x0, y0, dx, dy;

@@ -277,6 +277,48 @@ __global__ __launch_bounds__(1024) void k_index_scan(int64_t C, const int32_t* _
     if (C == 0 && t == 0) off[0] = 0;
 }
 
+// Smallest index of a polygon containing p, or -1: the candidates of p's
+// cell (their boxes first: only box hits read a record), then the global
+// list.  Each candidate: float32 screen, binary64 replay inside the band; a
+// NaN box (non-finite vertices) never rejects.
+__device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
+                                            const int32_t* __restrict__ cell_off,
+                                            const LocEntry* __restrict__ list,
+                                            const float4* __restrict__ qrec,
+                                            const double2* __restrict__ gen, int gbeg, int gend) {
+    int id = -1;
+    auto test = [&](int t) {
+        const float4 box = *reinterpret_cast<const float4*>(&list[t]);
+        if (p.x < box.x || p.y < box.y || p.x > box.z || p.y > box.w) return;
+        const int2 kq = *reinterpret_cast<const int2*>(&list[t].k);
+        if (id >= 0 && kq.x > id) return;  // cannot lower the answer
+        const float4* r = qrec + kq.y;
+        const float4 h0 = r[0], h1 = r[1];
+        const int nn = __float_as_int(h1.z);
+        const int n = nn & 0xffff, n4 = nn >> 16;
+        const float X = p.x - h0.x, Y = p.y - h0.y;
+        float M = -__builtin_huge_valf();
+        for (int e = 0; e < n4; ++e) {
+            const float4 c = r[2 + e];
+            M = fmaxf(M, fmaf(c.x, X, fmaf(c.y, Y, c.z)));
+        }
+        const float E =
+            fmaf(h0.z, fmaf(X, X, Y * Y), fmaf(h0.w, fabsf(X), fmaf(h1.x, fabsf(Y), h1.y)));
+        bool in = M < -E;
+        if (!(fabsf(M) > E)) in = voronoi64((double)p.x, (double)p.y, gen + __float_as_int(h1.w), n);
+        if (in) id = kq.x;
+    };
+    // outside the union of the cell boxes (or NaN): only the global list
+    if (G.any && p.x >= G.x0 && p.x <= G.x1 && p.y >= G.y0 && p.y <= G.y1) {
+        const int64_t c =
+            (int64_t)cell_of(p.y, G.y0, G.inv_h, G.gy) * G.gx + cell_of(p.x, G.x0, G.inv_w, G.gx);
+        const int beg = cell_off[c], end = cell_off[c + 1];
+        for (int t = beg; t < end; ++t) test(t);
+    }
+    for (int t = gbeg; t < gend; ++t) test(t);
+    return id;
+}
+
 __global__ __launch_bounds__(kBlock) void k_locate(const float4* __restrict__ qrec,
                                                  const double2* __restrict__ gen,
                                                  const LocGrid* __restrict__ grid,
@@ -290,41 +332,184 @@ __global__ __launch_bounds__(kBlock) void k_locate(const float4* __restrict__ qr
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
         const vfloat2 pv = __builtin_nontemporal_load(reinterpret_cast<const vfloat2*>(Q) + i);
-        const float2 p = make_float2(pv.x, pv.y);
-        int id = -1;
-        // entry t's polygon contains p (box, float32 screen, binary64 inside
-        // the band); a NaN box (non-finite vertices) never rejects
-        auto test = [&](int t) {
-            const float4 box = *reinterpret_cast<const float4*>(&list[t]);
-            if (p.x < box.x || p.y < box.y || p.x > box.z || p.y > box.w) return;
-            const int2 kq = *reinterpret_cast<const int2*>(&list[t].k);
-            if (id >= 0 && kq.x > id) return;  // cannot lower the answer
-            const float4* r = qrec + kq.y;
-            const float4 h0 = r[0], h1 = r[1];
-            const int nn = __float_as_int(h1.z);
-            const int n = nn & 0xffff, n4 = nn >> 16;
-            const float X = p.x - h0.x, Y = p.y - h0.y;
-            float M = -__builtin_huge_valf();
-            for (int e = 0; e < n4; ++e) {
-                const float4 c = r[2 + e];
-                M = fmaxf(M, fmaf(c.x, X, fmaf(c.y, Y, c.z)));
-            }
-            const float E =
-                fmaf(h0.z, fmaf(X, X, Y * Y), fmaf(h0.w, fabsf(X), fmaf(h1.x, fabsf(Y), h1.y)));
-            bool in = M < -E;
-            if (!(fabsf(M) > E))
-                in = voronoi64((double)p.x, (double)p.y, gen + __float_as_int(h1.w), n);
-            if (in) id = kq.x;
-        };
-        // outside the union of the cell boxes (or NaN): only the global list
-        if (G.any && p.x >= G.x0 && p.x <= G.x1 && p.y >= G.y0 && p.y <= G.y1) {
-            const int64_t c =
-                (int64_t)cell_of(p.y, G.y0, G.inv_h, G.gy) * G.gx + cell_of(p.x, G.x0, G.inv_w, G.gx);
-            const int beg = cell_off[c], end = cell_off[c + 1];
-            for (int t = beg; t < end; ++t) test(t);
+        ids[i] = locate_point(make_float2(pv.x, pv.y), G, cell_off, list, qrec, gen, gbeg, gend);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Coherent queries: the points are first binned by super-cell (sf x sf grid
+// cells; bin nbins = outside the grid's box or NaN), so that the lanes of a
+// wave share a few cells and their candidate loads hit the caches.
+//   k_bin_points<false>  per-block LDS histogram of the bins, added to the
+//                        global counts once per block;
+//   k_bin_points<true>   the same histogram per tile, a global reservation per
+//                        (tile, bin), then each point written to its slot;
+//   k_locate_binned      binned points in order, ids written back by index.
+// ---------------------------------------------------------------------------
+constexpr int kBinPer = 16;                  // points per thread per tile
+constexpr int kBinTile = kBlock * kBinPer;   // 4096 points
+
+struct BinnedPt {
+    float x, y;
+    int32_t idx, pad;
+};
+
+__device__ __forceinline__ int bin_of(float2 p, const LocGrid& G, int sf, int sgx, int nbins) {
+    if (!(G.any && p.x >= G.x0 && p.x <= G.x1 && p.y >= G.y0 && p.y <= G.y1)) return nbins;
+    const int cy = cell_of(p.y, G.y0, G.inv_h, G.gy), cx = cell_of(p.x, G.x0, G.inv_w, G.gx);
+    return (cy / sf) * sgx + cx / sf;
+}
+
+template <bool SCATTER>
+__global__ __launch_bounds__(kBlock) void k_bin_points(const float2* __restrict__ Q, int64_t m,
+                                                     const LocGrid* __restrict__ grid, int sf,
+                                                     int sgx, int nbins,
+                                                     int32_t* __restrict__ bin_cnt,
+                                                     const int32_t* __restrict__ bin_off,
+                                                     int32_t* __restrict__ bin_fill,
+                                                     BinnedPt* __restrict__ binned) {
+    extern __shared__ int32_t hist[];  // [nbins + 1] (+ [nbins + 1] bases when scattering)
+    int32_t* base = hist + (nbins + 1);
+    const int tid = threadIdx.x;
+    const LocGrid G = *grid;
+    const int64_t ntiles = (m + kBinTile - 1) / kBinTile;
+    if (!SCATTER) {
+        for (int b = tid; b <= nbins; b += kBlock) hist[b] = 0;
+        __syncthreads();
+    }
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (SCATTER) {
+            for (int b = tid; b <= nbins; b += kBlock) hist[b] = 0;
+            __syncthreads();
         }
-        for (int t = gbeg; t < gend; ++t) test(t);
-        ids[i] = id;
+        const int64_t i0 = tile * kBinTile;
+        int bin[kBinPer], slot[kBinPer];
+        float2 pt[kBinPer];
+#pragma unroll
+        for (int j = 0; j < kBinPer; ++j) {
+            const int64_t i = i0 + j * kBlock + tid;
+            bin[j] = -1;
+            if (i < m) {
+                const vfloat2 pv =
+                    __builtin_nontemporal_load(reinterpret_cast<const vfloat2*>(Q) + i);
+                pt[j] = make_float2(pv.x, pv.y);
+                bin[j] = bin_of(pt[j], G, sf, sgx, nbins);
+                slot[j] = atomicAdd(&hist[bin[j]], 1);
+            }
+        }
+        if (SCATTER) {
+            __syncthreads();
+            for (int b = tid; b <= nbins; b += kBlock)
+                base[b] = hist[b] ? bin_off[b] + atomicAdd(&bin_fill[b], hist[b]) : 0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kBinPer; ++j) {
+                if (bin[j] >= 0) {
+                    BinnedPt e;
+                    e.x = pt[j].x;
+                    e.y = pt[j].y;
+                    e.idx = (int32_t)(j * kBlock + tid);  // within the tile
+                    e.pad = (int32_t)tile;
+                    binned[base[bin[j]] + slot[j]] = e;
+                }
+            }
+            __syncthreads();  // hist and base are reused by the next tile
+        }
+    }
+    if (!SCATTER) {
+        __syncthreads();
+        for (int b = tid; b <= nbins; b += kBlock)
+            if (hist[b]) atomicAdd(&bin_cnt[b], hist[b]);
+    }
+}
+
+// Binned points, a tile of kLocTile at a time: the tile is counting-sorted
+// in LDS by the point's cell within its super-cell (sf * sf keys, one more
+// for points outside the grid's box), so consecutive lanes share a cell and
+// its candidates' loads are broadcasts; ids are written back by index.
+constexpr int kLocPer = 8;
+constexpr int kLocTile = kBlock * kLocPer;  // 2048 points
+constexpr int kMaxKeys = 1025;              // sf <= 32
+constexpr int kScanPer = (kMaxKeys + kBlock - 1) / kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_locate_binned(const float4* __restrict__ qrec,
+                                                        const double2* __restrict__ gen,
+                                                        const LocGrid* __restrict__ grid,
+                                                        const int32_t* __restrict__ cell_off,
+                                                        const LocEntry* __restrict__ list,
+                                                        const BinnedPt* __restrict__ binned,
+                                                        int64_t m, int sf,
+                                                        int32_t* __restrict__ ids) {
+    __shared__ BinnedPt sorted_s[kLocTile];
+    __shared__ int32_t key_s[kMaxKeys];
+    __shared__ int32_t part_s[kBlock];
+    const int tid = threadIdx.x;
+    const LocGrid G = *grid;
+    const int64_t C = (int64_t)G.gx * G.gy;
+    const int gbeg = cell_off[C], gend = cell_off[C + 1];
+    const bool local = sf <= 32;
+    const int nkeys = local ? sf * sf + 1 : 1;
+    const int64_t ntiles = (m + kLocTile - 1) / kLocTile;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t i0 = tile * kLocTile;
+        const int cnt = (int)(m - i0 < kLocTile ? m - i0 : kLocTile);
+        for (int k = tid; k < nkeys; k += kBlock) key_s[k] = 0;
+        __syncthreads();
+        BinnedPt e[kLocPer];
+        int key[kLocPer], slot[kLocPer];
+#pragma unroll
+        for (int j = 0; j < kLocPer; ++j) {
+            const int q = j * kBlock + tid;
+            key[j] = -1;
+            if (q < cnt) {
+                e[j] = binned[i0 + q];
+                const float2 p = make_float2(e[j].x, e[j].y);
+                int k = nkeys - 1;  // outside the box (or NaN)
+                if (local && G.any && p.x >= G.x0 && p.x <= G.x1 && p.y >= G.y0 && p.y <= G.y1)
+                    k = (cell_of(p.y, G.y0, G.inv_h, G.gy) % sf) * sf + cell_of(p.x, G.x0, G.inv_w, G.gx) % sf;
+                key[j] = k;
+                slot[j] = atomicAdd(&key_s[k], 1);
+            }
+        }
+        __syncthreads();
+        // exclusive scan of the key counts: kScanPer keys per thread
+        int run = 0;
+        for (int u = 0; u < kScanPer; ++u) {
+            const int k = tid * kScanPer + u;
+            if (k < nkeys) run += key_s[k];
+        }
+        part_s[tid] = run;
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int t = 0; t < kBlock; ++t) {
+                const int v = part_s[t];
+                part_s[t] = acc;
+                acc += v;
+            }
+        }
+        __syncthreads();
+        int acc = part_s[tid];
+        for (int u = 0; u < kScanPer; ++u) {
+            const int k = tid * kScanPer + u;
+            if (k < nkeys) {
+                const int v = key_s[k];
+                key_s[k] = acc;
+                acc += v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kLocPer; ++j)
+            if (key[j] >= 0) sorted_s[key_s[key[j]] + slot[j]] = e[j];
+        __syncthreads();
+        for (int q = tid; q < cnt; q += kBlock) {
+            const BinnedPt b = sorted_s[q];
+            const int id =
+                locate_point(make_float2(b.x, b.y), G, cell_off, list, qrec, gen, gbeg, gend);
+            ids[(int64_t)b.pad * kBinTile + b.idx] = id;
+        }
+        __syncthreads();  // the tile's LDS is reused
     }
 }
 
@@ -378,6 +563,53 @@ hipError_t launch_locate(const float4* qrec, const double2* gen, const LocGrid* 
     const int grid_blocks = (int)(want < max_blocks ? want : max_blocks);
     hipLaunchKernelGGL(k_locate, dim3(grid_blocks), dim3(kBlock), 0, stream, qrec, gen, grid,
                        cell_off, list, reinterpret_cast<const float2*>(Q), m, ids);
+    return hipGetLastError();
+}
+
+// Workspace of a binned query of m points with nbins super-cells.
+size_t locate_binned_workspace(int nbins, int64_t m, size_t* o_cnt, size_t* o_off, size_t* o_fill,
+                               size_t* o_pts) {
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    size_t off = 0;
+    *o_cnt = off;
+    off = up(off + 4 * (size_t)(nbins + 1));
+    *o_off = off;
+    off = up(off + 4 * (size_t)(nbins + 2));
+    *o_fill = off;
+    off = up(off + 4 * (size_t)(nbins + 1));
+    *o_pts = off;
+    off = up(off + sizeof(BinnedPt) * (size_t)(m > 0 ? m : 1));
+    return off;
+}
+
+hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const LocGrid* grid,
+                                const int32_t* cell_off, const LocEntry* list, int sf, int sgx,
+                                int nbins, const float* Q, int64_t m, int32_t* ids, void* ws,
+                                int cus, int max_blocks, hipStream_t stream) {
+    if (m == 0) return hipSuccess;
+    size_t o_cnt, o_off, o_fill, o_pts;
+    locate_binned_workspace(nbins, m, &o_cnt, &o_off, &o_fill, &o_pts);
+    char* b = static_cast<char*>(ws);
+    int32_t* cnt = reinterpret_cast<int32_t*>(b + o_cnt);
+    int32_t* boff = reinterpret_cast<int32_t*>(b + o_off);
+    int32_t* fill = reinterpret_cast<int32_t*>(b + o_fill);
+    BinnedPt* pts = reinterpret_cast<BinnedPt*>(b + o_pts);
+    const float2* Q2 = reinterpret_cast<const float2*>(Q);
+    const unsigned zb = (unsigned)((nbins + 1 + 255) / 256);
+    hipLaunchKernelGGL(k_index_zero, dim3(zb), dim3(256), 0, stream, cnt, (int64_t)(nbins + 1));
+    hipLaunchKernelGGL(k_index_zero, dim3(zb), dim3(256), 0, stream, fill, (int64_t)(nbins + 1));
+    const int64_t ntiles = (m + kBinTile - 1) / kBinTile;
+    const int64_t bmax = (int64_t)cus * 4;
+    const unsigned bb = (unsigned)(ntiles < bmax ? ntiles : bmax);
+    hipLaunchKernelGGL(k_bin_points<false>, dim3(bb), dim3(kBlock), 4 * (size_t)(nbins + 1), stream,
+                       Q2, m, grid, sf, sgx, nbins, cnt, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL(k_index_scan, dim3(1), dim3(1024), 0, stream, (int64_t)(nbins + 1), cnt, boff);
+    hipLaunchKernelGGL(k_bin_points<true>, dim3(bb), dim3(kBlock), 8 * (size_t)(nbins + 1), stream,
+                       Q2, m, grid, sf, sgx, nbins, nullptr, boff, fill, pts);
+    const int64_t want = (m + kLocTile - 1) / kLocTile;
+    const int gl = (int)(want < max_blocks ? want : max_blocks);
+    hipLaunchKernelGGL(k_locate_binned, dim3(gl), dim3(kBlock), 0, stream, qrec, gen, grid, cell_off,
+                       list, pts, m, sf, ids);
     return hipGetLastError();
 }
 

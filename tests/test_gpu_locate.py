@@ -1,7 +1,7 @@
 """GPU parity of the point-location index against the brute-force FP64
 oracle: every id equal (smallest containing polygon index, or -1), for
 partitions, overlapping and degenerate polygon sets, several grid shapes and
-the full-size partition."""
+the full-size partition; the plain and the binned query give the same ids."""
 from __future__ import annotations
 
 import json
@@ -36,9 +36,12 @@ def locate_gpu(P, off, V, Q, cells=0, status=None):
     idx = P.LocateIndex(torch.from_numpy(np.asarray(off, np.int64)).cuda(),
                         torch.from_numpy(np.ascontiguousarray(V, np.float64)).cuda(), cells=cells,
                         status=status)
-    ids = idx.locate(torch.from_numpy(np.ascontiguousarray(Q, np.float32)).cuda())
+    Qt = torch.from_numpy(np.ascontiguousarray(Q, np.float32)).cuda()
+    ids = idx.locate(Qt, binned=False)
+    ids_b = idx.locate(Qt, binned=True)  # points binned by super-cell first
     torch.cuda.synchronize()
     out = ids.cpu().numpy()
+    assert np.array_equal(out, ids_b.cpu().numpy()), "binned query differs"
     info = idx.info()
     idx.close()
     return out, info
