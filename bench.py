@@ -359,6 +359,22 @@ def run_extras(P, W, torch, stream, check):
     return out
 
 
+def gpu_info(torch) -> dict:
+    """Device name and the clocks rocm-smi reports right after the timed work
+    (clocks are not pinned)."""
+    info = {"name": torch.cuda.get_device_name(0)}
+    try:
+        import subprocess
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True, text=True,
+                           timeout=30)
+        data = json.loads(r.stdout) if r.returncode == 0 else {}
+        card = next(iter(data.values()), {}) if isinstance(data, dict) else {}
+        info["clocks"] = {k: v for k, v in card.items() if "clk" in k.lower()}
+    except Exception as e:  # the clock query is informational only
+        info["clocks"] = f"unavailable: {type(e).__name__}"
+    return info
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -569,6 +585,7 @@ def main() -> int:
         comparisons["fp32_plain_mismatches_on_sample"] = plain_mismatches
 
     extras = {} if args.no_extras else run_extras(P, W, torch, stream, not args.no_cpu)
+    gpu = gpu_info(torch)
 
     out = {
         "metric": "G point-polygon tests/s (Voronoi, certified float32 screen + binary64 "
@@ -593,6 +610,7 @@ def main() -> int:
         "kernels": kernels,
         "comparisons": comparisons,
         "cpu_baseline": cpu,
+        "gpu": gpu,
         "workloads": extras,
     }
     print(json.dumps(out), flush=True)

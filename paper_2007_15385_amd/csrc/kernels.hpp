@@ -90,12 +90,12 @@ struct alignas(16) LocRec {
     int status;            // pip_status of the polygon
     int usable;            // 0: contains no point; 1: in the grid cells; 2: global list
 };
-// Cell-list entry: the polygon's box, index and query-record offset (float4
-// units): record = {ox, oy, KQ, KA}, {KB, KC, n | n4 << 16, generator
-// offset}, then n4 coefficient rows.
+// Cell-list entry: the polygon's box, index, query-record offset (float4
+// units) and edge counts: record = {ox, oy, KQ, KA}, {KB, KC, n | n4 << 16,
+// generator offset}, then n4 coefficient rows.
 struct alignas(32) LocEntry {
     float bx0, by0, bx1, by1;
-    int k, qoff, pad0, pad1;
+    int k, qoff, nn, pad;  // nn = n | n4 << 16
 };
 struct LocGrid {
     float x0, y0, x1, y1;  // union of the cell-listed boxes

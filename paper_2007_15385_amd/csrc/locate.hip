@@ -227,7 +227,8 @@ __global__ void k_index_cells(int64_t P, const LocRec* __restrict__ rec,
     en.by1 = R.by1;
     en.k = (int)k;
     en.qoff = (int)R.qoff;
-    en.pad0 = en.pad1 = 0;
+    en.nn = R.n | (R.n4 << 16);
+    en.pad = 0;
     if (R.usable == 2) {  // global list: its count sits after the cells'
         const int64_t C = (int64_t)grid->gx * grid->gy;
         if (!FILL) atomicAdd(total, 1ull);
@@ -287,18 +288,20 @@ __device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
                                             const float4* __restrict__ qrec,
                                             const double2* __restrict__ gen, int gbeg, int gend) {
     int id = -1;
-    auto test = [&](int t) {
-        const float4 box = *reinterpret_cast<const float4*>(&list[t]);
-        if (p.x < box.x || p.y < box.y || p.x > box.z || p.y > box.w) return;
-        const int2 kq = *reinterpret_cast<const int2*>(&list[t].k);
-        if (id >= 0 && kq.x > id) return;  // cannot lower the answer
-        const float4* r = qrec + kq.y;
-        const float4 h0 = r[0], h1 = r[1];
-        const int nn = __float_as_int(h1.z);
+    // polygon k (record at qoff) contains p: float32 screen, binary64 inside the band
+    auto inside = [&](int qoff, int nn) -> bool {
+        const float4* r = qrec + qoff;
         const int n = nn & 0xffff, n4 = nn >> 16;
+        // the header and the first four rows in one round trip
+        const float4 h0 = r[0], h1 = r[1];
+        float4 c4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) c4[e] = r[2 + (e < n4 ? e : 0)];
         const float X = p.x - h0.x, Y = p.y - h0.y;
         float M = -__builtin_huge_valf();
-        for (int e = 0; e < n4; ++e) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) M = fmaxf(M, fmaf(c4[e].x, X, fmaf(c4[e].y, Y, c4[e].z)));
+        for (int e = 4; e < n4; ++e) {
             const float4 c = r[2 + e];
             M = fmaxf(M, fmaf(c.x, X, fmaf(c.y, Y, c.z)));
         }
@@ -306,16 +309,37 @@ __device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
             fmaf(h0.z, fmaf(X, X, Y * Y), fmaf(h0.w, fabsf(X), fmaf(h1.x, fabsf(Y), h1.y)));
         bool in = M < -E;
         if (!(fabsf(M) > E)) in = voronoi64((double)p.x, (double)p.y, gen + __float_as_int(h1.w), n);
-        if (in) id = kq.x;
+        return in;
+    };
+    // entries [beg, end): four at a time, their boxes and indices loaded
+    // together (one memory round trip), then the records of the box hits
+    auto scan = [&](int beg, int end) {
+        for (int t = beg; t < end; t += 4) {
+            float4 box[4];
+            int4 kq[4];  // k, qoff, n | n4 << 16
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int tu = t + u < end ? t + u : t;
+                box[u] = *reinterpret_cast<const float4*>(&list[tu]);
+                kq[u] = *reinterpret_cast<const int4*>(&list[tu].k);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (t + u >= end) break;
+                // a NaN box (non-finite vertices) never rejects
+                if (p.x < box[u].x || p.y < box[u].y || p.x > box[u].z || p.y > box[u].w) continue;
+                if (id >= 0 && kq[u].x > id) continue;  // cannot lower the answer
+                if (inside(kq[u].y, kq[u].z)) id = kq[u].x;
+            }
+        }
     };
     // outside the union of the cell boxes (or NaN): only the global list
     if (G.any && p.x >= G.x0 && p.x <= G.x1 && p.y >= G.y0 && p.y <= G.y1) {
         const int64_t c =
             (int64_t)cell_of(p.y, G.y0, G.inv_h, G.gy) * G.gx + cell_of(p.x, G.x0, G.inv_w, G.gx);
-        const int beg = cell_off[c], end = cell_off[c + 1];
-        for (int t = beg; t < end; ++t) test(t);
+        scan(cell_off[c], cell_off[c + 1]);
     }
-    for (int t = gbeg; t < gend; ++t) test(t);
+    scan(gbeg, gend);
     return id;
 }
 
