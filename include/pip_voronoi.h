@@ -13,6 +13,17 @@
  *   - sign of offset (Section 2.2, Algorithm 2), convex polygons;
  *   - ray crossing (Section 2.1, Algorithm 1), any simple polygon.
  *
+ * Entry points, by use:
+ *   - one polygon against a point array: pip_voronoi, pip_sign_of_offset,
+ *     pip_ray_crossing, pip_voronoi_fp32_plain (speed reference),
+ *     pip_voronoi_max_margin, polygon_to_generators; against a pixel grid
+ *     (Section 1's rasterisation): pip_voronoi_raster;
+ *   - many polygons: pip_voronoi_batched and its plans (pip_plan_*), each
+ *     polygon against its own points; pip_poses_to_polygons and
+ *     pip_voronoi_allpairs, one footprint at many poses against one cloud;
+ *     pip_index_* (Section 1's GIS use), the polygon containing each point;
+ *   - the differentiable collision cost: pip_cost_fwd, pip_cost_bwd.
+ *
  * Conventions shared by every entry point
  *   - Polygons: binary64 vertices v_0..v_{n-1}, interleaved x,y ([n][2]), in
  *     cyclic order, either orientation.  Edge i runs from v_{i-1} to v_i
@@ -33,7 +44,9 @@
  *     not allocate.
  *   - Streams: every compute call only enqueues work on `stream` (a
  *     hipStream_t; NULL is the default stream) and returns; results are ready
- *     when the stream has reached that point.
+ *     when the stream has reached that point.  Plan and index creation
+ *     (pip_plan_create_batched, pip_plan_autotune, pip_index_create)
+ *     allocate and synchronize.
  *   - Errors: argument errors are detected on the host before anything is
  *     enqueued and returned as a pip_status; pip_last_error() then holds a
  *     sentence naming the argument.  Data-dependent problems of a polygon
