@@ -381,7 +381,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--points", type=int, default=1 << 28, help="points per polygon")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26,
+    ap.add_argument("--cpu-sample", type=int, default=1 << 28,
                     help="points per polygon for the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -541,7 +541,7 @@ def main() -> int:
     if not args.no_cpu:
         from oracle import Oracle, pack_bits
         o = Oracle()
-        S = int(args.cpu_sample)
+        S = int(min(args.cpu_sample, m))
         cpu_t = 0.0
         mismatches = 0
         plain_mismatches = 0
@@ -575,8 +575,9 @@ def main() -> int:
             pass
         cpu = {"value": round(S * len(NS) / cpu_t / 1e9, 5), "unit": "G tests/s",
                "cores": threads, "kind": "oracle",
-               "sample": f"first {S} points of each of the 6 polygons' arrays "
-                         f"({S * len(NS)} tests), FP64 C oracle, OpenMP over points",
+               "sample": (f"all {S} points of each of the 6 polygons (the whole sweep, "
+                          if S == m else f"first {S} points of each of the 6 polygons' arrays (")
+                         + f"{S * len(NS)} tests), FP64 C oracle, OpenMP over points",
                "seconds": round(cpu_t, 2),
                "per_core_gtests_per_s": round(S * len(NS) / cpu_t / 1e9 / threads, 5),
                "single_thread_gtests_per_s": round(s1 * len(NS) / t1 / 1e9, 5),
