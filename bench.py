@@ -223,6 +223,17 @@ def run_extras(P, W, torch, stream, check):
     out["allpairs_culled"] = {"ms": round(ms_c, 4), "speedup_vs_dense": round(ms / ms_c, 2),
                               "dense_equivalent_gtests_per_s": round(nt / ms_c / 1e6, 1),
                               "labels_and_counts_equal_dense": same}
+    # autotuned, graph-captured plan over the exact variants
+    plan = P.AllpairsPlan(Vw, Qct)
+    try:
+        (cfg_c, cfg_p), tuned = plan.autotune(reps=5)
+        ms_g = _time(torch, stream, plan.launch, reps=10)
+        same = bool(torch.equal(plan.labels, dense_l) and torch.equal(plan.counts, dense_c))
+    finally:
+        plan.close()
+    out["allpairs_plan"] = {"variant": {"cull": cfg_c, "pair": cfg_p}, "autotune_ms": round(tuned, 4),
+                            "graph_ms": round(ms_g, 4),
+                            "labels_and_counts_equal_dense": same}
     # antipodal pairing (the car is centrally symmetric: 4 pairs instead of
     # 8 edges), alone and with culling; labels and counts must equal the dense
     for key, cull in (("allpairs_paired", 0), ("allpairs_paired_culled", 1)):

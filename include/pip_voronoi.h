@@ -342,6 +342,28 @@ pip_status pip_plan_config(pip_plan plan, pip_batched_config *config, float *bes
 pip_status pip_plan_set_config(pip_plan plan, const pip_batched_config *config);
 void pip_plan_destroy(pip_plan plan);
 
+/* All-pairs plans (Section 1's collision check: one footprint at many poses
+ * against one cloud): pip_voronoi_allpairs bound to its buffers (V
+ * [P][n][2], Q [m][2], labels [P][ceil(m/32)], counts [P], optional status
+ * [P]; the plan allocates its workspace).  The variants are the dense
+ * screen, the bounding-disk cull, antipodal pairs and both; all give the
+ * same labels and counts.  pip_plan_autotune runs each on the bound data,
+ * requires labels and counts equal word for word to the dense run's
+ * (PIP_EHIP otherwise), keeps the fastest and captures the hipGraph;
+ * pip_plan_launch replays it (capturing the context's options first if the
+ * plan was never tuned).  pip_plan_config / pip_plan_set_config reject
+ * all-pairs plans; the two calls below read and force the variant.  The
+ * buffers must stay valid while the plan is used. */
+typedef struct {
+    int32_t cull;  /* 1: skip (polygon, wave) pairs whose bounding disk misses */
+    int32_t pair;  /* 1: antipodal edge pairs for centrally symmetric polygons */
+} pip_allpairs_config;
+pip_status pip_plan_create_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double *V,
+                                    const float *Q, int64_t m, uint32_t *labels, int32_t *counts,
+                                    int32_t *status, pip_plan *out);
+pip_status pip_plan_allpairs_config(pip_plan plan, pip_allpairs_config *config, float *best_ms);
+pip_status pip_plan_allpairs_set_config(pip_plan plan, const pip_allpairs_config *config);
+
 /* ------------------------------------------------------------------------
  * Poses and all pairs (the collision check of Section 1: a convex car
  * footprint placed at many poses, tested against a lidar point cloud).

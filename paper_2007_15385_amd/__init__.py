@@ -16,7 +16,7 @@ from __future__ import annotations
 from ._lib import (PIP_F32, PIP_F64, PIP_OPT_ALLPAIRS_CULL, PIP_OPT_ALLPAIRS_PAIR, PIP_OPT_COST_CULL, PIP_OPT_COST_PAIR, PIP_OPT_MFMA_MIN_EDGES, PipError, lib_path, load_library,
                    num_label_words, status_name)
 from .api import get_option, set_option
-from .api import (BatchedPlan, LocateIndex, allpairs_workspace_bytes, batched_workspace_bytes, label_word_offsets, pip_poses_to_polygons,
+from .api import (AllpairsPlan, BatchedPlan, LocateIndex, allpairs_workspace_bytes, batched_workspace_bytes, label_word_offsets, pip_poses_to_polygons,
                   pip_ray_crossing, pip_sign_of_offset, pip_voronoi, pip_voronoi_allpairs,
                   pip_voronoi_batched, pip_voronoi_fp32_plain, pip_voronoi_max_margin, pip_voronoi_raster,
                   polygon_to_generators, unpack_labels)
@@ -27,7 +27,7 @@ __all__ = [
     "status_name", "polygon_to_generators", "pip_voronoi", "pip_sign_of_offset",
     "pip_ray_crossing", "pip_voronoi_fp32_plain", "pip_voronoi_max_margin", "pip_voronoi_raster", "unpack_labels",
     "pip_voronoi_batched", "batched_workspace_bytes", "label_word_offsets", "BatchedPlan",
-    "LocateIndex",
+    "LocateIndex", "AllpairsPlan",
     "pip_poses_to_polygons", "pip_voronoi_allpairs", "allpairs_workspace_bytes", "pip_cost_fwd", "pip_cost_bwd",
     "CollisionCost", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "PIP_OPT_COST_PAIR", "set_option", "get_option",
 ]

@@ -6,7 +6,8 @@ import threading
 
 import torch
 
-from ._lib import PIP_F32, PIP_F64, BatchedConfig, PipError, load_library, num_label_words
+from ._lib import (PIP_F32, PIP_F64, AllpairsConfig, BatchedConfig, PipError, load_library,
+                   num_label_words)
 
 _ctx_lock = threading.Lock()
 _ctx: dict[int, int] = {}
@@ -402,6 +403,69 @@ def pip_poses_to_polygons(footprint, pose, cs, out=None):
                                      out.data_ptr(), _stream(d))
     _check(s, "pip_poses_to_polygons", ctx)
     return out
+
+
+class AllpairsPlan:
+    """pip_voronoi_allpairs bound to its buffers: autotune() times the exact
+    variants (dense, culled, antipodal pairs, both) on the bound data,
+    checks that they agree word for word and captures the fastest in a
+    hipGraph; launch() replays it."""
+
+    def __init__(self, V, Q, labels=None, counts=None, status=None):
+        if V.dtype != torch.float64 or V.dim() != 3 or V.shape[2] != 2 or not V.is_contiguous():
+            raise ValueError("V must be a contiguous float64 tensor of shape [P, n, 2]")
+        if Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != 2 or not Q.is_contiguous():
+            raise ValueError("Q must be a contiguous float32 tensor of shape [m, 2]")
+        self.device = _dev(V)
+        Pn, n, m = V.shape[0], V.shape[1], Q.shape[0]
+        words = num_label_words(m)
+        if labels is None:
+            labels = torch.zeros((Pn, max(words, 1)), dtype=torch.int32, device=V.device)
+        if counts is None:
+            counts = torch.zeros(max(Pn, 1), dtype=torch.int32, device=V.device)
+        self.V, self.Q, self.labels, self.counts, self.status = V, Q, labels, counts, status
+        self.ctx = context(self.device)
+        h = ctypes.c_void_p()
+        s = _lib().pip_plan_create_allpairs(self.ctx, Pn, n, V.data_ptr(),
+                                            Q.data_ptr() if m else None, m, labels.data_ptr(),
+                                            counts.data_ptr(),
+                                            status.data_ptr() if status is not None else None,
+                                            ctypes.byref(h))
+        _check(s, "pip_plan_create_allpairs", self.ctx)
+        self.handle = h.value
+
+    def autotune(self, reps: int = 3):
+        s = _lib().pip_plan_autotune(self.handle, int(reps), _stream(self.device))
+        _check(s, "pip_plan_autotune", self.ctx)
+        return self.config()
+
+    def launch(self):
+        s = _lib().pip_plan_launch(self.handle, _stream(self.device))
+        _check(s, "pip_plan_launch", self.ctx)
+        return self.labels, self.counts
+
+    def config(self):
+        cfg = AllpairsConfig()
+        ms = ctypes.c_float()
+        s = _lib().pip_plan_allpairs_config(self.handle, ctypes.byref(cfg), ctypes.byref(ms))
+        _check(s, "pip_plan_allpairs_config", self.ctx)
+        return (cfg.cull, cfg.pair), float(ms.value)
+
+    def set_config(self, cull: int, pair: int):
+        cfg = AllpairsConfig(int(cull), int(pair))
+        s = _lib().pip_plan_allpairs_set_config(self.handle, ctypes.byref(cfg))
+        _check(s, "pip_plan_allpairs_set_config", self.ctx)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().pip_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def allpairs_workspace_bytes(P: int, n: int) -> int:

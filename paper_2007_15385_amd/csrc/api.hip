@@ -42,8 +42,22 @@ struct pip_index_s {
     int blocks = 0;
 };
 
+struct AllpairsArgs {
+    int32_t P = 0, n = 0;
+    const double* V = nullptr;
+    const float* Q = nullptr;
+    int64_t m = 0;
+    uint32_t* labels = nullptr;
+    int32_t* counts = nullptr;
+    int32_t* status = nullptr;
+};
+
 struct pip_plan_s {
     pip_ctx ctx = nullptr;
+    int kind = 0;  // 0: batched, 1: all pairs
+    AllpairsArgs A{};
+    pip_allpairs_config acfg{};
+    uint32_t* ref_counts = nullptr;
     pipdev::BatchedDev D{};
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -448,8 +462,50 @@ void pip_plan_destroy(pip_plan p) {
     if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->ws) (void)hipFree(p->ws);
     if (p->ref_labels) (void)hipFree(p->ref_labels);
+    if (p->ref_counts) (void)hipFree(p->ref_counts);
     if (p->d_diff) (void)hipFree(p->d_diff);
     delete p;
+}
+
+pip_status pip_plan_create_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double* V,
+                                    const float* Q, int64_t m, uint32_t* labels, int32_t* counts,
+                                    int32_t* status, pip_plan* out) {
+    if (!out) return fail(PIP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (P < 1) return fail(PIP_EINVAL, "a plan needs P >= 1");
+    if (n < 3) return fail(PIP_EINVAL, "n = %d: a polygon needs at least 3 vertices", (int)n);
+    if (n > PIP_MAX_EDGES) return fail(PIP_EUNSUPPORTED, "n = %d exceeds %d", (int)n, PIP_MAX_EDGES);
+    if (!V || !aligned(V, 8)) return fail(PIP_EINVAL, "V is NULL or misaligned");
+    pip_status s = check_points(Q, PIP_F32, m);
+    if (s != PIP_OK) return s;
+    if (m > 0 && (!labels || !aligned(labels, 4)))
+        return fail(PIP_EINVAL, "labels is NULL or not 4-byte aligned");
+    if (!counts || !aligned(counts, 4)) return fail(PIP_EINVAL, "counts is NULL or misaligned");
+    if (status && !aligned(status, 4)) return fail(PIP_EINVAL, "status is not 4-byte aligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    pip_plan p = new (std::nothrow) pip_plan_s();
+    if (!p) return fail(PIP_ENOMEM, "out of host memory");
+    p->ctx = ctx;
+    p->kind = 1;
+    p->A = AllpairsArgs{P, n, V, Q, m, labels, counts, status};
+    p->acfg.cull = ctx->allpairs_cull;
+    p->acfg.pair = ctx->allpairs_pair;
+    p->label_words = (int64_t)P * ((m + 31) / 32);
+    p->ws_bytes = pip_voronoi_allpairs_workspace_bytes(P, n);
+    hipError_t e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+        pip_plan_destroy(p);
+        return fail(PIP_ENOMEM, "hipMalloc of %zu workspace bytes failed", p->ws_bytes);
+    }
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        pip_plan_destroy(p);
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    *out = p;
+    return PIP_OK;
 }
 
 pip_status pip_plan_create_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_off,
@@ -513,8 +569,13 @@ pip_status capture_plan(pip_plan p) {
     }
     hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = pipdev::launch_batched(p->D, p->cfg.chunks_per_tile,
-                                           p->cfg.blocks_per_cu * p->ctx->cu_count, p->cap);
+    hipError_t le =
+        p->kind == 1
+            ? pipdev::launch_allpairs(p->A.P, p->A.n, p->A.V, p->A.Q, p->A.m, p->A.labels,
+                                      p->A.counts, p->A.status, p->ws, p->acfg.cull, p->acfg.pair,
+                                      p->cap)
+            : pipdev::launch_batched(p->D, p->cfg.chunks_per_tile,
+                                     p->cfg.blocks_per_cu * p->ctx->cu_count, p->cap);
     e = hipStreamEndCapture(p->cap, &p->graph);
     if (le != hipSuccess) return hip_fail(le, "kernel launch during capture");
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -527,9 +588,95 @@ pip_status capture_plan(pip_plan p) {
 
 extern "C" {
 
+namespace {
+
+// All pairs: the four exact variants (dense, culled, paired, both); each must
+// reproduce the first one's labels and counts word for word.
+pip_status autotune_allpairs(pip_plan p, int32_t reps, hipStream_t stream) {
+    hipError_t e;
+    const AllpairsArgs& A = p->A;
+    if (!p->ref_labels && p->label_words > 0 &&
+        (e = hipMalloc(&p->ref_labels, sizeof(uint32_t) * p->label_words)) != hipSuccess)
+        return fail(PIP_ENOMEM, "hipMalloc of the reference labels failed");
+    if (!p->ref_counts && (e = hipMalloc(&p->ref_counts, sizeof(uint32_t) * A.P)) != hipSuccess)
+        return fail(PIP_ENOMEM, "hipMalloc of the reference counts failed");
+    if (!p->d_diff && (e = hipMalloc(&p->d_diff, sizeof(unsigned long long))) != hipSuccess)
+        return fail(PIP_ENOMEM, "hipMalloc failed");
+    hipEvent_t a, b;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return hip_fail(e, "hipEventCreate");
+    }
+    auto run = [&](const pip_allpairs_config& c) {
+        return pipdev::launch_allpairs(A.P, A.n, A.V, A.Q, A.m, A.labels, A.counts, A.status, p->ws,
+                                       c.cull, c.pair, stream);
+    };
+    auto differ = [&](const uint32_t* ref, const uint32_t* cur, int64_t words,
+                      unsigned long long* out) -> hipError_t {
+        hipError_t r = pipdev::launch_count_diff(ref, cur, words, p->d_diff, stream);
+        if (r == hipSuccess) r = hipMemcpyAsync(out, p->d_diff, sizeof *out, hipMemcpyDeviceToHost, stream);
+        if (r == hipSuccess) r = hipStreamSynchronize(stream);
+        return r;
+    };
+    pip_status st = PIP_OK;
+    float best = -1.f;
+    pip_allpairs_config best_cfg = p->acfg;
+    for (int v = 0; v < 4 && st == PIP_OK; ++v) {
+        pip_allpairs_config c;
+        c.cull = v & 1;
+        c.pair = v >> 1;
+        if ((e = run(c)) != hipSuccess) { st = hip_fail(e, "kernel launch"); break; }  // warm-up
+        if (v == 0) {
+            e = hipMemcpyAsync(p->ref_counts, A.counts, sizeof(uint32_t) * A.P,
+                               hipMemcpyDeviceToDevice, stream);
+            if (e == hipSuccess && p->label_words > 0)
+                e = hipMemcpyAsync(p->ref_labels, A.labels, sizeof(uint32_t) * p->label_words,
+                                   hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) { st = hip_fail(e, "hipMemcpyAsync"); break; }
+        } else {
+            unsigned long long dl = 0, dc = 0;
+            e = p->label_words > 0 ? differ(p->ref_labels, A.labels, p->label_words, &dl) : hipSuccess;
+            if (e == hipSuccess)
+                e = differ(p->ref_counts, reinterpret_cast<const uint32_t*>(A.counts), A.P, &dc);
+            if (e != hipSuccess) { st = hip_fail(e, "label comparison"); break; }
+            if (dl != 0 || dc != 0) {
+                st = fail(PIP_EHIP, "autotune: variant (cull %d, pair %d) changed %llu label words, "
+                          "%llu counts", c.cull, c.pair, dl, dc);
+                break;
+            }
+        }
+        (void)hipEventRecord(a, stream);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = run(c);
+        (void)hipEventRecord(b, stream);
+        if (e != hipSuccess) { st = hip_fail(e, "kernel launch"); break; }
+        if ((e = hipEventSynchronize(b)) != hipSuccess) { st = hip_fail(e, "hipEventSynchronize"); break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        ms /= reps;
+        if (best < 0.f || ms < best) {
+            best = ms;
+            best_cfg = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != PIP_OK) return st;
+    p->acfg = best_cfg;
+    p->best_ms = best;
+    return capture_plan(p);
+}
+
+}  // namespace
+
 pip_status pip_plan_autotune(pip_plan p, int32_t reps, hipStream_t stream) {
     if (!p) return fail(PIP_EINVAL, "plan is NULL");
     if (reps < 1) reps = 3;
+    if (p->kind == 1) {
+        DeviceGuard g(p->ctx->device);
+        if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+        return autotune_allpairs(p, reps, stream);
+    }
     DeviceGuard g(p->ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e;
@@ -615,8 +762,26 @@ pip_status pip_plan_launch(pip_plan p, hipStream_t stream) {
     return PIP_OK;
 }
 
+pip_status pip_plan_allpairs_config(pip_plan p, pip_allpairs_config* cfg, float* best_ms) {
+    if (!p || p->kind != 1) return fail(PIP_EINVAL, "plan is NULL or not an all-pairs plan");
+    if (cfg) *cfg = p->acfg;
+    if (best_ms) *best_ms = p->best_ms;
+    return PIP_OK;
+}
+
+pip_status pip_plan_allpairs_set_config(pip_plan p, const pip_allpairs_config* cfg) {
+    if (!p || p->kind != 1 || !cfg) return fail(PIP_EINVAL, "not an all-pairs plan, or cfg is NULL");
+    if ((cfg->cull != 0 && cfg->cull != 1) || (cfg->pair != 0 && cfg->pair != 1))
+        return fail(PIP_EINVAL, "cull and pair must be 0 or 1");
+    DeviceGuard g(p->ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    p->acfg = *cfg;
+    return capture_plan(p);
+}
+
 pip_status pip_plan_config(pip_plan p, pip_batched_config* cfg, float* best_ms) {
     if (!p) return fail(PIP_EINVAL, "plan is NULL");
+    if (p->kind != 0) return fail(PIP_EINVAL, "not a batched plan");
     if (cfg) *cfg = p->cfg;
     if (best_ms) *best_ms = p->best_ms;
     return PIP_OK;
@@ -624,6 +789,7 @@ pip_status pip_plan_config(pip_plan p, pip_batched_config* cfg, float* best_ms) 
 
 pip_status pip_plan_set_config(pip_plan p, const pip_batched_config* cfg) {
     if (!p || !cfg) return fail(PIP_EINVAL, "plan or cfg is NULL");
+    if (p->kind != 0) return fail(PIP_EINVAL, "not a batched plan");
     pip_batched_config c;
     pip_status s = resolve_config(p->ctx, cfg, &c);
     if (s != PIP_OK) return s;

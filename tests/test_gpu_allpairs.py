@@ -278,3 +278,43 @@ def test_allpairs_pair_regular_and_fallback(P, oracle, n, expect):
         want = oracle.voronoi(V[k], Q.astype(np.float64))
         assert np.array_equal(lab[k], pack_bits(want)), k
         assert int(cnt[k]) == int(want.sum())
+
+
+def test_allpairs_plan_autotune_and_graph_replays(P):
+    """The all-pairs plan: autotune times the four exact variants on the lidar
+    configuration and keeps one; every replay of the captured graph (with eager
+    work and synchronisations between replays) gives the eager dense labels and
+    counts, and so does every forced variant."""
+    F = W.car_footprint()
+    Q = torch.from_numpy(W.lidar_cloud()).cuda()
+    poses, cs = W.random_poses()
+    Vw = P.pip_poses_to_polygons(torch.from_numpy(F).cuda(), torch.from_numpy(poses).cuda(),
+                                 torch.from_numpy(cs).cuda())
+    lab_e, cnt_e, _ = P.pip_voronoi_allpairs(Vw, Q)
+    torch.cuda.synchronize()
+    plan = P.AllpairsPlan(Vw, Q)
+    try:
+        cfg, ms = plan.autotune(reps=2)
+        say(f"[stat] all-pairs plan: variant (cull, pair) = {cfg}, {ms:.4f} ms")
+        assert cfg in ((0, 0), (1, 0), (0, 1), (1, 1)) and ms > 0
+        for _ in range(3):
+            plan.labels.zero_()
+            plan.counts.fill_(-1)
+            torch.cuda.synchronize()
+            plan.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(plan.labels, lab_e) and torch.equal(plan.counts, cnt_e)
+        for c in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            plan.set_config(*c)
+            plan.labels.zero_()
+            plan.launch()
+            torch.cuda.synchronize()
+            assert plan.config()[0] == c
+            assert torch.equal(plan.labels, lab_e) and torch.equal(plan.counts, cnt_e)
+        # the batched shape calls reject an all-pairs plan
+        import ctypes
+        from paper_2007_15385_amd._lib import BatchedConfig
+        from paper_2007_15385_amd.api import _lib as lib
+        assert lib().pip_plan_set_config(plan.handle, ctypes.byref(BatchedConfig(1, 1))) == 1
+    finally:
+        plan.close()
