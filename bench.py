@@ -355,6 +355,17 @@ def run_extras(P, W, torch, stream, check):
                     "fwd_speedup_vs_dense": round(fwd_ms / fwd_p, 2),
                     "bwd_speedup_vs_dense": round(bwd_ms / bwd_p, 2),
                     "max_cost_diff_vs_dense": {"abs": float(diff.max()), "rel_to_cost_plus_1e-3": rel}}
+    # autotuned, graph-captured plans (culling on or off, whichever is faster)
+    plans = {}
+    for key, bwd in (("fwd", False), ("bwd", True)):
+        cp = P.CostPlan(F32t, trt, Qdt, backward=bwd, grad_cost=ones)
+        try:
+            (cc, _), tuned = cp.autotune(reps=2)
+            plans[key] = {"cull": cc, "autotune_ms": round(tuned, 4),
+                          "graph_ms": round(_time(torch, stream, cp.launch, reps=3), 4)}
+        finally:
+            cp.close()
+    out["cost_plan"] = plans
     pairs = len(tr) * len(Qd)
     entry = {"poses": len(tr), "points": len(Qd), "pairs": pairs, "fwd_ms": round(fwd_ms, 3),
              "bwd_ms": round(bwd_ms, 3), "fwd_gpairs_per_s": round(pairs / fwd_ms / 1e6, 1),

@@ -352,17 +352,18 @@ void pip_plan_destroy(pip_plan plan);
  * (PIP_EHIP otherwise), keeps the fastest and captures the hipGraph;
  * pip_plan_launch replays it (capturing the context's options first if the
  * plan was never tuned).  pip_plan_config / pip_plan_set_config reject
- * all-pairs plans; the two calls below read and force the variant.  The
- * buffers must stay valid while the plan is used. */
+ * these plans (and collision-cost plans, below); pip_plan_variant and
+ * pip_plan_set_variant read and force their variant (recapturing the
+ * graph).  The buffers must stay valid while the plan is used. */
 typedef struct {
     int32_t cull;  /* 1: skip (polygon, wave) pairs whose bounding disk misses */
     int32_t pair;  /* 1: antipodal edge pairs for centrally symmetric polygons */
-} pip_allpairs_config;
+} pip_variant_config;
 pip_status pip_plan_create_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double *V,
                                     const float *Q, int64_t m, uint32_t *labels, int32_t *counts,
                                     int32_t *status, pip_plan *out);
-pip_status pip_plan_allpairs_config(pip_plan plan, pip_allpairs_config *config, float *best_ms);
-pip_status pip_plan_allpairs_set_config(pip_plan plan, const pip_allpairs_config *config);
+pip_status pip_plan_variant(pip_plan plan, pip_variant_config *config, float *best_ms);
+pip_status pip_plan_set_variant(pip_plan plan, const pip_variant_config *config);
 
 /* ------------------------------------------------------------------------
  * Poses and all pairs (the collision check of Section 1: a convex car
@@ -427,6 +428,21 @@ pip_status pip_cost_bwd(pip_ctx ctx, const float *footprint, int32_t n, const fl
                         const float *Q, int64_t m, const float *grad_cost, float *grad_pose,
                         float *grad_footprint, float *residual, void *workspace,
                         size_t workspace_bytes, hipStream_t stream);
+
+/* Collision-cost plans: pip_cost_fwd (backward = 0; cost) or pip_cost_bwd
+ * (backward = 1; grad_cost, grad_pose, grad_footprint, optional residual)
+ * bound to its buffers, with a workspace the plan allocates.
+ * pip_plan_autotune times the cost with and without the bounding-disk cull
+ * (antipodal pairs as the context's PIP_OPT_COST_PAIR at creation), requires
+ * the outputs of both equal word for word (PIP_EHIP otherwise), keeps the
+ * faster and captures the hipGraph; pip_plan_launch replays it;
+ * pip_plan_variant / pip_plan_set_variant read and force (cull, pair).
+ * Errors as pip_cost_fwd / pip_cost_bwd, PIP_EINVAL for K < 1,
+ * PIP_ENOMEM. */
+pip_status pip_plan_create_cost(pip_ctx ctx, int32_t backward, const float *footprint, int32_t n,
+                                const float *pose, int64_t K, const float *Q, int64_t m,
+                                float *cost, const float *grad_cost, float *grad_pose,
+                                float *grad_footprint, float *residual, pip_plan *out);
 
 #ifdef __cplusplus
 }

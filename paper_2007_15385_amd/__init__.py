@@ -20,7 +20,7 @@ from .api import (AllpairsPlan, BatchedPlan, LocateIndex, allpairs_workspace_byt
                   pip_ray_crossing, pip_sign_of_offset, pip_voronoi, pip_voronoi_allpairs,
                   pip_voronoi_batched, pip_voronoi_fp32_plain, pip_voronoi_max_margin, pip_voronoi_raster,
                   polygon_to_generators, unpack_labels)
-from .autograd import CollisionCost, collision_cost, pip_cost_bwd, pip_cost_fwd
+from .autograd import CollisionCost, CostPlan, collision_cost, pip_cost_bwd, pip_cost_fwd
 
 __all__ = [
     "PIP_F32", "PIP_F64", "PipError", "lib_path", "load_library", "num_label_words",
@@ -29,5 +29,5 @@ __all__ = [
     "pip_voronoi_batched", "batched_workspace_bytes", "label_word_offsets", "BatchedPlan",
     "LocateIndex", "AllpairsPlan",
     "pip_poses_to_polygons", "pip_voronoi_allpairs", "allpairs_workspace_bytes", "pip_cost_fwd", "pip_cost_bwd",
-    "CollisionCost", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "PIP_OPT_COST_PAIR", "set_option", "get_option",
+    "CollisionCost", "CostPlan", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "PIP_OPT_COST_PAIR", "set_option", "get_option",
 ]

@@ -76,8 +76,10 @@ SIGNATURES = {
     "pip_plan_set_config": (_int, [_vp, _vp]),
     "pip_plan_create_allpairs": (_int, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp,
                                         _c.POINTER(_vp)]),
-    "pip_plan_allpairs_config": (_int, [_vp, _vp, _c.POINTER(_c.c_float)]),
-    "pip_plan_allpairs_set_config": (_int, [_vp, _vp]),
+    "pip_plan_variant": (_int, [_vp, _vp, _c.POINTER(_c.c_float)]),
+    "pip_plan_create_cost": (_int, [_vp, _i32, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp,
+                                    _vp, _c.POINTER(_vp)]),
+    "pip_plan_set_variant": (_int, [_vp, _vp]),
     "pip_plan_destroy": (None, [_vp]),
     "pip_poses_to_polygons": (_int, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp]),
     "pip_voronoi_allpairs_workspace_bytes": (_c.c_size_t, [_i32, _i32]),
@@ -94,7 +96,7 @@ class BatchedConfig(ctypes.Structure):
     _fields_ = [("chunks_per_tile", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32)]
 
 
-class AllpairsConfig(ctypes.Structure):
+class VariantConfig(ctypes.Structure):
     _fields_ = [("cull", ctypes.c_int32), ("pair", ctypes.c_int32)]
 
 _lock = threading.Lock()

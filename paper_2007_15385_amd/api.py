@@ -6,7 +6,7 @@ import threading
 
 import torch
 
-from ._lib import (PIP_F32, PIP_F64, AllpairsConfig, BatchedConfig, PipError, load_library,
+from ._lib import (PIP_F32, PIP_F64, VariantConfig, BatchedConfig, PipError, load_library,
                    num_label_words)
 
 _ctx_lock = threading.Lock()
@@ -445,16 +445,16 @@ class AllpairsPlan:
         return self.labels, self.counts
 
     def config(self):
-        cfg = AllpairsConfig()
+        cfg = VariantConfig()
         ms = ctypes.c_float()
-        s = _lib().pip_plan_allpairs_config(self.handle, ctypes.byref(cfg), ctypes.byref(ms))
-        _check(s, "pip_plan_allpairs_config", self.ctx)
+        s = _lib().pip_plan_variant(self.handle, ctypes.byref(cfg), ctypes.byref(ms))
+        _check(s, "pip_plan_variant", self.ctx)
         return (cfg.cull, cfg.pair), float(ms.value)
 
     def set_config(self, cull: int, pair: int):
-        cfg = AllpairsConfig(int(cull), int(pair))
-        s = _lib().pip_plan_allpairs_set_config(self.handle, ctypes.byref(cfg))
-        _check(s, "pip_plan_allpairs_set_config", self.ctx)
+        cfg = VariantConfig(int(cull), int(pair))
+        s = _lib().pip_plan_set_variant(self.handle, ctypes.byref(cfg))
+        _check(s, "pip_plan_set_variant", self.ctx)
 
     def close(self):
         if getattr(self, "handle", None):

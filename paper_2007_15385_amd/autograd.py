@@ -71,6 +71,77 @@ def pip_cost_bwd(footprint, poses, points, grad_cost, workspace=None):
     return gp[:K], gF, res
 
 
+class CostPlan:
+    """pip_cost_fwd (backward=False) or pip_cost_bwd (backward=True) bound to
+    fixed buffers: autotune() times the cost with and without the
+    bounding-disk cull, checks that both give the same outputs word for word
+    and captures the faster in a hipGraph; launch() replays it.  The
+    outputs are the attributes cost, or grad_pose, grad_footprint, residual."""
+
+    def __init__(self, footprint, poses, points, backward: bool = False, grad_cost=None):
+        import ctypes
+        self.F, self.P, self.Q = _footprint(footprint), _poses(poses), _points(points)
+        self.device = _dev(self.F)
+        n, K, m = self.F.shape[0], self.P.shape[0], self.Q.shape[0]
+        dev = self.F.device
+        self.backward = bool(backward)
+        self.cost = None if backward else torch.zeros(max(K, 1), dtype=torch.float32, device=dev)
+        self.grad_cost = None
+        if backward:
+            g = grad_cost if grad_cost is not None else torch.ones(K, device=dev)
+            self.grad_cost = g.reshape(-1).to(torch.float32).contiguous()
+            if self.grad_cost.numel() != K:
+                raise ValueError("grad_cost must have one entry per pose")
+        self.grad_pose = torch.zeros((max(K, 1), 3), dtype=torch.float32, device=dev) if backward else None
+        self.grad_footprint = torch.zeros((n, 2), dtype=torch.float32, device=dev) if backward else None
+        self.residual = torch.zeros(2, dtype=torch.float32, device=dev) if backward else None
+        self.ctx = context(self.device)
+        ptr = lambda t: t.data_ptr() if t is not None else None
+        h = ctypes.c_void_p()
+        s = _lib().pip_plan_create_cost(self.ctx, 1 if backward else 0, self.F.data_ptr(), n,
+                                        self.P.data_ptr(), K, ptr(self.Q) if m else None, m,
+                                        ptr(self.cost), ptr(self.grad_cost), ptr(self.grad_pose),
+                                        ptr(self.grad_footprint), ptr(self.residual),
+                                        ctypes.byref(h))
+        _check(s, "pip_plan_create_cost", self.ctx)
+        self.handle = h.value
+
+    def autotune(self, reps: int = 3):
+        s = _lib().pip_plan_autotune(self.handle, int(reps), _stream(self.device))
+        _check(s, "pip_plan_autotune", self.ctx)
+        return self.config()
+
+    def launch(self):
+        s = _lib().pip_plan_launch(self.handle, _stream(self.device))
+        _check(s, "pip_plan_launch", self.ctx)
+
+    def config(self):
+        import ctypes
+        from ._lib import VariantConfig
+        cfg = VariantConfig()
+        ms = ctypes.c_float()
+        s = _lib().pip_plan_variant(self.handle, ctypes.byref(cfg), ctypes.byref(ms))
+        _check(s, "pip_plan_variant", self.ctx)
+        return (cfg.cull, cfg.pair), float(ms.value)
+
+    def set_config(self, cull: int, pair: int):
+        import ctypes
+        from ._lib import VariantConfig
+        s = _lib().pip_plan_set_variant(self.handle, ctypes.byref(VariantConfig(int(cull), int(pair))))
+        _check(s, "pip_plan_set_variant", self.ctx)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib().pip_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class CollisionCost(torch.autograd.Function):
     """cost[...] = sum over points of relu(min over edges of the normalized
     Voronoi margin) for each pose in poses[..., 3]; differentiable with

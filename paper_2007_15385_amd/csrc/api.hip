@@ -52,11 +52,26 @@ struct AllpairsArgs {
     int32_t* status = nullptr;
 };
 
+struct CostArgs {
+    const float* F = nullptr;
+    int32_t n = 0;
+    const float* pose = nullptr;
+    int64_t K = 0;
+    const float* Q = nullptr;
+    int64_t m = 0;
+    float* cost = nullptr;                                     // forward
+    const float* grad_cost = nullptr;                          // backward
+    float* grad_pose = nullptr;
+    float* grad_F = nullptr;
+    float* residual = nullptr;
+};
+
 struct pip_plan_s {
     pip_ctx ctx = nullptr;
-    int kind = 0;  // 0: batched, 1: all pairs
+    int kind = 0;  // 0: batched, 1: all pairs, 2: cost forward, 3: cost backward
     AllpairsArgs A{};
-    pip_allpairs_config acfg{};
+    CostArgs Cst{};
+    pip_variant_config acfg{};
     uint32_t* ref_counts = nullptr;
     pipdev::BatchedDev D{};
     void* ws = nullptr;
@@ -558,6 +573,28 @@ pip_status pip_plan_create_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_of
 
 namespace {
 
+// One launch of the plan's work with its current configuration.
+hipError_t launch_plan_once(pip_plan p, hipStream_t stream) {
+    const CostArgs& C = p->Cst;
+    switch (p->kind) {
+        case 1:
+            return pipdev::launch_allpairs(p->A.P, p->A.n, p->A.V, p->A.Q, p->A.m, p->A.labels,
+                                           p->A.counts, p->A.status, p->ws, p->acfg.cull,
+                                           p->acfg.pair, stream);
+        case 2:
+            return pipdev::launch_cost(false, C.F, C.n, C.pose, C.K, C.Q, C.m, nullptr, C.cost,
+                                       nullptr, nullptr, nullptr, p->ws, p->acfg.cull, p->acfg.pair,
+                                       stream);
+        case 3:
+            return pipdev::launch_cost(true, C.F, C.n, C.pose, C.K, C.Q, C.m, C.grad_cost, nullptr,
+                                       C.grad_pose, C.grad_F, C.residual, p->ws, p->acfg.cull,
+                                       p->acfg.pair, stream);
+        default:
+            return pipdev::launch_batched(p->D, p->cfg.chunks_per_tile,
+                                          p->cfg.blocks_per_cu * p->ctx->cu_count, stream);
+    }
+}
+
 pip_status capture_plan(pip_plan p) {
     if (p->exec) {
         (void)hipGraphExecDestroy(p->exec);
@@ -569,13 +606,7 @@ pip_status capture_plan(pip_plan p) {
     }
     hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le =
-        p->kind == 1
-            ? pipdev::launch_allpairs(p->A.P, p->A.n, p->A.V, p->A.Q, p->A.m, p->A.labels,
-                                      p->A.counts, p->A.status, p->ws, p->acfg.cull, p->acfg.pair,
-                                      p->cap)
-            : pipdev::launch_batched(p->D, p->cfg.chunks_per_tile,
-                                     p->cfg.blocks_per_cu * p->ctx->cu_count, p->cap);
+    hipError_t le = launch_plan_once(p, p->cap);
     e = hipStreamEndCapture(p->cap, &p->graph);
     if (le != hipSuccess) return hip_fail(le, "kernel launch during capture");
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
@@ -590,16 +621,45 @@ extern "C" {
 
 namespace {
 
-// All pairs: the four exact variants (dense, culled, paired, both); each must
-// reproduce the first one's labels and counts word for word.
-pip_status autotune_allpairs(pip_plan p, int32_t reps, hipStream_t stream) {
+// The output words a variant must reproduce: (pointer, 32-bit words) pairs.
+int plan_outputs(pip_plan p, uint32_t** ptr, int64_t* words) {
+    const CostArgs& C = p->Cst;
+    switch (p->kind) {
+        case 1:
+            ptr[0] = p->A.labels;
+            words[0] = p->label_words;
+            ptr[1] = reinterpret_cast<uint32_t*>(p->A.counts);
+            words[1] = p->A.P;
+            return 2;
+        case 2:
+            ptr[0] = reinterpret_cast<uint32_t*>(C.cost);
+            words[0] = C.K;
+            return 1;
+        case 3:
+            ptr[0] = reinterpret_cast<uint32_t*>(C.grad_pose);
+            words[0] = 3 * C.K;
+            ptr[1] = reinterpret_cast<uint32_t*>(C.grad_F);
+            words[1] = 2 * (int64_t)C.n;
+            return 2;
+        default:
+            return 0;
+    }
+}
+
+// All pairs and cost: the exact variants (all pairs: dense, culled, paired,
+// both; cost: culled or not, pairing as configured); each must reproduce the
+// first one's outputs word for word.
+pip_status autotune_variants(pip_plan p, int32_t reps, hipStream_t stream) {
     hipError_t e;
-    const AllpairsArgs& A = p->A;
-    if (!p->ref_labels && p->label_words > 0 &&
-        (e = hipMalloc(&p->ref_labels, sizeof(uint32_t) * p->label_words)) != hipSuccess)
-        return fail(PIP_ENOMEM, "hipMalloc of the reference labels failed");
-    if (!p->ref_counts && (e = hipMalloc(&p->ref_counts, sizeof(uint32_t) * A.P)) != hipSuccess)
-        return fail(PIP_ENOMEM, "hipMalloc of the reference counts failed");
+    uint32_t* out[2] = {nullptr, nullptr};
+    int64_t words[2] = {0, 0};
+    const int nout = plan_outputs(p, out, words);
+    if (!p->ref_labels && words[0] > 0 &&
+        (e = hipMalloc(&p->ref_labels, sizeof(uint32_t) * words[0])) != hipSuccess)
+        return fail(PIP_ENOMEM, "hipMalloc of the reference outputs failed");
+    if (nout > 1 && !p->ref_counts && words[1] > 0 &&
+        (e = hipMalloc(&p->ref_counts, sizeof(uint32_t) * words[1])) != hipSuccess)
+        return fail(PIP_ENOMEM, "hipMalloc of the reference outputs failed");
     if (!p->d_diff && (e = hipMalloc(&p->d_diff, sizeof(unsigned long long))) != hipSuccess)
         return fail(PIP_ENOMEM, "hipMalloc failed");
     hipEvent_t a, b;
@@ -608,10 +668,14 @@ pip_status autotune_allpairs(pip_plan p, int32_t reps, hipStream_t stream) {
         (void)hipEventDestroy(a);
         return hip_fail(e, "hipEventCreate");
     }
-    auto run = [&](const pip_allpairs_config& c) {
-        return pipdev::launch_allpairs(A.P, A.n, A.V, A.Q, A.m, A.labels, A.counts, A.status, p->ws,
-                                       c.cull, c.pair, stream);
+    auto run = [&](const pip_variant_config& c) {
+        const pip_variant_config keep = p->acfg;
+        p->acfg = c;
+        const hipError_t r = launch_plan_once(p, stream);
+        p->acfg = keep;
+        return r;
     };
+    uint32_t* ref[2] = {p->ref_labels, p->ref_counts};
     auto differ = [&](const uint32_t* ref, const uint32_t* cur, int64_t words,
                       unsigned long long* out) -> hipError_t {
         hipError_t r = pipdev::launch_count_diff(ref, cur, words, p->d_diff, stream);
@@ -621,28 +685,28 @@ pip_status autotune_allpairs(pip_plan p, int32_t reps, hipStream_t stream) {
     };
     pip_status st = PIP_OK;
     float best = -1.f;
-    pip_allpairs_config best_cfg = p->acfg;
-    for (int v = 0; v < 4 && st == PIP_OK; ++v) {
-        pip_allpairs_config c;
+    pip_variant_config best_cfg = p->acfg;
+    // all pairs: (cull, pair) in {0,1}^2; cost: cull in {0,1}, pair as configured
+    const int nvar = p->kind == 1 ? 4 : 2;
+    for (int v = 0; v < nvar && st == PIP_OK; ++v) {
+        pip_variant_config c;
         c.cull = v & 1;
-        c.pair = v >> 1;
+        c.pair = p->kind == 1 ? v >> 1 : p->acfg.pair;
         if ((e = run(c)) != hipSuccess) { st = hip_fail(e, "kernel launch"); break; }  // warm-up
         if (v == 0) {
-            e = hipMemcpyAsync(p->ref_counts, A.counts, sizeof(uint32_t) * A.P,
-                               hipMemcpyDeviceToDevice, stream);
-            if (e == hipSuccess && p->label_words > 0)
-                e = hipMemcpyAsync(p->ref_labels, A.labels, sizeof(uint32_t) * p->label_words,
-                                   hipMemcpyDeviceToDevice, stream);
+            for (int o = 0; o < nout && e == hipSuccess; ++o)
+                if (words[o] > 0)
+                    e = hipMemcpyAsync(ref[o], out[o], sizeof(uint32_t) * words[o],
+                                       hipMemcpyDeviceToDevice, stream);
             if (e != hipSuccess) { st = hip_fail(e, "hipMemcpyAsync"); break; }
         } else {
-            unsigned long long dl = 0, dc = 0;
-            e = p->label_words > 0 ? differ(p->ref_labels, A.labels, p->label_words, &dl) : hipSuccess;
-            if (e == hipSuccess)
-                e = differ(p->ref_counts, reinterpret_cast<const uint32_t*>(A.counts), A.P, &dc);
-            if (e != hipSuccess) { st = hip_fail(e, "label comparison"); break; }
-            if (dl != 0 || dc != 0) {
-                st = fail(PIP_EHIP, "autotune: variant (cull %d, pair %d) changed %llu label words, "
-                          "%llu counts", c.cull, c.pair, dl, dc);
+            unsigned long long d[2] = {0, 0};
+            for (int o = 0; o < nout && e == hipSuccess; ++o)
+                if (words[o] > 0) e = differ(ref[o], out[o], words[o], &d[o]);
+            if (e != hipSuccess) { st = hip_fail(e, "output comparison"); break; }
+            if (d[0] != 0 || d[1] != 0) {
+                st = fail(PIP_EHIP, "autotune: variant (cull %d, pair %d) changed %llu + %llu "
+                          "output words", c.cull, c.pair, d[0], d[1]);
                 break;
             }
         }
@@ -672,10 +736,10 @@ pip_status autotune_allpairs(pip_plan p, int32_t reps, hipStream_t stream) {
 pip_status pip_plan_autotune(pip_plan p, int32_t reps, hipStream_t stream) {
     if (!p) return fail(PIP_EINVAL, "plan is NULL");
     if (reps < 1) reps = 3;
-    if (p->kind == 1) {
+    if (p->kind != 0) {
         DeviceGuard g(p->ctx->device);
         if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-        return autotune_allpairs(p, reps, stream);
+        return autotune_variants(p, reps, stream);
     }
     DeviceGuard g(p->ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
@@ -762,15 +826,15 @@ pip_status pip_plan_launch(pip_plan p, hipStream_t stream) {
     return PIP_OK;
 }
 
-pip_status pip_plan_allpairs_config(pip_plan p, pip_allpairs_config* cfg, float* best_ms) {
-    if (!p || p->kind != 1) return fail(PIP_EINVAL, "plan is NULL or not an all-pairs plan");
+pip_status pip_plan_variant(pip_plan p, pip_variant_config* cfg, float* best_ms) {
+    if (!p || p->kind == 0) return fail(PIP_EINVAL, "plan is NULL or a batched plan");
     if (cfg) *cfg = p->acfg;
     if (best_ms) *best_ms = p->best_ms;
     return PIP_OK;
 }
 
-pip_status pip_plan_allpairs_set_config(pip_plan p, const pip_allpairs_config* cfg) {
-    if (!p || p->kind != 1 || !cfg) return fail(PIP_EINVAL, "not an all-pairs plan, or cfg is NULL");
+pip_status pip_plan_set_variant(pip_plan p, const pip_variant_config* cfg) {
+    if (!p || p->kind == 0 || !cfg) return fail(PIP_EINVAL, "plan is NULL or batched, or cfg is NULL");
     if ((cfg->cull != 0 && cfg->cull != 1) || (cfg->pair != 0 && cfg->pair != 1))
         return fail(PIP_EINVAL, "cull and pair must be 0 or 1");
     DeviceGuard g(p->ctx->device);
@@ -866,8 +930,8 @@ size_t pip_cost_workspace_bytes(int32_t n, int64_t K, int64_t m) {
 }  // extern "C"
 
 namespace {
-pip_status check_cost(pip_ctx ctx, const float* F, int32_t n, const float* pose, int64_t K,
-                      const float* Q, int64_t m, void* ws, size_t ws_bytes) {
+pip_status check_cost_args(pip_ctx ctx, const float* F, int32_t n, const float* pose, int64_t K,
+                           const float* Q, int64_t m) {
     if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
     if (!F || !aligned(F, 4)) return fail(PIP_EINVAL, "footprint is NULL or misaligned");
     if (n < 3) return fail(PIP_EINVAL, "n = %d: a polygon needs at least 3 vertices", (int)n);
@@ -878,6 +942,13 @@ pip_status check_cost(pip_ctx ctx, const float* F, int32_t n, const float* pose,
     if (K > 0 && (!pose || !aligned(pose, 4))) return fail(PIP_EINVAL, "pose is NULL or misaligned");
     if (m > 0 && (!Q || !aligned(Q, 8))) return fail(PIP_EINVAL, "Q is NULL or not 8-byte aligned");
     if (K > ((int64_t)1 << 31) || m > ((int64_t)1 << 40)) return fail(PIP_EUNSUPPORTED, "too large");
+    return PIP_OK;
+}
+
+pip_status check_cost(pip_ctx ctx, const float* F, int32_t n, const float* pose, int64_t K,
+                      const float* Q, int64_t m, void* ws, size_t ws_bytes) {
+    pip_status s = check_cost_args(ctx, F, n, pose, K, Q, m);
+    if (s != PIP_OK) return s;
     const size_t need = pip_cost_workspace_bytes(n, K, m);
     if (!ws || ws_bytes < need)
         return fail(PIP_EINVAL, "workspace of %zu bytes needed (got %zu)", need, ws_bytes);
@@ -922,6 +993,50 @@ pip_status pip_cost_bwd(pip_ctx ctx, const float* footprint, int32_t n, const fl
                                        grad_footprint, residual, workspace, ctx->cost_cull,
                                        ctx->cost_pair, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+
+pip_status pip_plan_create_cost(pip_ctx ctx, int32_t backward, const float* footprint, int32_t n,
+                                const float* pose, int64_t K, const float* Q, int64_t m, float* cost,
+                                const float* grad_cost, float* grad_pose, float* grad_footprint,
+                                float* residual, pip_plan* out) {
+    if (!out) return fail(PIP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (K < 1) return fail(PIP_EINVAL, "a plan needs K >= 1");
+    pip_status s = check_cost_args(ctx, footprint, n, pose, K, Q, m);
+    if (s != PIP_OK) return s;
+    const size_t need = pip_cost_workspace_bytes(n, K, m);
+    if (!backward && (!cost || !aligned(cost, 4))) return fail(PIP_EINVAL, "cost is NULL or misaligned");
+    if (backward) {
+        if (!grad_cost || !aligned(grad_cost, 4)) return fail(PIP_EINVAL, "grad_cost is NULL or misaligned");
+        if (!grad_pose || !aligned(grad_pose, 4)) return fail(PIP_EINVAL, "grad_pose is NULL or misaligned");
+        if (!grad_footprint || !aligned(grad_footprint, 4))
+            return fail(PIP_EINVAL, "grad_footprint is NULL or misaligned");
+        if (residual && !aligned(residual, 4)) return fail(PIP_EINVAL, "residual is misaligned");
+    }
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    pip_plan p = new (std::nothrow) pip_plan_s();
+    if (!p) return fail(PIP_ENOMEM, "out of host memory");
+    p->ctx = ctx;
+    p->kind = backward ? 3 : 2;
+    p->Cst = CostArgs{footprint, n, pose, K, Q, m, cost, grad_cost, grad_pose, grad_footprint, residual};
+    p->acfg.cull = ctx->cost_cull;
+    p->acfg.pair = ctx->cost_pair;
+    p->ws_bytes = need;
+    hipError_t e = hipMalloc(&p->ws, p->ws_bytes);
+    if (e != hipSuccess) {
+        pip_plan_destroy(p);
+        return fail(PIP_ENOMEM, "hipMalloc of %zu workspace bytes failed", p->ws_bytes);
+    }
+    e = hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        pip_plan_destroy(p);
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    *out = p;
     return PIP_OK;
 }
 

@@ -290,3 +290,48 @@ def test_cost_pair_falls_back_for_asymmetric_footprint(P):
     b = _cost_opts(P, F, poses, Q, w, 0, 1)
     for x, y in zip(a, b):
         assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+
+
+@pytest.mark.parametrize("backward", [False, True], ids=["forward", "backward"])
+def test_cost_plan_autotune_and_graph_replays(P, scene, backward):
+    """Cost plans: autotune times the cost with and without culling (outputs
+    equal word for word), and every replay of the captured graph (eager work
+    and synchronisations between replays) and every forced variant gives the
+    eager outputs bit for bit."""
+    F, Q, poses = scene
+    w = np.linspace(0.5, 2.0, len(poses)).astype(np.float32)
+    if backward:
+        want = gpu_grad(P, F, poses, Q, w)[:2]
+    else:
+        want = (gpu_cost(P, F, poses, Q),)
+    plan = P.CostPlan(torch.from_numpy(F).cuda(), torch.from_numpy(poses).cuda(),
+                      torch.from_numpy(Q).cuda(), backward=backward,
+                      grad_cost=torch.from_numpy(w).cuda())
+    outs = (plan.grad_pose, plan.grad_footprint) if backward else (plan.cost,)
+
+    def check():
+        for t, x in zip(outs, want):
+            got = t[: len(x)].cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), np.ascontiguousarray(x).view(np.uint32))
+
+    try:
+        cfg, ms = plan.autotune(reps=2)
+        say(f"[stat] cost plan ({'backward' if backward else 'forward'}): (cull, pair) = {cfg}, {ms:.3f} ms")
+        assert cfg in ((0, 0), (1, 0)) and ms > 0
+        for _ in range(3):
+            for t in outs:
+                t.fill_(7.0)
+            torch.cuda.synchronize()
+            plan.launch()
+            torch.cuda.synchronize()
+            check()
+        for c in ((0, 0), (1, 0)):
+            plan.set_config(*c)
+            for t in outs:
+                t.zero_()
+            plan.launch()
+            torch.cuda.synchronize()
+            assert plan.config()[0] == c
+            check()
+    finally:
+        plan.close()
