@@ -349,14 +349,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         __builtin_amdgcn_wave_barrier();
         cur_k = k;
     };
-    // the chunk after g in this wave's sequence
-    auto next_chunk = [&](int64_t gg) -> int64_t {
-        int64_t g2 = gg + 1;
-        if (g2 % G == 0 || g2 >= nchunks) {
-            tile += W;
-            g2 = tile * G;
+    // the chunk after gg in this wave's sequence; pos is gg's place in its
+    // tile (a counter instead of a 64-bit remainder per chunk)
+    auto next_chunk = [&](int64_t gg, int& pos) -> int64_t {
+        if (pos + 1 < G && gg + 1 < nchunks) {
+            ++pos;
+            return gg + 1;
         }
-        return g2;
+        tile += W;
+        pos = 0;
+        return tile * G;
     };
 
     // Descriptors travel by vector load, issued after the point prefetch, so
@@ -377,7 +379,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         return c;
     };
     const int64_t g0 = g;  // a valid index for the descriptor loads past the end
-    int64_t g2 = next_chunk(g);
+    int pos2 = 0;          // place of g2 (then g3) in its tile
+    int64_t g2 = next_chunk(g, pos2);
     bool more = g2 < nchunks;
     auto d2v = load_desc_v(more ? g2 : g0);
 
@@ -391,7 +394,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             load_chunk_b(Q, d2, lane, pb);
             if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
         }
-        int64_t g3 = more ? next_chunk(g2) : g2;
+        int64_t g3 = more ? next_chunk(g2, pos2) : g2;
         bool more3 = more && g3 < nchunks;
         d2v = load_desc_v(more3 ? g3 : (more ? g2 : g0));
         process(pa, d);
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             load_chunk_b(Q, d2, lane, pa);
             if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
         }
-        g3 = more ? next_chunk(g2) : g2;
+        g3 = more ? next_chunk(g2, pos2) : g2;
         more3 = more && g3 < nchunks;
         d2v = load_desc_v(more3 ? g3 : (more ? g2 : g0));
         process(pb, d);
