@@ -37,7 +37,7 @@ NS = (3, 4, 8, 16, 32, 64)
 
 # device code of the single-polygon streaming kernels (whose HBM traffic
 # profiles/hbm_traffic.json records); the shared declarations header is left out
-STREAM_SOURCES = ("device.hpp", "stream.hip", "stream32.hpp", "stream_mfma.hip")
+STREAM_SOURCES = ("device.hpp", "radial.hpp", "stream.hip", "stream32.hpp", "stream_mfma.hip")
 
 
 def kernel_source_hash() -> str:
@@ -89,7 +89,8 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir) -> int
     sf, sw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
 
     def voronoi(rows):
-        return [v for _, name, v in rows if "k_stream32<0>" in name or "k_stream_mfma<0," in name]
+        return [v for _, name, v in rows
+                if "k_stream32<0>" in name or "k_stream_mfma<0," in name or "k_stream32_radial" in name]
     fe = voronoi(_counter_rows(fetch_dir, "FETCH_SIZE"))
     wr = voronoi(_counter_rows(write_dir, "WRITE_SIZE"))
     if len(fe) != len(NS) or len(wr) != len(NS):
@@ -110,6 +111,23 @@ def ingest_counters(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir) -> int
         json.dump(out, fh, indent=1)
     print(f"scale FETCH_SIZE {sf:.4f}, WRITE_SIZE {sw:.4f}; wrote profiles/hbm_traffic.json")
     return 0
+
+
+def annulus_fraction(P, torch, V, Q, sample=1 << 20):
+    """Share of the first `sample` points that the radial pre-screen leaves to
+    the per-edge screen (float64 evaluation of its tests on the host; a
+    diagnostic, not a label)."""
+    b = P.pip_voronoi_radial_bounds(torch.from_numpy(V).cuda()).cpu().numpy()
+    p0 = P.polygon_to_generators(torch.from_numpy(V).cuda()).cpu().numpy()[0]
+    q = Q[:sample]
+    X = (q[:, 0] - np.float32(p0[0])).astype(np.float32)
+    Y = (q[:, 1] - np.float32(p0[1])).astype(np.float32)
+    o = (4 * (X.view(np.uint32) >> 31) + 2 * (Y.view(np.uint32) >> 31)
+         + (np.abs(Y) > np.abs(X))).astype(np.int64)
+    r2 = (X.astype(np.float64) ** 2 + Y.astype(np.float64) ** 2).astype(np.float32)
+    tin, tout, tfar = b[:8][o], b[8:16][o], b[16]
+    decided = (r2 < tin) | ((r2 > tout) & (r2 < tfar))
+    return round(float(1.0 - decided.mean()), 5)
 
 
 def _time(torch, stream, fn, reps=5, warm=1):
@@ -509,13 +527,29 @@ def main() -> int:
                         "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                         "fp32_tflops": round(tfl, 2),
                         "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)})
+    # which screen each polygon size takes: the radial pre-screen (if on for
+    # this size) wins over the matrix cores, which win over the vector screen
+    mfma_min = int(P.get_option(P.PIP_OPT_MFMA_MIN_EDGES))
+    radial_min = int(P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES))
+
+    def screen_of(n):
+        if radial_min > 0 and n >= radial_min:
+            return "radial"
+        return "mfma" if mfma_min > 0 and n >= mfma_min else "valu"
+
+    for r in kernels:
+        r["screen"] = screen_of(r["n"])
+        if r["screen"] == "radial":
+            r["radial_annulus_frac"] = annulus_fraction(P, torch, *host_q[r["n"]])
     dom = max(kernels, key=lambda r: r["ms"])
     # binding roofline of the dominant launch: bytes vs flops at peak
     t_hbm = BYTES_PER_TEST * m / (HBM_PEAK_GBS * 1e9)
     t_alu = 4.0 * dom["n"] * m / (FP32_VALU_PEAK_TFLOPS * 1e12)
-    # polygons with at least this many edges take the matrix-core screen
-    mfma_min = int(P.get_option(P.PIP_OPT_MFMA_MIN_EDGES))
-    on_mfma = mfma_min > 0 and dom["n"] >= mfma_min
+    on_mfma = dom["screen"] == "mfma"
+    if dom["screen"] == "radial":
+        # a few operations per point; the per-edge screen runs on the annulus
+        # points only, so the launch is priced by its bytes
+        t_alu = 0.0
     if t_alu > t_hbm:
         # fp32 products on the matrix cores, or two fp32 fma per margin on the
         # vector units: both priced against the 157.3 TFLOP/s fp32 peak
@@ -525,7 +559,9 @@ def main() -> int:
         roof = {"bound": "hbm", "achieved": dom["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": dom["hbm_frac"]}
     roof["kernel"] = (f"k_stream_mfma<voronoi,{64 if dom['n'] > 32 else 32}> n={dom['n']}"
-                      if on_mfma else f"k_stream32<voronoi> n={dom['n']}")
+                      if on_mfma else
+                      f"k_stream32_radial n={dom['n']}" if dom["screen"] == "radial" else
+                      f"k_stream32<voronoi> n={dom['n']}")
     roof["traffic"] = traffic_for(f"voronoi_f32_n{dom['n']}")
     roof["algorithmic_per_launch"] = ({"flop": 4.0 * dom["n"] * m}
                                       if roof["bound"] in ("alu", "mfma")
@@ -545,9 +581,19 @@ def main() -> int:
         return a.elapsed_time(b) / reps
 
     soo = {n: time_fn(P.pip_sign_of_offset, n) for n in NS}
+    # the per-edge screens alone (radial pre-screen off), as the paper's
+    # comparison runs every test on every edge
+    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 0)
+    try:
+        full = {n: time_fn(P.pip_voronoi, n) for n in NS}
+    finally:
+        P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, radial_min)
     plain = {n: time_fn(P.pip_voronoi_fp32_plain, n) for n in NS}
     ray = {n: time_fn(P.pip_ray_crossing, n, reps=1) for n in NS}
     comparisons = {
+        "voronoi_per_edge_screen_gtests_per_s":
+            round(tests_per_step / (sum(full.values()) * 1e-3) / 1e9, 2),
+        "voronoi_per_edge_screen_ms": {str(n): round(v, 4) for n, v in full.items()},
         "sign_of_offset_gtests_per_s": round(tests_per_step / (sum(soo.values()) * 1e-3) / 1e9, 2),
         "sign_of_offset_ms": {str(n): round(v, 4) for n, v in soo.items()},
         "fp32_plain_gtests_per_s": round(tests_per_step / (sum(plain.values()) * 1e-3) / 1e9, 2),

@@ -138,13 +138,27 @@ typedef struct pip_index_s *pip_index;
  *     2^-20) as n/2 pairs: the smaller of the two signed distances is
  *     h - |t| of one affine form, at edge i when t >= 0.  Costs and gradients
  *     change by float32 rounding only (they are tolerance-graded); other
- *     footprints keep the per-edge loop.  Default 0. */
+ *     footprints keep the per-edge loop.  Default 0.
+ *   PIP_OPT_RADIAL_MIN_EDGES: pip_voronoi on float32 points first compares
+ *     each point's squared distance from p_0 (in the float32 local frame)
+ *     with two thresholds per octant of directions, derived in binary64 from
+ *     the generators and the screen's error band (pip_voronoi_radial_bounds):
+ *     below the inner one every binary64 comparison of Algorithm 5 says
+ *     inside, beyond the outer one (and short of a far limit) one of them says
+ *     outside.  Only the points in between take the per-edge screen (and, in
+ *     its band, the binary64 recheck), so labels are unchanged.  Used for
+ *     polygons with at least this many edges (before the matrix-core path);
+ *     0 disables it.  Default 20 (measured: the per-edge screen is faster for
+ *     fewer edges, where more points fall between the radii).  Not from the
+ *     paper: a screen in front of its test, from the nearest-generator
+ *     reading of Section 4. */
 typedef enum {
     PIP_OPT_MFMA_MIN_EDGES = 1,
     PIP_OPT_ALLPAIRS_CULL = 2,
     PIP_OPT_COST_CULL = 3,
     PIP_OPT_ALLPAIRS_PAIR = 4,
-    PIP_OPT_COST_PAIR = 5
+    PIP_OPT_COST_PAIR = 5,
+    PIP_OPT_RADIAL_MIN_EDGES = 6
 } pip_option;
 pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value);
 pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);
@@ -161,6 +175,21 @@ pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);
  */
 pip_status polygon_to_generators(pip_ctx ctx, const double *V, int32_t n, double *P,
                                  int32_t *status, hipStream_t stream);
+
+/*
+ * Thresholds of the radial pre-screen of pip_voronoi (Section 4, Eq. 1 and
+ * 9-11 read as a nearest-generator test), for tests and diagnostics.
+ *   V    [n][2] binary64 vertices, 3 <= n <= PIP_MAX_EDGES.
+ *   out  [17] float32 (device): out[o] = T_in and out[8 + o] = T_out of octant
+ *        o = 4 s(X) + 2 s(Y) + (|Y| > |X|) (s = sign bit), out[16] = T_far,
+ *        where X, Y are a point's float32 local coordinates (point minus
+ *        fl32(p_0)) and r2 = fl32(X^2 + Y^2): r2 < T_in means the label is
+ *        inside, T_out < r2 < T_far that it is outside.  A polygon that is not
+ *        valid and convex gets T_in = 0, T_out = +inf.
+ * Asynchronous on `stream`; allocates nothing.
+ */
+pip_status pip_voronoi_radial_bounds(pip_ctx ctx, const double *V, int32_t n, float *out,
+                                     hipStream_t stream);
 
 /*
  * Voronoi point-inclusion test (Section 4, Algorithm 5) of m points against

@@ -15,6 +15,7 @@ PIP_OPT_ALLPAIRS_CULL = 2
 PIP_OPT_COST_CULL = 3
 PIP_OPT_ALLPAIRS_PAIR = 4
 PIP_OPT_COST_PAIR = 5
+PIP_OPT_RADIAL_MIN_EDGES = 6
 
 STATUS_NAMES = {
     0: "PIP_OK", 1: "PIP_EINVAL", 2: "PIP_EDEGENERATE", 3: "PIP_ENONCONVEX", 4: "PIP_EHIP",
@@ -53,6 +54,7 @@ SIGNATURES = {
     "pip_last_error": (_c.c_char_p, [_vp]),
     "polygon_to_generators": (_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
     "pip_voronoi": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
+    "pip_voronoi_radial_bounds": (_int, [_vp, _vp, _i32, _vp, _vp]),
     "pip_sign_of_offset": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_ray_crossing": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_voronoi_fp32_plain": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),

@@ -129,6 +129,19 @@ def pip_voronoi(V, Q, labels=None, status=None):
     return _run_labels("pip_voronoi", V, Q, labels, status)
 
 
+def pip_voronoi_radial_bounds(V):
+    """Thresholds of pip_voronoi's radial pre-screen: float32 tensor [17] =
+    T_in[8], T_out[8] (octant o = 4 s(X) + 2 s(Y) + (|Y| > |X|), s = sign
+    bit of the float32 local coordinate) and T_far."""
+    V = _polygon(V)
+    d = _dev(V)
+    out = torch.empty(17, dtype=torch.float32, device=V.device)
+    ctx = context(d)
+    s = _lib().pip_voronoi_radial_bounds(ctx, V.data_ptr(), V.shape[0], out.data_ptr(), _stream(d))
+    _check(s, "pip_voronoi_radial_bounds", ctx)
+    return out
+
+
 def pip_sign_of_offset(V, Q, labels=None, status=None):
     return _run_labels("pip_sign_of_offset", V, Q, labels, status)
 

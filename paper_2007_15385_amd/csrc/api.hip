@@ -19,6 +19,8 @@ struct pip_ctx_s {
     int raster_blocks = 0;         // persistent grid of the raster kernel
     int batched_blocks_per_cu = 0;
     int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
+    int radial_min_edges = 20;     // Voronoi polygons with at least this many edges: radial pre-screen
+    int radial_blocks = 0;         // persistent grid of the radial kernel
     int allpairs_cull = 0;         // skip (polygon, wave) pairs whose bounding disk misses the points
     int cost_cull = 0;             // skip (pose, wave) pairs of the collision cost likewise
     int allpairs_pair = 0;         // antipodal edge pairs for centrally symmetric polygons
@@ -168,6 +170,16 @@ int mfma_blocks(pip_ctx ctx, int kind, int n) {
     return b;
 }
 
+int radial_blocks(pip_ctx ctx) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (ctx->radial_blocks == 0) {
+        int per_cu = 0;
+        if (pipdev::radial_max_blocks_per_cu(&per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
+        ctx->radial_blocks = per_cu * ctx->cu_count;
+    }
+    return ctx->radial_blocks;
+}
+
 pip_status run_stream(pip_ctx ctx, int kind, const double* V, int32_t n, const void* Q,
                       pip_dtype qdt, int64_t m, uint32_t* labels, float* margin,
                       int32_t* status, hipStream_t stream) {
@@ -201,7 +213,13 @@ pip_status run_stream(pip_ctx ctx, int kind, const double* V, int32_t n, const v
               ctx->mfma_min_edges > 0 && n >= ctx->mfma_min_edges)
                  ? 1
                  : 0;
-    L.max_blocks = L.mfma ? mfma_blocks(ctx, kind, n) : persistent_blocks(ctx, kind, (int)qdt);
+    L.radial = (qdt == PIP_F32 && kind == pipdev::K_VORONOI && ctx->radial_min_edges > 0 &&
+                n >= ctx->radial_min_edges)
+                   ? 1
+                   : 0;
+    L.max_blocks = L.radial ? radial_blocks(ctx)
+                 : L.mfma   ? mfma_blocks(ctx, kind, n)
+                            : persistent_blocks(ctx, kind, (int)qdt);
     L.stream = stream;
     if (qdt == PIP_F32 && kind != pipdev::K_RAY && kind != pipdev::K_MARGIN) {
         // the recheck queues code a point as (chunk iteration << 9 | point):
@@ -272,6 +290,20 @@ pip_status polygon_to_generators(pip_ctx ctx, const double* V, int32_t n, double
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_generators_one(V, n, P, status, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+pip_status pip_voronoi_radial_bounds(pip_ctx ctx, const double* V, int32_t n, float* out,
+                                     hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    pip_status s = check_polygon(V, n);
+    if (s != PIP_OK) return s;
+    if (!out) return fail(PIP_EINVAL, "out is NULL");
+    if (!aligned(out, 4)) return fail(PIP_EINVAL, "out is not 4-byte aligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_radial_bounds(V, n, out, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -1232,6 +1264,11 @@ pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
             if (value != 0 && value != 1) return fail(PIP_EINVAL, "PIP_OPT_COST_PAIR must be 0 or 1");
             ctx->cost_pair = (int)value;
             return PIP_OK;
+        case PIP_OPT_RADIAL_MIN_EDGES:
+            if (value < 0 || value > PIP_MAX_EDGES + 1)
+                return fail(PIP_EINVAL, "PIP_OPT_RADIAL_MIN_EDGES must be in [0, %d]", PIP_MAX_EDGES + 1);
+            ctx->radial_min_edges = (int)value;
+            return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
@@ -1253,6 +1290,9 @@ pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
             return PIP_OK;
         case PIP_OPT_COST_PAIR:
             *value = ctx->cost_pair;
+            return PIP_OK;
+        case PIP_OPT_RADIAL_MIN_EDGES:
+            *value = ctx->radial_min_edges;
             return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);

@@ -19,6 +19,7 @@ struct StreamLaunch {
     int32_t* status;      // device [1] or null
     int max_blocks;       // upper bound on the persistent grid
     int mfma;             // 1: matrix-core margins (float32 points, Voronoi / sign of offset)
+    int radial;           // 1: radial pre-screen (float32 points, Voronoi); wins over mfma
     hipStream_t stream;
 };
 
@@ -26,6 +27,8 @@ hipError_t launch_stream_mfma(const StreamLaunch& L);
 hipError_t stream_mfma_max_blocks_per_cu(int kind, int n, int* out);
 
 hipError_t launch_stream(const StreamLaunch& L);
+hipError_t radial_max_blocks_per_cu(int* out);
+hipError_t launch_radial_bounds(const double* V, int n, float* out, hipStream_t stream);
 
 // Per-polygon table row of the batched and all-pairs paths.
 struct alignas(16) PolyHdr {

@@ -17,6 +17,7 @@
 // afterwards with an atomic OR by the same wave, after a fence.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "radial.hpp"
 #include "stream32.hpp"
 
 using namespace pipdev;
@@ -445,6 +446,232 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     }
 }
 
+// ----------------------------------------------------------------------------
+// Voronoi with the radial pre-screen (radial.hpp).  The fast path of a chunk
+// costs a few operations per point: r2 = fl32(X^2 + Y^2), the octant's two
+// thresholds from LDS and three compares decide every point closer to p_0
+// than the octant's inner radius (inside) or beyond its outer radius
+// (outside).  The chunk's label words are stored at once with the other
+// points' bits 0; those points (coordinates as loaded and a position code,
+// as in the recheck queue) enter a per-wave ring in LDS.
+//
+// The ring is consumed in rounds of 64 entries, one per lane, at most one
+// round per chunk in the steady state, while the wave's next chunk is being
+// loaded: a round's LDS and arithmetic latency hides behind that load instead
+// of stopping the stream.  A lane screens its point against the candidate
+// edges of the point's octant (radial.hpp) with the band of the float32
+// screen, re-decides it in binary64 over the same edges when the band leaves
+// it undecided, and sets its inside bit with an atomic OR.
+//
+// A round only takes entries of chunks at least two iterations old: the
+// store of chunk k - 2 was issued before the loads of chunk k, and vector
+// memory operations complete in issue order, so waiting for chunk k's points
+// has completed that store and no OR can be overtaken by it.  When a push
+// would overflow the ring, rounds run first (waiting for every store if no
+// old entry is left); at the end the wave waits for its stores and empties
+// the ring.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// One round: entries head .. head + cnt - 1 of the ring (cnt <= 64), entry
+// head + l on lane l.  Every lane walks the wave's longest candidate list;
+// a shorter list is padded with repeats, so no lane needs a mask.
+__device__ __forceinline__ void radial_round(const PolyLds& S, const RadialTab& R, const uint32_t* qc,
+                                             const float2* qp, uint32_t head, int cnt,
+                                             uint32_t* labels, int lane, int64_t c0,
+                                             int64_t stride) {
+    const bool valid = lane < cnt;
+    const uint32_t slot = (head + (uint32_t)lane) & (kQueue32 - 1);
+    const float2 q = qp[slot];
+    const uint32_t cd = qc[slot];
+    const float X = q.x - S.ox, Y = q.y - S.oy;
+    const int c = radial_class(R, X, Y);
+    const uint8_t* list = R.list[c];
+    const int len = wave_max_int(valid ? R.len4[c] : 0);
+    float M = -__builtin_huge_valf();
+    for (int t = 0; t < len; t += 4) {
+        const uint32_t ix = *reinterpret_cast<const uint32_t*>(list + t);  // 4 edge indices
+        const float4 k0 = S.coef[ix & 255u], k1 = S.coef[(ix >> 8) & 255u];
+        const float4 k2 = S.coef[(ix >> 16) & 255u], k3 = S.coef[ix >> 24];
+        const float m0 = fmaf(k0.x, X, fmaf(k0.y, Y, k0.z));
+        const float m1 = fmaf(k1.x, X, fmaf(k1.y, Y, k1.z));
+        const float m2 = fmaf(k2.x, X, fmaf(k2.y, Y, k2.z));
+        const float m3 = fmaf(k3.x, X, fmaf(k3.y, Y, k3.z));
+        M = fmaxf(fmaxf(M, m0), m1);
+        M = fmaxf(fmaxf(M, m2), m3);
+    }
+    const float r2 = fmaf(X, X, Y * Y);
+    const float E = fmaf(S.KQ, r2, fmaf(S.KA, fabsf(X), fmaf(S.KB, fabsf(Y), S.KC)));
+    bool in = valid && M < -E;
+    if (valid && !(M < -E) && !(M > E))  // inside the band: binary64, Algorithm 5
+        in = voronoi64_list((double)q.x, (double)q.y, S.gen, list, R.len4[c]);
+    if (in) {
+        const int64_t idx = (c0 + (int64_t)(cd >> 9) * stride) * kChunk32 + (cd & 511u);
+        or_label_bit(labels, idx >> 5, (uint32_t)(idx & 31));
+    }
+}
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_stream32_radial(
+    const double* __restrict__ V, int n, const float2* __restrict__ Q, int64_t m,
+    uint32_t* __restrict__ labels, int32_t* __restrict__ status) {
+    __shared__ PolyLds S;
+    __shared__ RadialTab R;
+    __shared__ uint32_t queue_c[kWavesPerBlock][kQueue32];
+    __shared__ float2 queue_p[kWavesPerBlock][kQueue32];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int64_t nfull = m / kChunk32;
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t c0 = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    int64_t chunk = c0;
+    uint32_t k = 0;  // chunks of this wave so far
+
+    double2 vt = make_double2(0.0, 0.0);
+    if (tid < n) vt = make_double2(V[2 * tid], V[2 * tid + 1]);
+    float2 pa[kP32], pb[kP32];
+    if (nfull > 0) load_full32(Q, chunk < nfull ? chunk : nfull - 1, lane, pa);
+
+    if (tid < n) S.vtx[tid] = vt;
+    if (tid == 0) S.n = n;
+    __syncthreads();
+    if (wv == 0) {
+        prepare_polygon(S, K_VORONOI, lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        prepare_radial(S, lane, R);
+    }
+    __syncthreads();
+    if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
+
+    const float ox = S.ox, oy = S.oy;
+    const float tfar = R.tfar;
+    const char* tab = reinterpret_cast<const char*>(R.t);
+    uint32_t* qc = queue_c[wv];
+    float2* qp = queue_p[wv];
+    // ring positions (wave-uniform, counting pushes modulo 2^32): entries
+    // head .. tail - 1; those before `safe` belong to chunks at least two
+    // iterations old.  tail - head never exceeds the ring size.
+    uint32_t head = 0, tail = 0, tail_prev = 0;
+
+    auto process = [&](const float2(&p)[kP32], int64_t ch, int64_t rem) {
+        uint32_t safe = tail_prev;  // tail after the push of chunk k - 2
+        tail_prev = tail;           // tail after the push of chunk k - 1
+        const bool full = rem >= kChunk32;
+        uint64_t inm[kP32], amb[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            const float X = p[j].x - ox, Y = p[j].y - oy;
+            const float r2 = fmaf(X, X, Y * Y);
+            // octant byte offset: 32 sign(X) + 16 sign(Y) + 8 (|Y| > |X|)
+            const uint32_t off = ((__float_as_uint(X) >> 31) << 5) | ((__float_as_uint(Y) >> 31) << 4) |
+                                 (fabsf(Y) > fabsf(X) ? 8u : 0u);
+            const float2 t = *reinterpret_cast<const float2*>(tab + off);
+            const bool in = r2 < t.x;
+            const bool out = (r2 > t.y) & (r2 < tfar);
+            inm[j] = __ballot(in);
+            amb[j] = ~(inm[j] | __ballot(out));
+        }
+        if (!full) {
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const uint64_t vm = __ballot(lane + kWave * j < rem);
+                inm[j] &= vm;
+                amb[j] &= vm;
+            }
+        }
+        const uint32_t w = chunk_word32(inm);
+        const int64_t nw = full ? kWords32 : (rem + 31) / 32;
+        if (lane < nw) labels[ch * kWords32 + lane] = w;
+        int na = 0;
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) na += __popcll(amb[j]);
+        if (na != 0) {
+            while (tail - head + (uint32_t)na > (uint32_t)kQueue32) {  // make room
+                if (safe == head) {  // no old entry left: wait for every store
+                    wave_drain();
+                    safe = tail;
+                }
+                const int cnt = min((int)(safe - head), kWave);
+                radial_round(S, R, qc, qp, head, cnt, labels, lane, c0, stride);
+                head += (uint32_t)cnt;
+            }
+            const uint64_t lt = lanemask_lt();
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                if ((amb[j] >> lane) & 1ull) {
+                    const uint32_t slot = (tail + (uint32_t)__popcll(amb[j] & lt)) & (kQueue32 - 1);
+                    qc[slot] = (k << 9) | (uint32_t)(lane + kWave * j);
+                    qp[slot] = p[j];
+                }
+                tail += (uint32_t)__popcll(amb[j]);
+            }
+        }
+        if (safe - head >= (uint32_t)kWave) {  // one full round of old entries
+            radial_round(S, R, qc, qp, head, kWave, labels, lane, c0, stride);
+            head += kWave;
+        }
+        ++k;
+    };
+
+    for (;;) {
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pb);
+        process(pa, chunk, kChunk32);
+        chunk += stride;
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pa);
+        process(pb, chunk, kChunk32);
+        chunk += stride;
+    }
+    if (chunk == nfull && nfull * kChunk32 < m) {  // the partial chunk
+        const int64_t base = nfull * kChunk32;
+        const int rem = (int)(m - base);
+        float2 pt[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            const int r = lane + kWave * j;
+            pt[j] = Q[base + (r < rem ? r : rem - 1)];
+        }
+        process(pt, chunk, rem);
+    }
+    if (head != tail) {  // the rest of the ring, after every store of this wave
+        wave_drain();
+        while (head != tail) {
+            const int cnt = min((int)(tail - head), kWave);
+            radial_round(S, R, qc, qp, head, cnt, labels, lane, c0, stride);
+            head += (uint32_t)cnt;
+        }
+    }
+}
+
+// Thresholds of the radial pre-screen, for tests and diagnostics: one wave
+// prepares the polygon and writes T_in[8], T_out[8], T_far.
+__global__ __launch_bounds__(kWave) void k_radial_bounds(const double* __restrict__ V, int n,
+                                                        float* __restrict__ out) {
+    __shared__ PolyLds S;
+    __shared__ RadialTab R;
+    const int lane = threadIdx.x;
+    if (lane < n) S.vtx[lane] = make_double2(V[2 * lane], V[2 * lane + 1]);
+    if (lane == 0) S.n = n;
+    __syncthreads();
+    prepare_polygon(S, K_VORONOI, lane);
+    __syncthreads();
+    prepare_radial(S, lane, R);
+    __syncthreads();
+    if (lane < 8) {
+        out[lane] = R.t[lane].x;
+        out[8 + lane] = R.t[lane].y;
+    }
+    if (lane == 0) out[16] = R.tfar;
+}
+
 // polygon_to_generators: one wave derives p_0 and the n outer generators.
 __global__ __launch_bounds__(kWave) void k_generators_one(const double* __restrict__ V, int n,
                                                          double* __restrict__ P,
@@ -474,6 +701,16 @@ hipError_t launch_stream32_t(const StreamLaunch& L) {
     return hipGetLastError();
 }
 
+hipError_t launch_stream32_radial(const StreamLaunch& L) {
+    const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
+    const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
+    int grid = (int)(want < L.max_blocks ? want : L.max_blocks);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_stream32_radial, dim3(grid), dim3(kBlock), 0, L.stream, L.V, L.n,
+                       static_cast<const float2*>(L.Q), L.m, L.labels, L.status);
+    return hipGetLastError();
+}
+
 template <int KIND, typename PT>
 hipError_t launch_stream_t(const StreamLaunch& L) {
     const int64_t nchunks = (L.m + kChunk - 1) / kChunk;
@@ -491,6 +728,7 @@ namespace pipdev {
 
 hipError_t launch_stream(const StreamLaunch& L) {
     const bool f64 = L.qdt == 1;
+    if (L.radial && !f64 && L.kind == K_VORONOI) return launch_stream32_radial(L);
     if (L.mfma && !f64 && (L.kind == K_VORONOI || L.kind == K_SOO)) return launch_stream_mfma(L);
     switch (L.kind) {
         case K_VORONOI:
@@ -526,6 +764,15 @@ hipError_t stream_max_blocks_per_cu(int kind, int qdt, int* out) {
         default: return hipErrorInvalidValue;
     }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, f, kBlock, 0);
+}
+
+hipError_t radial_max_blocks_per_cu(int* out) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)k_stream32_radial, kBlock, 0);
+}
+
+hipError_t launch_radial_bounds(const double* V, int n, float* out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_radial_bounds, dim3(1), dim3(kWave), 0, stream, V, n, out);
+    return hipGetLastError();
 }
 
 }  // namespace pipdev

@@ -32,14 +32,17 @@ def P():
     return P
 
 
-@pytest.fixture(autouse=True, params=["mfma", "valu"])
+@pytest.fixture(autouse=True, params=["radial", "mfma", "valu"])
 def screen(request, P):
-    """Every test runs with the matrix-core screen for all polygon sizes and
-    with the vector screen for all sizes (the default switches at 12 edges)."""
-    old = P.get_option(P.PIP_OPT_MFMA_MIN_EDGES)
+    """Every test runs with each float32 screen forced for all polygon sizes:
+    the radial pre-screen (Voronoi only; the other tests take the vector
+    screen), the matrix-core screen and the vector screen."""
+    old = (P.get_option(P.PIP_OPT_MFMA_MIN_EDGES), P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES))
     P.set_option(P.PIP_OPT_MFMA_MIN_EDGES, 3 if request.param == "mfma" else 0)
+    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 3 if request.param == "radial" else 0)
     yield request.param
-    P.set_option(P.PIP_OPT_MFMA_MIN_EDGES, old)
+    P.set_option(P.PIP_OPT_MFMA_MIN_EDGES, old[0])
+    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, old[1])
 
 
 TESTS = {
