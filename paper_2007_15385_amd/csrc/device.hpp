@@ -56,8 +56,13 @@ struct alignas(32) PolyLds {
     double2 vtx[kMaxEdges];          // vertices v_0..v_{n-1}
     double2 gen[kMaxEdges + 1];      // p_0, then p_i for edge i (v_{i-1} -> v_i)
     float4 coef[kMaxEdges];          // float32 filter coefficients, padded by copies of edge 0
-    double4 ray[kMaxEdges];          // ray crossing: (V'_y, V_y, dV_x, dV_y)
-    double rhs[kMaxEdges];           // ray crossing: RHS of the line equation
+    union {
+        struct {
+            double4 ray[kMaxEdges];  // ray crossing: (V'_y, V_y, dV_x, dV_y)
+            double rhs[kMaxEdges];   // ray crossing: RHS of the line equation
+        };
+        uint32_t aux[kMaxEdges * 10];  // free for kernels that never take the ray-crossing test
+    };
     float ox, oy;                    // float32 local origin
     float KQ, KA, KB, KC;            // band E = KQ (X^2 + Y^2) + KA |X| + KB |Y| + KC
     int n, n4, status;

@@ -451,26 +451,26 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
 // costs a few operations per point: r2 = fl32(X^2 + Y^2), the octant's two
 // thresholds from LDS and three compares decide every point closer to p_0
 // than the octant's inner radius (inside) or beyond its outer radius
-// (outside).  The chunk's label words are stored at once with the other
-// points' bits 0; those points (coordinates as loaded and a position code,
-// as in the recheck queue) enter a per-wave ring in LDS.
+// (outside).  The other points (coordinates as loaded and a position code)
+// enter a per-wave ring in LDS.
 //
-// The ring is consumed in rounds of 64 entries, one per lane, at most one
-// round per chunk in the steady state, while the wave's next chunk is being
-// loaded: a round's LDS and arithmetic latency hides behind that load instead
-// of stopping the stream.  A lane screens its point against the candidate
-// edges of the point's octant (radial.hpp) with the band of the float32
-// screen, re-decides it in binary64 over the same edges when the band leaves
-// it undecided, and sets its inside bit with an atomic OR.
-//
-// A round only takes entries of chunks at least two iterations old: the
-// store of chunk k - 2 was issued before the loads of chunk k, and vector
-// memory operations complete in issue order, so waiting for chunk k's points
-// has completed that store and no OR can be overtaken by it.  When a push
-// would overflow the ring, rounds run first (waiting for every store if no
-// old entry is left); at the end the wave waits for its stores and empties
-// the ring.
+// The label words of the wave's last eight chunks stay in LDS (in the
+// polygon block's space for the ray-crossing test, unused here).  The ring
+// is consumed in rounds of 64 entries, one per lane: a lane screens its point
+// against the candidate edges of the point's octant (radial.hpp) with the
+// band of the float32 screen, re-decides it in binary64 over the same edges
+// when the band leaves it undecided, and sets its inside bit in the LDS copy
+// of the word with an LDS atomic OR.  A full round runs whenever 64 entries
+// wait; a chunk's words go to memory with one plain store seven chunks later,
+// after its remaining entries have been settled (in a partial round if the
+// full rounds have not reached them).  No global read-modify-write is needed
+// and a chunk costs a fixed set of memory operations (its loads and one
+// store).
 // ----------------------------------------------------------------------------
+constexpr int kSlots = 8;  // chunks whose label words stay in LDS
+static_assert(kWavesPerBlock * kSlots * kWords32 <= kMaxEdges * 10,
+              "the word rings fit the polygon block's free space");
+
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
@@ -479,11 +479,11 @@ __device__ __forceinline__ int wave_max_int(int v) {
 
 // One round: entries head .. head + cnt - 1 of the ring (cnt <= 64), entry
 // head + l on lane l.  Every lane walks the wave's longest candidate list;
-// a shorter list is padded with repeats, so no lane needs a mask.
+// a shorter list is padded with repeats, so no lane needs a mask.  An entry's
+// code is (slot << 9) | r for point r of the chunk in word-ring slot `slot`.
 __device__ __forceinline__ void radial_round(const PolyLds& S, const RadialTab& R, const uint32_t* qc,
                                              const float2* qp, uint32_t head, int cnt,
-                                             uint32_t* labels, int lane, int64_t c0,
-                                             int64_t stride) {
+                                             uint32_t (*words)[kWords32], int lane) {
     const bool valid = lane < cnt;
     const uint32_t slot = (head + (uint32_t)lane) & (kQueue32 - 1);
     const float2 q = qp[slot];
@@ -509,10 +509,7 @@ __device__ __forceinline__ void radial_round(const PolyLds& S, const RadialTab& 
     bool in = valid && M < -E;
     if (valid && !(M < -E) && !(M > E))  // inside the band: binary64, Algorithm 5
         in = voronoi64_list((double)q.x, (double)q.y, S.gen, list, R.len4[c]);
-    if (in) {
-        const int64_t idx = (c0 + (int64_t)(cd >> 9) * stride) * kChunk32 + (cd & 511u);
-        or_label_bit(labels, idx >> 5, (uint32_t)(idx & 31));
-    }
+    if (in) atomicOr(&words[(cd >> 9) & (kSlots - 1)][(cd & 511u) >> 5], 1u << (cd & 31u));
 }
 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_stream32_radial(
@@ -522,7 +519,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     __shared__ RadialTab R;
     __shared__ uint32_t queue_c[kWavesPerBlock][kQueue32];
     __shared__ float2 queue_p[kWavesPerBlock][kQueue32];
-
+    __shared__ uint32_t ring_end[kWavesPerBlock][kSlots];  // ring tail after each slot's push
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -549,21 +546,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     }
     __syncthreads();
     if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
-
     const float ox = S.ox, oy = S.oy;
     const float tfar = R.tfar;
     const char* tab = reinterpret_cast<const char*>(R.t);
     uint32_t* qc = queue_c[wv];
     float2* qp = queue_p[wv];
+    uint32_t(*words)[kWords32] =
+        reinterpret_cast<uint32_t(*)[kWords32]>(S.aux + wv * kSlots * kWords32);
+    uint32_t* ends = ring_end[wv];
     // ring positions (wave-uniform, counting pushes modulo 2^32): entries
-    // head .. tail - 1; those before `safe` belong to chunks at least two
-    // iterations old.  tail - head never exceeds the ring size.
-    uint32_t head = 0, tail = 0, tail_prev = 0;
+    // head .. tail - 1; tail - head never exceeds the ring size
+    uint32_t head = 0, tail = 0;
 
-    auto process = [&](const float2(&p)[kP32], int64_t ch, int64_t rem) {
-        uint32_t safe = tail_prev;  // tail after the push of chunk k - 2
-        tail_prev = tail;           // tail after the push of chunk k - 1
+    // settle every entry pushed before `end` (partial rounds allowed)
+    auto settle = [&](uint32_t end) {
+        while ((int)(end - head) > 0) {
+            const int cnt = min((int)(end - head), kWave);
+            radial_round(S, R, qc, qp, head, cnt, words, lane);
+            head += (uint32_t)cnt;
+        }
+    };
+    // words of the wave's i-th chunk (i < k) from LDS to memory
+    auto store_chunk = [&](uint32_t i) {
+        const int64_t ch = c0 + (int64_t)i * stride;
+        const int64_t nw = ch < nfull ? kWords32 : ((m - nfull * kChunk32) + 31) / 32;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < nw) labels[ch * kWords32 + lane] = words[i & (kSlots - 1)][lane];
+    };
+    auto process = [&](const float2(&p)[kP32], int64_t rem) {
         const bool full = rem >= kChunk32;
+        const uint32_t sl = k & (kSlots - 1);
         uint64_t inm[kP32], amb[kP32];
 #pragma unroll
         for (int j = 0; j < kP32; ++j) {
@@ -587,19 +599,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             }
         }
         const uint32_t w = chunk_word32(inm);
-        const int64_t nw = full ? kWords32 : (rem + 31) / 32;
-        if (lane < nw) labels[ch * kWords32 + lane] = w;
+        if (lane < kWords32) words[sl][lane] = w;
         int na = 0;
 #pragma unroll
         for (int j = 0; j < kP32; ++j) na += __popcll(amb[j]);
         if (na != 0) {
             while (tail - head + (uint32_t)na > (uint32_t)kQueue32) {  // make room
-                if (safe == head) {  // no old entry left: wait for every store
-                    wave_drain();
-                    safe = tail;
-                }
-                const int cnt = min((int)(safe - head), kWave);
-                radial_round(S, R, qc, qp, head, cnt, labels, lane, c0, stride);
+                const int cnt = min((int)(tail - head), kWave);
+                radial_round(S, R, qc, qp, head, cnt, words, lane);
                 head += (uint32_t)cnt;
             }
             const uint64_t lt = lanemask_lt();
@@ -607,27 +614,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             for (int j = 0; j < kP32; ++j) {
                 if ((amb[j] >> lane) & 1ull) {
                     const uint32_t slot = (tail + (uint32_t)__popcll(amb[j] & lt)) & (kQueue32 - 1);
-                    qc[slot] = (k << 9) | (uint32_t)(lane + kWave * j);
+                    // the lane index from the hardware, not a register kept live
+                    qc[slot] = (sl << 9) | ((uint32_t)__lane_id() + kWave * j);
                     qp[slot] = p[j];
                 }
                 tail += (uint32_t)__popcll(amb[j]);
             }
         }
-        if (safe - head >= (uint32_t)kWave) {  // one full round of old entries
-            radial_round(S, R, qc, qp, head, kWave, labels, lane, c0, stride);
+        if (lane == 0) ends[sl] = tail;
+        if (tail - head >= (uint32_t)kWave) {  // a full round
+            radial_round(S, R, qc, qp, head, kWave, words, lane);
             head += kWave;
+        }
+        if (k + 1 >= kSlots) {  // chunk k - 7 leaves the word ring before chunk k + 1 reuses its slot
+            const uint32_t old = k + 1 - kSlots;
+            __builtin_amdgcn_wave_barrier();
+            settle(ends[old & (kSlots - 1)]);
+            store_chunk(old);
         }
         ++k;
     };
-
     for (;;) {
         if (chunk >= nfull) break;
         load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pb);
-        process(pa, chunk, kChunk32);
+        process(pa, kChunk32);
         chunk += stride;
         if (chunk >= nfull) break;
         load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pa);
-        process(pb, chunk, kChunk32);
+        process(pb, kChunk32);
         chunk += stride;
     }
     if (chunk == nfull && nfull * kChunk32 < m) {  // the partial chunk
@@ -639,16 +653,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             const int r = lane + kWave * j;
             pt[j] = Q[base + (r < rem ? r : rem - 1)];
         }
-        process(pt, chunk, rem);
+        process(pt, rem);
     }
-    if (head != tail) {  // the rest of the ring, after every store of this wave
-        wave_drain();
-        while (head != tail) {
-            const int cnt = min((int)(tail - head), kWave);
-            radial_round(S, R, qc, qp, head, cnt, labels, lane, c0, stride);
-            head += (uint32_t)cnt;
-        }
-    }
+    settle(tail);  // every entry, then the chunks still in the word ring
+    for (uint32_t i = k >= kSlots - 1 ? k - (kSlots - 1) : 0; i < k; ++i) store_chunk(i);
 }
 
 // Thresholds of the radial pre-screen, for tests and diagnostics: one wave
