@@ -282,6 +282,23 @@ def run_extras(P, W, torch, stream, check):
         tfl = 4.0 * n * N * N / (ms_r * 1e-3) / 1e12
         e = {"ms": round(ms_r, 4), "gpixels_per_s": round(N * N / ms_r / 1e6, 1),
              "fp32_tflops": round(tfl, 2), "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)}
+        radial_min = int(P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES))
+        if radial_min > 0 and n >= radial_min:
+            # the radial pre-screen decides most pixels from r2; the 4n flop
+            # figure above is the per-edge work it replaces.  The per-edge
+            # raster alone, for comparison:
+            e["screen"] = "radial"
+            e["per_edge_equivalent_tflops"] = e.pop("fp32_tflops")
+            e["fp32_frac"] = None  # the 4n flop per pixel are not executed
+            P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 0)
+            try:
+                e["per_edge_ms"] = round(_time(torch, stream, lambda: P.pip_voronoi_raster(
+                    Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N, labels=lab_r), reps=10), 4)
+            finally:
+                P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, radial_min)
+            lab_r = P.pip_voronoi_raster(Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N, labels=lab_r)
+        else:
+            e["screen"] = "per_edge"
         if check:
             rows = np.sort(rr.choice(N, 64, replace=False))
             got = lab_r.cpu().numpy().view(np.uint32)[rows]

@@ -147,8 +147,10 @@ typedef struct pip_index_s *pip_index;
  *     inside, beyond the outer one (and short of a far limit) one of them says
  *     outside.  Only the points in between take the per-edge screen (and, in
  *     its band, the binary64 recheck), so labels are unchanged.  Used for
- *     polygons with at least this many edges (before the matrix-core path);
- *     0 disables it.  Default 20 (measured: the per-edge screen is faster for
+ *     polygons with at least this many edges (before the matrix-core path),
+ *     and likewise by pip_voronoi_raster (with its own band, and the per-edge
+ *     screen for every 512-pixel segment that holds a pixel between the
+ *     radii); 0 disables it.  Default 20 (measured: the per-edge screen is faster for
  *     fewer edges, where more points fall between the radii).  Not from the
  *     paper: a screen in front of its test, from the nearest-generator
  *     reading of Section 4. */

@@ -16,7 +16,7 @@ struct pip_ctx_s {
     std::mutex mu;
     int stream_blocks[8][2] = {};  // cached persistent grid per (kind, dtype); 0 = unknown
     int mfma_blocks[2][4] = {};    // same for the matrix-core screen (kind, edge bucket)
-    int raster_blocks = 0;         // persistent grid of the raster kernel
+    int raster_blocks[2] = {};     // persistent grid of the raster kernel (per-edge, radial)
     int batched_blocks_per_cu = 0;
     int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
     int radial_min_edges = 20;     // Voronoi polygons with at least this many edges: radial pre-screen
@@ -358,18 +358,20 @@ pip_status pip_voronoi_raster(pip_ctx ctx, const double* V, int32_t n, double x0
     if (empty && !status) return PIP_OK;
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const int radial = ctx->radial_min_edges > 0 && n >= ctx->radial_min_edges ? 1 : 0;
     int blocks;
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
-        if (ctx->raster_blocks == 0) {
+        if (ctx->raster_blocks[radial] == 0) {
             int per_cu = 0;
-            if (pipdev::raster_max_blocks_per_cu(&per_cu) != hipSuccess || per_cu < 1) per_cu = 1;
-            ctx->raster_blocks = per_cu * ctx->cu_count;
+            if (pipdev::raster_max_blocks_per_cu(radial, &per_cu) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            ctx->raster_blocks[radial] = per_cu * ctx->cu_count;
         }
-        blocks = ctx->raster_blocks;
+        blocks = ctx->raster_blocks[radial];
     }
     pipdev::RasterGrid G{x0, y0, dx, dy, empty ? 0 : width, empty ? 0 : height};
-    hipError_t e = pipdev::launch_raster(V, n, G, labels, status, blocks, stream);
+    hipError_t e = pipdev::launch_raster(V, n, G, labels, status, radial, blocks, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }

@@ -129,8 +129,8 @@ struct RasterGrid {
     int64_t width, height;
 };
 hipError_t launch_raster(const double* V, int n, const RasterGrid& G, uint32_t* labels,
-                         int32_t* status, int max_blocks, hipStream_t stream);
-hipError_t raster_max_blocks_per_cu(int* out);
+                         int32_t* status, int radial, int max_blocks, hipStream_t stream);
+hipError_t raster_max_blocks_per_cu(int radial, int* out);
 struct CostLayout {
     size_t tab, part_cost, part_pose, part_gen, stage;
     int T;

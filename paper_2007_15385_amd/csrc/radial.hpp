@@ -117,13 +117,16 @@ __device__ __forceinline__ bool in_arc(double2 v, double2 s, double2 e) {
 // octant without an outer bound, lists every edge.
 //
 // Called by one whole wave after prepare_polygon (S.coef, S.K*, S.status set).
-__device__ inline void prepare_radial(const PolyLds& S, int lane, RadialTab& R) {
+// KC_band replaces the band's constant term where a kernel widens it (the
+// raster, whose pixel coordinates carry one more rounding); negative: S.KC.
+__device__ inline void prepare_radial(const PolyLds& S, int lane, RadialTab& R,
+                                      float KC_band = -1.0f) {
     const int n = S.n;
     const bool act = lane < n;
     const int i = act ? lane : 0;
     const int j = i + 1 < n ? i + 1 : 0;
     const float4 ci = S.coef[i], cj = S.coef[j];  // (A, B, -C)
-    const double KQ = S.KQ, KC = S.KC;
+    const double KQ = S.KQ, KC = KC_band >= 0.0f ? KC_band : S.KC;
     const double KAB = sqrt((double)S.KA * (double)S.KA + (double)S.KB * (double)S.KB);
     const double g = 2.0 * kU32 * (1.0 + kU32);
     const double ai = sqrt((double)ci.x * ci.x + (double)ci.y * ci.y);

@@ -23,18 +23,37 @@
 // band's own conversion, formed in binary64 once per segment.  Undecided
 // pixels are re-decided in binary64 on the spot from their recomputed
 // coordinates.
+//
+// With the radial pre-screen (radial.hpp, thresholds derived with the
+// raster's band constant), a pixel closer to p_0 than its octant's inner
+// radius is inside and one beyond the outer radius outside, from r2 alone;
+// only the segments holding a pixel between the radii run the per-edge
+// screen (rows cross the polygon's boundary at two places, so most segments
+// need no margin at all).  A whole segment is decided first when it can be:
+// X = fl32(i dx + b) is monotone in the pixel index i and r2 =
+// fl32(X^2 + Y^2) in |X| (correctly rounded operations keep order), so the
+// segment's largest r2 is at an end pixel and its smallest at the other end,
+// or at least fl32(Y^2) if X changes sign.  Along a row the octant of a pixel
+// (sign bits of X and Y, |Y| > |X|) runs through four octants in a fixed
+// order as X grows (Y >= 0: 4, 5, 1, 0; Y < 0: 6, 7, 3, 2), so a segment's
+// pixels lie in the octants between those of its end pixels.  Below the
+// smallest T_in of those octants every pixel is inside; beyond their largest
+// T_out (and short of T_far) every pixel is outside, with no per-pixel work.
 #include "device.hpp"
 #include "kernels.hpp"
+#include "radial.hpp"
 #include "stream32.hpp"
 
 using namespace pipdev;
 
 namespace {
 
+template <bool RADIAL>
 __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V, int n,
                                                  RasterGrid G, uint32_t* __restrict__ labels,
                                                  int32_t* __restrict__ status) {
     __shared__ PolyLds S;
+    __shared__ RadialTab R;
     __shared__ float KC_s;                                // band constant with the X term
     __shared__ float ax_s[kMaxEdges];                     // A_i
     __shared__ float cy_s[kWavesPerBlock][kMaxEdges];     // fma(B_i, Y, -C_i) of the segment's row
@@ -57,6 +76,12 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
             const double DX = 1.02 * kU32 * T + 2.0 * kU64 * (fabs(G.x0) + span);
             const double infl = 1.0 + 9.5367431640625e-07;  // 1 + 2^-20
             KC_s = round_up_f32(((double)S.KC + alpha * DX + 50.0 * kU64 * (T + DX) * DX) * infl);
+        }
+        if constexpr (RADIAL) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            prepare_radial(S, lane, R, KC_s);
         }
     }
     __syncthreads();
@@ -84,6 +109,45 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
         }
         const double py = G.y0 + (double)row * G.dy;
         const float Y = (float)(py - (double)oy);
+        const int64_t left = row_words - s * kWords32;
+        const int nw = left < kWords32 ? (int)left : kWords32;
+        if constexpr (RADIAL) {  // the whole segment at once, from its end pixels
+            const int i0 = (int)s * kChunk32;
+            const int64_t rem = G.width - (int64_t)i0;
+            const int last = i0 + (rem < kChunk32 ? (int)rem : kChunk32) - 1;
+            const float yy = Y * Y;
+            const float Xa = fmaf((float)i0, dxf, bxf), Xb = fmaf((float)last, dxf, bxf);
+            const float ra = fmaf(Xa, Xa, yy), rb = fmaf(Xb, Xb, yy);
+            const float rmax = fmaxf(ra, rb);
+            const float rmin = (Xa < 0.0f) != (Xb < 0.0f) ? yy : fminf(ra, rb);
+            // position along the row's octant sequence: 0 (X < 0, |Y| <= |X|),
+            // 1 (X < 0, |Y| > |X|), 2 (X >= 0, |Y| > |X|), 3 (X >= 0, |Y| <= |X|);
+            // "X < 0" is the sign bit, as in the per-pixel octant
+            const auto seq = [&](float X) {
+                const bool neg = (__float_as_uint(X) >> 31) != 0;
+                const bool steep = fabsf(Y) > fabsf(X);
+                return neg ? (steep ? 1 : 0) : (steep ? 2 : 3);
+            };
+            const int qa = seq(Xa), qb = seq(Xb);
+            const uint32_t sy = __float_as_uint(Y) >> 31;
+            float tin = __builtin_huge_valf(), tout = 0.0f;
+            for (int q = min(qa, qb); q <= max(qa, qb); ++q) {
+                const int o = (q < 2 ? 4 : 0) + 2 * (int)sy + ((q == 1 || q == 2) ? 1 : 0);
+                tin = fminf(tin, R.t[o].x);
+                tout = fmaxf(tout, R.t[o].y);
+            }
+            const bool all_in = rmax < tin;  // NaN: false
+            const bool all_out = rmin > tout && rmax < R.tfar;
+            if (all_in || all_out) {
+                uint32_t w = 0;
+                if (all_in) {  // bits of the segment's existing pixels
+                    const int64_t b = rem - 32 * (int64_t)lane;
+                    w = b >= 32 ? ~0u : (b > 0 ? (1u << b) - 1u : 0u);
+                }
+                if (lane < nw) labels[row * row_words + s * kWords32 + lane] = w;
+                continue;
+            }
+        }
         // this row's inner products, one edge per lane (same wave reads them)
         if (lane < n4) {
             const float4 c = S.coef[lane];
@@ -95,6 +159,26 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
         float X[kP32], M[kP32];
 #pragma unroll
         for (int j = 0; j < kP32; ++j) X[j] = fmaf((float)(i0 + lane + kWave * j), dxf, bxf);
+        uint64_t rin[kP32], ramb[kP32];  // radial decisions: inside, between the radii
+        uint64_t any_amb = ~0ull;
+        if constexpr (RADIAL) {
+            const char* tab = reinterpret_cast<const char*>(R.t);
+            const float tfar = R.tfar;
+            const uint32_t sy = (__float_as_uint(Y) >> 31) << 4;
+            const float yy = Y * Y;
+            any_amb = 0;
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const float r2 = fmaf(X[j], X[j], yy);  // the r2 of the thresholds
+                const uint32_t off = ((__float_as_uint(X[j]) >> 31) << 5) | sy |
+                                     (fabsf(Y) > fabsf(X[j]) ? 8u : 0u);
+                const float2 t = *reinterpret_cast<const float2*>(tab + off);
+                rin[j] = __ballot(r2 < t.x);
+                ramb[j] = ~(rin[j] | __ballot((r2 > t.y) & (r2 < tfar)));
+                any_amb |= ramb[j];
+            }
+        }
+        if (any_amb) {  // per-edge screen of the whole segment
         const float4* A4 = reinterpret_cast<const float4*>(ax_s);
         const float4* C4 = reinterpret_cast<const float4*>(cy_s[wv]);
         {  // edges 0-3 start the max (n4 >= 4)
@@ -113,14 +197,24 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
                 M[j] = fmaxf(fmaxf(M[j], fmaf(a.z, X[j], c.z)), fmaf(a.w, X[j], c.w));
             }
         }
+        }
         // inside: M < -E; undecided: !(|M| > E) (E >= 0; NaN undecided)
         uint64_t inm[kP32], unc[kP32];
         uint64_t any_unc = 0;
 #pragma unroll
         for (int j = 0; j < kP32; ++j) {
-            const float E = fmaf(KQ, X[j] * X[j], fmaf(KA, fabsf(X[j]), eY));
-            inm[j] = __ballot(M[j] < -E);
-            unc[j] = __ballot(!(fabsf(M[j]) > E));
+            if (any_amb) {
+                const float E = fmaf(KQ, X[j] * X[j], fmaf(KA, fabsf(X[j]), eY));
+                inm[j] = __ballot(M[j] < -E);
+                unc[j] = __ballot(!(fabsf(M[j]) > E));
+            } else {
+                inm[j] = 0;
+                unc[j] = 0;
+            }
+            if constexpr (RADIAL) {  // the radial decision wherever it has one
+                inm[j] = (inm[j] & ramb[j]) | rin[j];
+                unc[j] &= ramb[j];
+            }
             any_unc |= unc[j];
         }
         const int64_t rem = G.width - (int64_t)i0;  // pixels of this segment in the row
@@ -148,8 +242,6 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
             }
         }
         const uint32_t w = chunk_word32(inm);
-        const int64_t left = row_words - s * kWords32;
-        const int nw = left < kWords32 ? (int)left : kWords32;
         if (lane < nw) labels[row * row_words + s * kWords32 + lane] = w;
     }
 }
@@ -159,17 +251,21 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
 namespace pipdev {
 
 hipError_t launch_raster(const double* V, int n, const RasterGrid& G, uint32_t* labels,
-                         int32_t* status, int max_blocks, hipStream_t stream) {
+                         int32_t* status, int radial, int max_blocks, hipStream_t stream) {
     const int64_t segs = (G.width + kChunk32 - 1) / kChunk32 * G.height;
     const int64_t want = (segs + kWavesPerBlock - 1) / kWavesPerBlock;
     int grid = (int)(want < max_blocks ? want : max_blocks);
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_raster, dim3(grid), dim3(kBlock), 0, stream, V, n, G, labels, status);
+    if (radial)
+        hipLaunchKernelGGL(k_raster<true>, dim3(grid), dim3(kBlock), 0, stream, V, n, G, labels, status);
+    else
+        hipLaunchKernelGGL(k_raster<false>, dim3(grid), dim3(kBlock), 0, stream, V, n, G, labels, status);
     return hipGetLastError();
 }
 
-hipError_t raster_max_blocks_per_cu(int* out) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)k_raster, kBlock, 0);
+hipError_t raster_max_blocks_per_cu(int radial, int* out) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        out, radial ? (const void*)k_raster<true> : (const void*)k_raster<false>, kBlock, 0);
 }
 
 }  // namespace pipdev

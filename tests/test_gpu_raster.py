@@ -29,6 +29,16 @@ def P():
     return P
 
 
+@pytest.fixture(autouse=True, params=["radial", "per_edge"])
+def screen(request, P):
+    """Every test runs with the radial pre-screen forced for every polygon
+    size and with it off."""
+    old = P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES)
+    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 3 if request.param == "radial" else 0)
+    yield request.param
+    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, old)
+
+
 def raster_gpu(P, V, x0, y0, dx, dy, width, height, status=None):
     Vt = torch.from_numpy(np.ascontiguousarray(V, dtype=np.float64)).cuda()
     st = torch.full((1,), -7, dtype=torch.int32, device="cuda")
@@ -135,3 +145,22 @@ def test_raster_full_size(P, oracle):
     bad = int((got != want).sum())
     say(f"[stat] raster: {int(img.sum())} inside pixels, {bad} words differ")
     assert bad == 0
+
+
+def test_raster_full_size_64_edges_rows(P, oracle):
+    """The 16384 x 16384 raster of a 64-gon (the benchmark's second raster):
+    128 rows spread over the image, every label word against the oracle's
+    single-row raster at the same binary64 row coordinate."""
+    rng = np.random.default_rng(2007153852 + 64)
+    V = W.circle_polygon(64, 1.0, rng.uniform(-0.1, 0.1, 2), rng)
+    N = 16384
+    say("[case] raster 64-gon full size: GPU")
+    got = raster_gpu(P, V, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N)
+    rows = np.sort(np.random.default_rng(5).choice(N, 128, replace=False))
+    rows[:4] = [0, N // 2, N // 2 + 1, N - 1]
+    rows = np.unique(rows)
+    say("[case] raster 64-gon full size: oracle rows")
+    for j in rows:
+        img = oracle.voronoi_raster(V, -1.5, -1.5 + int(j) * (3.0 / N), 3.0 / N, 3.0 / N, N, 1)
+        want = np.packbits(img[0], bitorder="little").view(np.uint32)
+        assert np.array_equal(got[j], want), f"row {j}"
