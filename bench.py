@@ -198,6 +198,37 @@ def run_extras(P, W, torch, stream, check):
         entry["mismatches_48_polygons"] = bad
     out["uneven_batch"] = entry
     plan.close()
+
+    # a batch of 32-edge polygons: the radial pre-screen (default from 20
+    # edges) against the per-edge screen, each in its own autotuned plan
+    B32 = W.uneven_batch(n_lo=32, n_hi=32)
+    t32 = [torch.from_numpy(a).to(dev) for a in (B32.vtx_off, B32.V, B32.pt_off, B32.Q,
+                                                   B32.lbl_word_off)]
+    e32 = {"polygons": B32.num_polygons, "tests": B32.num_tests}
+    radial_min = int(P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES))
+    for key, rmin in (("graph_ms", radial_min), ("per_edge_graph_ms", 0)):
+        P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, rmin)
+        try:
+            pl = P.BatchedPlan(*t32)
+            pl.autotune(reps=3)
+            e32[key] = round(_time(torch, stream, pl.launch, reps=10), 4)
+            if check and key == "graph_ms":
+                lab_b = pl.labels.cpu().numpy().view(np.uint32)
+                bad = 0
+                for k in sorted(rng.choice(B32.num_polygons, 16, replace=False)):
+                    p0, p1 = B32.pt_off[k], B32.pt_off[k + 1]
+                    v0, v1 = B32.vtx_off[k], B32.vtx_off[k + 1]
+                    want = o.voronoi(B32.V[v0:v1], B32.Q[p0:p1].astype(np.float64))
+                    w0 = B32.lbl_word_off[k]
+                    got = unpack_bits(lab_b[w0:w0 + (p1 - p0 + 31) // 32], p1 - p0)
+                    bad += int((got != want).sum())
+                e32["mismatches_16_polygons"] = bad
+            pl.close()
+        finally:
+            P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, radial_min)
+    e32["gtests_per_s"] = round(B32.num_tests / e32["graph_ms"] / 1e6, 2)
+    out["batch_n32"] = e32
+    del t32
     del vo, Vb, po, Qb, lo, B
     torch.cuda.empty_cache()
     print("[bench] uneven batch done", file=sys.stderr, flush=True)

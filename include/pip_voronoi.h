@@ -148,9 +148,11 @@ typedef struct pip_index_s *pip_index;
  *     outside.  Only the points in between take the per-edge screen (and, in
  *     its band, the binary64 recheck), so labels are unchanged.  Used for
  *     polygons with at least this many edges (before the matrix-core path),
- *     and likewise by pip_voronoi_raster (with its own band, and the per-edge
+ *     likewise by pip_voronoi_raster (with its own band, and the per-edge
  *     screen for every 512-pixel segment that holds a pixel between the
- *     radii); 0 disables it.  Default 20 (measured: the per-edge screen is faster for
+ *     radii) and by pip_voronoi_batched and batched plans for every polygon
+ *     of the batch that has this many edges (a plan or workspace takes the
+ *     setting when it is created or launched); 0 disables it.  Default 20 (measured: the per-edge screen is faster for
  *     fewer edges, where more points fall between the radii).  Not from the
  *     paper: a screen in front of its test, from the nearest-generator
  *     reading of Section 4. */

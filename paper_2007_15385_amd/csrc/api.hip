@@ -415,7 +415,7 @@ pip_status check_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_off, const d
 pipdev::BatchedDev make_dev(int32_t P, const int64_t* vtx_off, const double* V,
                             int64_t total_vertices, const int64_t* pt_off, const float* Q,
                             int64_t total_points, const int64_t* lbl_word_off, uint32_t* labels,
-                            int32_t* status, void* ws) {
+                            int32_t* status, void* ws, int radial_min) {
     pipdev::BatchedLayout L;
     pipdev::batched_workspace_layout(P, total_vertices, total_points, &L);
     char* b = static_cast<char*>(ws);
@@ -438,6 +438,8 @@ pipdev::BatchedDev make_dev(int32_t P, const int64_t* vtx_off, const double* V,
     D.desc = b + L.desc;
     D.misc = reinterpret_cast<int64_t*>(b + L.misc);
     D.max_chunks = L.max_chunks;
+    D.radial = reinterpret_cast<float*>(b + L.radial);
+    D.radial_min = radial_min;
     return D;
 }
 
@@ -496,7 +498,8 @@ pip_status pip_voronoi_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_off, c
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     const pipdev::BatchedDev D = make_dev(P, vtx_off, V, total_vertices, pt_off, Q, total_points,
-                                          lbl_word_off, labels, status, workspace);
+                                          lbl_word_off, labels, status, workspace,
+                                          ctx->radial_min_edges);
     return launch_batched_cfg(ctx, D, c, stream);
 }
 
@@ -597,7 +600,7 @@ pip_status pip_plan_create_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_of
         return hip_fail(e, "hipStreamCreateWithFlags");
     }
     p->D = make_dev(P, vtx_off, V, total_vertices, pt_off, Q, total_points, lbl_word_off, labels,
-                    status, p->ws);
+                    status, p->ws, ctx->radial_min_edges);
     resolve_config(ctx, nullptr, &p->cfg);
     *out = p;
     return PIP_OK;

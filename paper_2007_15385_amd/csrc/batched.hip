@@ -19,6 +19,7 @@
 // static polygons (Section 7: generators stored beside the vertices).
 #include "device.hpp"
 #include "kernels.hpp"
+#include "radial.hpp"
 #include "stream32.hpp"
 
 using namespace pipdev;
@@ -37,6 +38,7 @@ constexpr int kLoadNT = 2;  // cache-policy bit of a non-temporal (streaming) lo
 
 __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
     __shared__ PolyLds S[kWavesPerBlock];
+    __shared__ RadialTab RT[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int64_t k = (int64_t)blockIdx.x * kWavesPerBlock + wv;
@@ -62,6 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
             H->status = bad;
             H->ox = H->oy = 0.f;
             H->KQ = H->KA = H->KB = H->KC = __builtin_huge_valf();
+            H->radial = 0;
             D.chunk_cnt[k] = chunks;
             if (D.status) D.status[k] = bad;
         }
@@ -79,7 +82,24 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
     if (lane < n4) C[lane] = L.coef[lane];
     double2* G = D.gen + gen_base(D.vtx_off, k);
     for (int i = lane; i <= n; i += kWave) G[i] = L.gen[i];
+    // radial pre-screen thresholds (radial.hpp), for polygons large enough
+    int radial = 0;
+    if (D.radial_min > 0 && n >= D.radial_min) {
+        RadialTab& T = RT[wv];
+        prepare_radial(L, lane, T);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float* row = D.radial + k * kRadialRow;
+        if (lane < 8) {
+            row[2 * lane] = T.t[lane].x;
+            row[2 * lane + 1] = T.t[lane].y;
+        }
+        if (lane == 0) row[16] = T.tfar;
+        radial = T.tfar > 0.0f ? 1 : 0;  // a usable table has a positive far limit
+    }
     if (lane == 0) {
+        H->radial = radial;
         H->ox = L.ox;
         H->oy = L.oy;
         H->KQ = L.KQ;
@@ -218,8 +238,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     const float4* __restrict__ coef, const double2* __restrict__ gen,
     const int64_t* __restrict__ vtx_off, const int64_t* __restrict__ pt_off,
     const int64_t* __restrict__ lbl_word_off, const float2* __restrict__ Q,
-    uint32_t* __restrict__ labels, const int64_t* __restrict__ misc, int G) {
+    uint32_t* __restrict__ labels, const int64_t* __restrict__ misc,
+    const float* __restrict__ radial, int G) {
     __shared__ float4 coefs[kWavesPerBlock][2][kMaxEdges];  // current / next polygon
+    __shared__ __align__(16) float rtab[kWavesPerBlock][2][kRadialRow];  // their radial thresholds
+    __shared__ float2 cpt[kWavesPerBlock][kWave];             // compacted annulus points
+    __shared__ int32_t cres[kWavesPerBlock][kWave];           // and their decisions
     __shared__ QueueB queue[kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -239,10 +263,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     load_chunk_b(Q, d, lane, pa);
     int cb = 0;  // LDS table of the current polygon; rows past n4 are never read
     coefs[wv][1][lane] = coef[coef_base(vtx_off, d.k) + lane];
+    if (lane < kRadialRow) rtab[wv][1][lane] = radial[(int64_t)d.k * kRadialRow + lane];
 
     int cur_k = -1;
     float ox = 0.f, oy = 0.f, KQ = 0.f, KA = 0.f, KB = 0.f, KC = 0.f;
     int n4 = 0;
+    int use_radial = 0;
     int64_t ptk = 0, wk = 0;
     int qcount = 0;
     QueueB& q = queue[wv];
@@ -252,7 +278,80 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         const int cnt = __builtin_amdgcn_readfirstlane(cd.count);
         const bool full = cnt >= kChunk32;
         uint64_t inm[kP32], unc[kP32];
-        if (n4 > 0) {
+        if (use_radial) {
+            // Radial pre-screen (radial.hpp): most points are decided from r2
+            // against their octant's radii; the rest are compacted one per lane
+            // and screened against every edge, 64 at a time.
+            const float* T = rtab[wv][cb];
+            const float tfar = T[16];
+            uint64_t amb[kP32];
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const float X = p[j].x - ox, Y = p[j].y - oy;
+                const float r2 = fmaf(X, X, Y * Y);
+                const uint32_t o = ((__float_as_uint(X) >> 31) << 2) | ((__float_as_uint(Y) >> 31) << 1) |
+                                   (fabsf(Y) > fabsf(X) ? 1u : 0u);
+                const float2 t = *reinterpret_cast<const float2*>(T + 2 * o);
+                inm[j] = __ballot(r2 < t.x);
+                amb[j] = ~(inm[j] | __ballot((r2 > t.y) & (r2 < tfar)));
+                unc[j] = 0;
+            }
+            if (!full) {
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const uint64_t vm = __ballot(lane + kWave * j < cnt);
+                    inm[j] &= vm;
+                    amb[j] &= vm;
+                }
+            }
+            int na = 0;
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) na += __popcll(amb[j]);
+            const uint64_t lt = lanemask_lt();
+            for (int base = 0; base < na; base += kWave) {
+                int run = 0;  // rank of a lane's point among the chunk's annulus points
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const int rank = run + __popcll(amb[j] & lt) - base;
+                    if (((amb[j] >> lane) & 1ull) && rank >= 0 && rank < kWave) cpt[wv][rank] = p[j];
+                    run += __popcll(amb[j]);
+                }
+                __builtin_amdgcn_wave_barrier();
+                const int cntp = min(na - base, kWave);
+                int res = 0;  // 1 inside, 2 inside the band
+                if (lane < cntp) {
+                    const float2 qq = cpt[wv][lane];
+                    const float X = qq.x - ox, Y = qq.y - oy;
+                    const float4* cf = coefs[wv][cb];
+                    float M = -__builtin_huge_valf();
+                    for (int e = 0; e < n4; e += 4) {
+                        const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
+                        const float m0 = fmaf(c0.x, X, fmaf(c0.y, Y, c0.z));
+                        const float m1 = fmaf(c1.x, X, fmaf(c1.y, Y, c1.z));
+                        const float m2 = fmaf(c2.x, X, fmaf(c2.y, Y, c2.z));
+                        const float m3 = fmaf(c3.x, X, fmaf(c3.y, Y, c3.z));
+                        M = fmaxf(fmaxf(M, m0), m1);
+                        M = fmaxf(fmaxf(M, m2), m3);
+                    }
+                    const float r2 = fmaf(X, X, Y * Y);
+                    const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X), fmaf(KB, fabsf(Y), KC)));
+                    res = M < -E ? 1 : (M > E ? 0 : 2);
+                }
+                cres[wv][lane] = res;
+                __builtin_amdgcn_wave_barrier();
+                run = 0;
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const int rank = run + __popcll(amb[j] & lt) - base;
+                    const bool mine = ((amb[j] >> lane) & 1ull) && rank >= 0 && rank < kWave;
+                    const int r = mine ? cres[wv][rank] : 0;
+                    inm[j] |= __ballot(r == 1);
+                    unc[j] |= __ballot(r == 2);
+                    run += __popcll(amb[j]);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        } else if (n4 > 0) {
             float X[kP32], Y[kP32], Mx[kP32];
             {  // edges 0-3 (n4 >= 4) start the max
                 const float4* cf = coefs[wv][cb];
@@ -343,6 +442,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         KB = H.KB;
         KC = H.KC;
         n4 = __builtin_amdgcn_readfirstlane(H.n4);
+        use_radial = __builtin_amdgcn_readfirstlane(H.radial);
         ptk = pt_off[k];
         wk = lbl_word_off[k];
         cb ^= 1;
@@ -390,9 +490,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         {  // a new polygon's rows go to the spare LDS table (load issued first)
             const bool newpoly = d2.k != d.k;
             float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
+            float rn = 0.f;
             if (newpoly) cn = coef[coef_base(vtx_off, d2.k) + lane];
+            if (newpoly && lane < kRadialRow) rn = radial[(int64_t)d2.k * kRadialRow + lane];
             load_chunk_b(Q, d2, lane, pb);
             if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
+            if (newpoly && lane < kRadialRow) rtab[wv][cb ^ 1][lane] = rn;
         }
         int64_t g3 = more ? next_chunk(g2, pos2) : g2;
         bool more3 = more && g3 < nchunks;
@@ -408,9 +511,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         {
             const bool newpoly = d2.k != d.k;
             float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
+            float rn = 0.f;
             if (newpoly) cn = coef[coef_base(vtx_off, d2.k) + lane];
+            if (newpoly && lane < kRadialRow) rn = radial[(int64_t)d2.k * kRadialRow + lane];
             load_chunk_b(Q, d2, lane, pa);
             if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
+            if (newpoly && lane < kRadialRow) rtab[wv][cb ^ 1][lane] = rn;
         }
         g3 = more ? next_chunk(g2, pos2) : g2;
         more3 = more && g3 < nchunks;
@@ -447,6 +553,8 @@ size_t batched_workspace_layout(int64_t P, int64_t total_vertices, int64_t total
     off = up(off + sizeof(ChunkDesc) * (size_t)L->max_chunks);
     L->misc = off;
     off = up(off + 64);
+    L->radial = off;
+    off = up(off + sizeof(float) * kRadialRow * (size_t)P);
     return off;
 }
 
@@ -462,7 +570,7 @@ hipError_t launch_batched(const BatchedDev& D, int G, int blocks, hipStream_t st
     hipLaunchKernelGGL(k_batched_voronoi, dim3(blocks), dim3(kBlock), 0, stream,
                        reinterpret_cast<const ChunkDesc*>(D.desc), D.hdr, D.coef, D.gen, D.vtx_off,
                        D.pt_off, D.lbl_word_off, reinterpret_cast<const float2*>(D.Q), D.labels,
-                       D.misc, G);
+                       D.misc, D.radial, G);
     return hipGetLastError();
 }
 

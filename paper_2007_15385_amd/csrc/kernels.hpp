@@ -38,7 +38,8 @@ struct alignas(16) PolyHdr {
     int status;            // pip_status of this polygon
     float cx, cy, rad;     // disk (float32 centre, radius rounded up) containing the polygon
     int npair;             // > 0: coefficient rows are npair antipodal edge pairs (all pairs)
-    int pad[3];
+    int radial;            // 1: the batched screen takes the radial pre-screen (table usable)
+    int pad[2];
 };
 
 // Device view of a batched request plus its workspace.
@@ -61,10 +62,14 @@ struct BatchedDev {
     void* desc;
     int64_t* misc;
     int64_t max_chunks;
+    float* radial;   // [P][kRadialRow]: (T_in, T_out) of octants 0..7, then T_far
+    int radial_min;  // polygons with at least this many edges use it; 0: none
 };
 
+constexpr int kRadialRow = 20;  // floats per polygon in the batched radial table
+
 struct BatchedLayout {
-    size_t hdr, coef, gen, chunk_cnt, chunk_off, desc, misc;
+    size_t hdr, coef, gen, chunk_cnt, chunk_off, desc, misc, radial;
     int64_t max_chunks;
 };
 

@@ -27,6 +27,16 @@ def P():
     return P
 
 
+@pytest.fixture(autouse=True, params=["radial", "per_edge"])
+def screen(request, P):
+    """Every test runs with the radial pre-screen forced for every polygon
+    size and with it off (plans and workspaces take the setting at creation)."""
+    old = P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES)
+    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 3 if request.param == "radial" else 0)
+    yield request.param
+    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, old)
+
+
 def to_dev(B):
     d = "cuda"
     return (torch.from_numpy(B.vtx_off).to(d), torch.from_numpy(B.V).to(d),
