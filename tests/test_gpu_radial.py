@@ -271,3 +271,53 @@ def test_option_range(P):
     with pytest.raises(P.PipError):
         P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 66)
     assert P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES) == 3
+
+
+def random_polygons(count, seed):
+    """Convex polygons with random vertex counts, aspect ratios up to 300:1,
+    rotations and centres up to 1e4 from the origin."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        n = int(rng.integers(3, 65))
+        V = W.circle_polygon(n, 1.0, (0.0, 0.0), rng)
+        V[:, 0] *= float(np.exp(rng.uniform(0.0, np.log(300.0))))
+        a = rng.uniform(0.0, 2.0 * math.pi)
+        R = np.array([[math.cos(a), -math.sin(a)], [math.sin(a), math.cos(a)]])
+        V = V @ R.T * float(np.exp(rng.uniform(np.log(1e-2), np.log(1e2))))
+        V += rng.uniform(-1e4, 1e4, 2) * (rng.random() < 0.5)
+        out.append(V)
+    return out
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_bounds_sound_random_polygons(P, oracle, seed):
+    """60 random convex polygons: every point just under an octant's T_in is
+    inside and every point just beyond its T_out (short of T_far) outside."""
+    checked = 0
+    for V in random_polygons(20, seed):
+        tin, tout, tfar = bounds(P, V)
+        if (tin == 0).all():
+            continue  # screen off for this polygon (allowed; labels still exact)
+        p0 = oracle.centroid(V)[0]
+        ox, oy = np.float32(p0[0]), np.float32(p0[1])
+        pin, pout = [], []
+        for o in range(8):
+            for f in (1.0, 1 - 1e-6, 1 - 1e-3):
+                Q = ring_points(ox, oy, math.sqrt(tin[o]) * f, o, k=1001)
+                X, Y = local(Q, ox, oy)
+                r2 = X.astype(np.float64) ** 2 + Y.astype(np.float64) ** 2
+                pin.append(Q[(octant(X, Y) == o) & (r2 * (1 + 2.0 ** -22) < tin[o])])
+            if np.isfinite(tout[o]):
+                for f in (1.0, 1 + 1e-6, 1 + 1e-3, 2.0):
+                    Q = ring_points(ox, oy, math.sqrt(tout[o]) * f, o, k=1001)
+                    X, Y = local(Q, ox, oy)
+                    r2 = X.astype(np.float64) ** 2 + Y.astype(np.float64) ** 2
+                    pout.append(Q[(octant(X, Y) == o) & (r2 > tout[o] * (1 + 2.0 ** -22)) &
+                                  (r2 * (1 + 2.0 ** -22) < tfar)])
+        Qi, Qo = np.concatenate(pin), np.concatenate(pout)
+        assert oracle.voronoi(V, Qi.astype(np.float64)).all(), "a point under T_in is outside"
+        assert not oracle.voronoi(V, Qo.astype(np.float64)).any(), "a point beyond T_out is inside"
+        checked += 1
+    say(f"[stat] seed {seed}: {checked} of 20 polygons with the screen on")
+    assert checked >= 8
