@@ -589,6 +589,9 @@ def main() -> int:
         r["screen"] = screen_of(r["n"])
         if r["screen"] == "radial":
             r["radial_annulus_frac"] = annulus_fraction(P, torch, *host_q[r["n"]])
+            # only the annulus points meet the 4n flop per-edge screen
+            r["per_edge_equivalent_tflops"] = r.pop("fp32_tflops")
+            r["fp32_frac"] = None
     dom = max(kernels, key=lambda r: r["ms"])
     # binding roofline of the dominant launch: bytes vs flops at peak
     t_hbm = BYTES_PER_TEST * m / (HBM_PEAK_GBS * 1e9)

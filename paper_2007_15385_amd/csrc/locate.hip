@@ -249,6 +249,28 @@ __global__ void k_index_cells(int64_t P, const LocRec* __restrict__ rec,
         }
 }
 
+// Each list (the cells', then the global list) in ascending polygon index,
+// so that a point's first containing candidate is its answer and its later
+// box hits skip their records.  One thread per list, insertion sort; lists
+// longer than kSortMax keep their order (the answer does not depend on it).
+constexpr int kSortMax = 64;
+__global__ void k_index_sort(int64_t nlists, const int32_t* __restrict__ cell_off,
+                             LocEntry* __restrict__ list) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nlists) return;
+    const int b = cell_off[i], e = cell_off[i + 1];
+    if (e - b > kSortMax) return;
+    for (int a = b + 1; a < e; ++a) {
+        const LocEntry x = list[a];
+        int j = a;
+        while (j > b && list[j - 1].k > x.k) {
+            list[j] = list[j - 1];
+            --j;
+        }
+        list[j] = x;
+    }
+}
+
 // Exclusive scan of count[0..C) into off[0..C] in one block.
 __global__ __launch_bounds__(1024) void k_index_scan(int64_t C, const int32_t* __restrict__ count,
                                                    int32_t* __restrict__ off) {
@@ -277,6 +299,8 @@ __global__ __launch_bounds__(1024) void k_index_scan(int64_t C, const int32_t* _
     if (e == C && b < e) off[C] = (int32_t)acc;
     if (C == 0 && t == 0) off[0] = 0;
 }
+
+constexpr int kScanBatch = 8;  // cell entries per round trip (a cell holds ~5 on average)
 
 // Smallest index of a polygon containing p, or -1: the candidates of p's
 // cell (their boxes first: only box hits read a record), then the global
@@ -311,25 +335,38 @@ __device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
         if (!(fabsf(M) > E)) in = voronoi64((double)p.x, (double)p.y, gen + __float_as_int(h1.w), n);
         return in;
     };
-    // entries [beg, end): four at a time, their boxes and indices loaded
-    // together (one memory round trip), then the records of the box hits
+    // entries [beg, end): kScanBatch at a time, their boxes and indices
+    // loaded together (one memory round trip); the box hits become a bit mask
+    // and each lane walks its own hits, so the lanes' record loads overlap.
+    // Lists are in ascending polygon index (up to kSortMax entries), so hits
+    // after a lane's first containing polygon skip their records.
     auto scan = [&](int beg, int end) {
-        for (int t = beg; t < end; t += 4) {
-            float4 box[4];
-            int4 kq[4];  // k, qoff, n | n4 << 16
+        for (int t = beg; t < end; t += kScanBatch) {
+            float4 box[kScanBatch];
+            int4 kq[kScanBatch];  // k, qoff, n | n4 << 16
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kScanBatch; ++u) {
                 const int tu = t + u < end ? t + u : t;
                 box[u] = *reinterpret_cast<const float4*>(&list[tu]);
                 kq[u] = *reinterpret_cast<const int4*>(&list[tu].k);
             }
+            uint32_t hits = 0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (t + u >= end) break;
+            for (int u = 0; u < kScanBatch; ++u) {
                 // a NaN box (non-finite vertices) never rejects
-                if (p.x < box[u].x || p.y < box[u].y || p.x > box[u].z || p.y > box[u].w) continue;
-                if (id >= 0 && kq[u].x > id) continue;  // cannot lower the answer
-                if (inside(kq[u].y, kq[u].z)) id = kq[u].x;
+                const bool miss =
+                    p.x < box[u].x || p.y < box[u].y || p.x > box[u].z || p.y > box[u].w;
+                if (t + u < end && !miss) hits |= 1u << u;
+            }
+            while (hits) {
+                const int u = __builtin_ctz(hits);
+                hits &= hits - 1;
+                int4 e = kq[0];
+#pragma unroll
+                for (int v = 1; v < kScanBatch; ++v)
+                    if (u == v) e = kq[v];
+                if (id >= 0 && e.x > id) continue;  // cannot lower the answer
+                if (inside(e.y, e.z)) id = e.x;
             }
         }
     };
@@ -451,22 +488,22 @@ __global__ __launch_bounds__(kBlock) void k_bin_points(const float2* __restrict_
 // in LDS by the point's cell within its super-cell (sf * sf keys, one more
 // for points outside the grid's box), so consecutive lanes share a cell and
 // its candidates' loads are broadcasts; ids are written back by index.
-constexpr int kLocPer = 8;
-constexpr int kLocTile = kBlock * kLocPer;  // 2048 points
-constexpr int kMaxKeys = 1025;              // sf <= 32
-constexpr int kScanPer = (kMaxKeys + kBlock - 1) / kBlock;
+// 512-thread blocks: the 37 KB of LDS per tile then serve 8 waves, and at
+// 4 waves per SIMD (<= 128 VGPRs) two blocks share a CU.
+constexpr int kLocBlock = 512;
+constexpr int kLocPer = 4;
+constexpr int kLocTile = kLocBlock * kLocPer;  // 2048 points
+constexpr int kMaxKeys = 1025;                 // sf <= 32
+constexpr int kScanPer = (kMaxKeys + kLocBlock - 1) / kLocBlock;
 
-__global__ __launch_bounds__(kBlock) void k_locate_binned(const float4* __restrict__ qrec,
-                                                        const double2* __restrict__ gen,
-                                                        const LocGrid* __restrict__ grid,
-                                                        const int32_t* __restrict__ cell_off,
-                                                        const LocEntry* __restrict__ list,
-                                                        const BinnedPt* __restrict__ binned,
-                                                        int64_t m, int sf,
-                                                        int32_t* __restrict__ ids) {
+__global__ __launch_bounds__(kLocBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_locate_binned(
+    const float4* __restrict__ qrec, const double2* __restrict__ gen,
+    const LocGrid* __restrict__ grid, const int32_t* __restrict__ cell_off,
+    const LocEntry* __restrict__ list, const BinnedPt* __restrict__ binned, int64_t m, int sf,
+    int32_t* __restrict__ ids) {
     __shared__ BinnedPt sorted_s[kLocTile];
     __shared__ int32_t key_s[kMaxKeys];
-    __shared__ int32_t part_s[kBlock];
+    __shared__ int32_t part_s[kLocBlock / kWave];
     const int tid = threadIdx.x;
     const LocGrid G = *grid;
     const int64_t C = (int64_t)G.gx * G.gy;
@@ -477,13 +514,13 @@ __global__ __launch_bounds__(kBlock) void k_locate_binned(const float4* __restri
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t i0 = tile * kLocTile;
         const int cnt = (int)(m - i0 < kLocTile ? m - i0 : kLocTile);
-        for (int k = tid; k < nkeys; k += kBlock) key_s[k] = 0;
+        for (int k = tid; k < nkeys; k += kLocBlock) key_s[k] = 0;
         __syncthreads();
         BinnedPt e[kLocPer];
         int key[kLocPer], slot[kLocPer];
 #pragma unroll
         for (int j = 0; j < kLocPer; ++j) {
-            const int q = j * kBlock + tid;
+            const int q = j * kLocBlock + tid;
             key[j] = -1;
             if (q < cnt) {
                 e[j] = binned[i0 + q];
@@ -502,18 +539,19 @@ __global__ __launch_bounds__(kBlock) void k_locate_binned(const float4* __restri
             const int k = tid * kScanPer + u;
             if (k < nkeys) run += key_s[k];
         }
-        part_s[tid] = run;
-        __syncthreads();
-        if (tid == 0) {
-            int acc = 0;
-            for (int t = 0; t < kBlock; ++t) {
-                const int v = part_s[t];
-                part_s[t] = acc;
-                acc += v;
-            }
+        // exclusive over the block: a scan within the wave, then the totals
+        // of the waves before this one
+        const int lane = tid & (kWave - 1);
+        int incl = run;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int t = __shfl_up(incl, d);
+            if (lane >= d) incl += t;
         }
+        if (lane == kWave - 1) part_s[tid / kWave] = incl;
         __syncthreads();
-        int acc = part_s[tid];
+        int acc = incl - run;
+        for (int w = 0; w < tid / kWave; ++w) acc += part_s[w];
         for (int u = 0; u < kScanPer; ++u) {
             const int k = tid * kScanPer + u;
             if (k < nkeys) {
@@ -527,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_locate_binned(const float4* __restri
         for (int j = 0; j < kLocPer; ++j)
             if (key[j] >= 0) sorted_s[key_s[key[j]] + slot[j]] = e[j];
         __syncthreads();
-        for (int q = tid; q < cnt; q += kBlock) {
+        for (int q = tid; q < cnt; q += kLocBlock) {
             const BinnedPt b = sorted_s[q];
             const int id =
                 locate_point(make_float2(b.x, b.y), G, cell_off, list, qrec, gen, gbeg, gend);
@@ -576,6 +614,8 @@ hipError_t index_fill(int64_t P, const LocRec* rec, const LocGrid* grid, int64_t
     if (P > 0)
         hipLaunchKernelGGL(k_index_cells<true>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0,
                            stream, P, rec, grid, cnt, cell_off, list, nullptr);
+    hipLaunchKernelGGL(k_index_sort, dim3((unsigned)((cells + 1 + 255) / 256)), dim3(256), 0,
+                       stream, cells + 1, cell_off, list);
     return hipGetLastError();
 }
 
@@ -632,7 +672,7 @@ hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const Lo
                        Q2, m, grid, sf, sgx, nbins, nullptr, boff, fill, pts);
     const int64_t want = (m + kLocTile - 1) / kLocTile;
     const int gl = (int)(want < max_blocks ? want : max_blocks);
-    hipLaunchKernelGGL(k_locate_binned, dim3(gl), dim3(kBlock), 0, stream, qrec, gen, grid, cell_off,
+    hipLaunchKernelGGL(k_locate_binned, dim3(gl), dim3(kLocBlock), 0, stream, qrec, gen, grid, cell_off,
                        list, pts, m, sf, ids);
     return hipGetLastError();
 }

@@ -130,6 +130,26 @@ def test_locate_overlapping_and_unusual(P, oracle):
     assert s[-5:].tolist() == [3, 2, 1, 1, 2]  # non-convex, zero area, non-finite, 2 vertices, zero edge
 
 
+def test_locate_long_cell_lists(P, oracle):
+    """Concentric squares: 40 about one centre (cell lists of up to 40
+    entries, kept in ascending index, several 8-entry batches per cell) and
+    100 about another (lists longer than the 64 entries that are sorted, so
+    they keep the fill order); listed smallest first (the answer is the
+    smallest square containing the point) and then shuffled."""
+    rng = np.random.default_rng(23)
+    sq = np.array([[-1.0, -1], [1, -1], [1, 1], [-1, 1]])
+    polys = []
+    for cx, cnt in ((-5.0, 40), (5.0, 100)):
+        polys += [sq * s + [cx, 0.25] for s in np.linspace(0.1, 4.0, cnt)]
+    for name, perm in (("smallest first", np.arange(len(polys))),
+                       ("shuffled", rng.permutation(len(polys)))):
+        ps = [polys[i] for i in perm]
+        off = np.concatenate([[0], np.cumsum([len(p) for p in ps])])
+        V = np.concatenate(ps)
+        Q = np.concatenate([rng.uniform(-10, 10, (30_000, 2)), V])
+        check(P, oracle, off, V, Q, tag=f"long lists, {name}")
+
+
 @pytest.mark.parametrize("origin", [(1000.0, -500.0), (1.0e5, 1.0e5)])
 def test_locate_far_from_origin(P, oracle, origin):
     rng = np.random.default_rng(3)
