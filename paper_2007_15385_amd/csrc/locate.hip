@@ -344,11 +344,16 @@ __device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
         for (int t = beg; t < end; t += kScanBatch) {
             float4 box[kScanBatch];
             int4 kq[kScanBatch];  // k, qoff, n | n4 << 16
+            // entries past the list's end are not loaded: the kernel is bound by
+            // its memory requests more than by their latency
 #pragma unroll
             for (int u = 0; u < kScanBatch; ++u) {
-                const int tu = t + u < end ? t + u : t;
-                box[u] = *reinterpret_cast<const float4*>(&list[tu]);
-                kq[u] = *reinterpret_cast<const int4*>(&list[tu].k);
+                box[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+                kq[u] = make_int4(0, 0, 0, 0);
+                if (t + u < end) {
+                    box[u] = *reinterpret_cast<const float4*>(&list[t + u]);
+                    kq[u] = *reinterpret_cast<const int4*>(&list[t + u].k);
+                }
             }
             uint32_t hits = 0;
 #pragma unroll
