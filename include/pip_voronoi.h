@@ -285,7 +285,7 @@ pip_status pip_index_locate(pip_index index, const float *Q, int64_t m, int32_t 
  * pip_index_locate_workspace_bytes(index, m) bytes (0 for a NULL index or
  * negative m).  Allocates nothing; asynchronous on `stream`.  Errors:
  * PIP_EINVAL for bad arguments or a short workspace, PIP_EUNSUPPORTED for
- * m > 2^40. */
+ * m >= 2^31 (the copy is indexed with 32-bit offsets). */
 size_t pip_index_locate_workspace_bytes(pip_index index, int64_t m);
 pip_status pip_index_locate_binned(pip_index index, const float *Q, int64_t m, int32_t *ids,
                                    void *workspace, size_t ws_bytes, hipStream_t stream);

@@ -1220,7 +1220,8 @@ pip_status pip_index_locate_binned(pip_index x, const float* Q, int64_t m, int32
                                    void* workspace, size_t ws_bytes, hipStream_t stream) {
     if (!x) return fail(PIP_EINVAL, "index is NULL");
     if (m < 0) return fail(PIP_EINVAL, "m = %lld is negative", (long long)m);
-    if (m > (int64_t(1) << 40)) return fail(PIP_EUNSUPPORTED, "m = %lld is too large", (long long)m);
+    // the binned copy is indexed with int32 offsets
+    if (m >= (int64_t(1) << 31)) return fail(PIP_EUNSUPPORTED, "m = %lld is too large", (long long)m);
     if (m > 0 && (!Q || !aligned(Q, 8))) return fail(PIP_EINVAL, "Q is NULL or not 8-byte aligned");
     if (m > 0 && (!ids || !aligned(ids, 4))) return fail(PIP_EINVAL, "ids is NULL or misaligned");
     if (m == 0) return PIP_OK;

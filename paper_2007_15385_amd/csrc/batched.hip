@@ -227,12 +227,6 @@ __device__ __forceinline__ void load_chunk_b(const float2* __restrict__ Q, const
     }
 }
 
-__device__ __forceinline__ int64_t uniform64(int64_t v) {
-    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const int hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_batched_voronoi(
     const ChunkDesc* __restrict__ desc, const PolyHdr* __restrict__ hdr,
     const float4* __restrict__ coef, const double2* __restrict__ gen,

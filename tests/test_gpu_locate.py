@@ -169,6 +169,17 @@ def test_locate_empty_and_errors(P):
         locate_gpu(P, [0, 65], big, np.zeros((1, 2)))
     with pytest.raises(P.PipError):  # vtx_off[P] != number of vertices
         P.LocateIndex(torch.tensor([0, 3], dtype=torch.int64).cuda(), torch.from_numpy(V).cuda())
+    # the binned query indexes its copy of the points with 32-bit offsets: a
+    # count of 2^31 is refused before anything is read or launched
+    from paper_2007_15385_amd.api import _lib as _raw
+    idx = P.LocateIndex(torch.tensor([0, 4], dtype=torch.int64).cuda(), torch.from_numpy(V).cuda())
+    q = torch.zeros((1, 2), dtype=torch.float32, device="cuda")
+    ids = torch.empty(1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+    s = _raw().pip_index_locate_binned(idx.handle, q.data_ptr(), 1 << 31, ids.data_ptr(),
+                                       ws.data_ptr(), ws.numel(), None)
+    assert s == 6  # PIP_EUNSUPPORTED
+    idx.close()
 
 
 def test_locate_full_size(P, oracle):
