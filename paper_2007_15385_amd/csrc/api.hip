@@ -1232,7 +1232,7 @@ pip_status pip_index_locate_binned(pip_index x, const float* Q, int64_t m, int32
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_locate_binned(x->qrec, x->gen, x->grid, x->cell_off, x->list, x->sf,
                                                 x->sgx, x->nbins, Q, m, ids, workspace,
-                                                x->ctx->cu_count, x->blocks, stream);
+                                                x->ctx->cu_count, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }

@@ -127,7 +127,7 @@ size_t locate_binned_workspace(int nbins, int64_t m, size_t* o_cnt, size_t* o_of
 hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const LocGrid* grid,
                                 const int32_t* cell_off, const LocEntry* list, int sf, int sgx,
                                 int nbins, const float* Q, int64_t m, int32_t* ids, void* ws,
-                                int cus, int max_blocks, hipStream_t stream);
+                                int cus, hipStream_t stream);
 // Coverage raster: pixel (i, j) = (x0 + i dx, y0 + j dy), binary64.
 struct RasterGrid {
     double x0, y0, dx, dy;

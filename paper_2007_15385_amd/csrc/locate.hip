@@ -654,7 +654,7 @@ size_t locate_binned_workspace(int nbins, int64_t m, size_t* o_cnt, size_t* o_of
 hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const LocGrid* grid,
                                 const int32_t* cell_off, const LocEntry* list, int sf, int sgx,
                                 int nbins, const float* Q, int64_t m, int32_t* ids, void* ws,
-                                int cus, int max_blocks, hipStream_t stream) {
+                                int cus, hipStream_t stream) {
     if (m == 0) return hipSuccess;
     size_t o_cnt, o_off, o_fill, o_pts;
     locate_binned_workspace(nbins, m, &o_cnt, &o_off, &o_fill, &o_pts);
@@ -675,10 +675,11 @@ hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const Lo
     hipLaunchKernelGGL(k_index_scan, dim3(1), dim3(1024), 0, stream, (int64_t)(nbins + 1), cnt, boff);
     hipLaunchKernelGGL(k_bin_points<true>, dim3(bb), dim3(kBlock), 8 * (size_t)(nbins + 1), stream,
                        Q2, m, grid, sf, sgx, nbins, nullptr, boff, fill, pts);
-    const int64_t want = (m + kLocTile - 1) / kLocTile;
-    const int gl = (int)(want < max_blocks ? want : max_blocks);
-    hipLaunchKernelGGL(k_locate_binned, dim3(gl), dim3(kLocBlock), 0, stream, qrec, gen, grid, cell_off,
-                       list, pts, m, sf, ids);
+    // one block per tile (m < 2^31: fewer than 2^20 tiles): more blocks than
+    // fit on the chip at once even out the end of the launch
+    const int64_t tiles = (m + kLocTile - 1) / kLocTile;
+    hipLaunchKernelGGL(k_locate_binned, dim3((unsigned)tiles), dim3(kLocBlock), 0, stream, qrec, gen,
+                       grid, cell_off, list, pts, m, sf, ids);
     return hipGetLastError();
 }
 
