@@ -54,7 +54,6 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "oracle_centroid": (ctypes.c_int, [_D, _i64, _D, _D]),
         "oracle_generators": (ctypes.c_int, [_D, _i64, _D]),
         "oracle_voronoi": (ctypes.c_int, [_D, _i64, _D, _i64, _U8]),
-        "oracle_voronoi_with_generators": (None, [_D, _i64, _D, _i64, _U8]),
         "oracle_locate": (ctypes.c_int, [_I64, _i64, _D, _D, _i64, _I32]),
         "oracle_voronoi_raster": (ctypes.c_int, [_D, _i64, ctypes.c_double, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_double, _i64, _i64,
@@ -158,13 +157,6 @@ class Oracle:
         if rc != 0:
             raise MemoryError("oracle_locate")
         return ids
-
-    def voronoi_with_generators(self, P, Q) -> np.ndarray:
-        P = _f64(P).reshape(-1, 2)
-        Q = _f64(Q).reshape(-1, 2)
-        out = np.zeros(len(Q), dtype=np.uint8)
-        self.lib.oracle_voronoi_with_generators(_p(P), len(P) - 1, _p(Q), len(Q), _p(out, _U8))
-        return out.astype(bool)
 
     def voronoi_max_margin(self, V, Q) -> np.ndarray:
         V = _f64(V).reshape(-1, 2)

@@ -233,26 +233,6 @@ int oracle_locate(const int64_t *vtx_off, int64_t P, const double *V, const doub
 }
 
 /*
- * Same test with the generators given (P as produced above); used for
- * batched and all-pairs work where the generators are derived once.
- */
-void oracle_voronoi_with_generators(const double *P, int64_t n, const double *Q, int64_t m,
-                                    uint8_t *isin)
-{
-#pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < m; ++k) {
-        double px = Q[2 * k], py = Q[2 * k + 1];
-        double M0 = sqdist(px, py, P[0], P[1]);
-        int in = isfinite(px) && isfinite(py);
-        for (int64_t i = 0; i < n; ++i) {
-            double Mi = sqdist(px, py, P[2 * (i + 1)], P[2 * (i + 1) + 1]);
-            if (!(M0 <= Mi)) in = 0;
-        }
-        isin[k] = (uint8_t)in;
-    }
-}
-
-/*
  * Largest Voronoi margin per point: max_i (|p - p_0|^2 - |p - p_i|^2), the
  * quantity whose sign Algorithm 5 tests (Eq. 11 rearranged); <= 0 inside.
  * Each difference is formed from the two squared distances of Algorithm 5.

@@ -538,6 +538,32 @@ def pin_cost_hash(o):
     assert np.all(np.abs(gp) <= ap + 1e-12) and np.all(np.abs(gF) <= aF + 1e-12)
 
 
+def pin_cost_argmin(o):
+    """Hand-worked states of the unit square (``tests/golden/cost_argmin_square.json``):
+    the minimising edge of each inside point, the lowest index on exact
+    ties, -1 on the boundary and outside; the cost and the pose gradient,
+    which follows the tie rule (every value is exact in binary64)."""
+    g = golden("cost_argmin_square.json")
+    F = np.array(g["footprint"], dtype=float)
+    pose = np.array(g["pose"], dtype=float)
+    Q = np.array(g["points"], dtype=float)
+    st = o.cost_state(F, pose, Q)
+    assert st.tolist() == g["state"], st
+    assert o.cost(F, pose[None], Q)[0] == g["cost"]
+    gp, _ = o.cost_grad(F, pose[None], Q)
+    assert gp[0].tolist() == g["grad_pose"], gp
+    # the hash follows the state: a tie point nudged towards its second edge
+    # changes the hash, and nudging it towards its own edge does not
+    _, h0 = o.cost_with_hash(F, pose[None], Q)
+    Q1 = Q.copy()
+    Q1[4] = [0.25 + 2.0 ** -20, 0.25]   # now edge 1 is nearer
+    _, h1 = o.cost_with_hash(F, pose[None], Q1)
+    Q2 = Q.copy()
+    Q2[4] = [0.25 - 2.0 ** -20, 0.25]   # edge 0 stays the minimum
+    _, h2 = o.cost_with_hash(F, pose[None], Q2)
+    assert h1[0] != h0[0] and h2[0] == h0[0]
+
+
 ALL_PINS = [
     pin_square_and_triangle,
     pin_raster_exact,
@@ -562,4 +588,5 @@ ALL_PINS = [
     pin_cost_gradient_fd,
     pin_cost_gradient_cw,
     pin_cost_hash,
+    pin_cost_argmin,
 ]

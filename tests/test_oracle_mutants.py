@@ -57,6 +57,12 @@ MUTANTS = [
      "double cbx = sigma * (ry / L + f * ex / L3);"),
     ("grad_a_index", "double cay = sigma * ((rx - ex) / L + f * ey / L3);",
      "double cay = sigma * ((rx - ey) / L + f * ey / L3);"),
+    ("cost_argmin_tie_last", "\n            if (i == 0 || d < best) {",
+     "\n            if (i == 0 || d <= best) {"),
+    ("grad_argmin_tie_last", "\n                if (i == 0 || d < best) {",
+     "\n                if (i == 0 || d <= best) {"),
+    ("cost_state_off_by_one", "if (state) state[j] = (int32_t)arg;",
+     "if (state) state[j] = (int32_t)arg + 1;"),
 ]
 
 
