@@ -1204,7 +1204,7 @@ pip_status pip_index_locate(pip_index x, const float* Q, int64_t m, int32_t* ids
     if (m == 0) return PIP_OK;
     DeviceGuard g(x->ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    hipError_t e = pipdev::launch_locate(x->qrec, x->gen, x->grid, x->cell_off, x->list, Q, m, ids,
+    hipError_t e = pipdev::launch_locate(x->rec, x->P, x->qrec, x->gen, x->grid, x->cell_off, x->list, Q, m, ids,
                                          x->blocks, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
@@ -1230,7 +1230,7 @@ pip_status pip_index_locate_binned(pip_index x, const float* Q, int64_t m, int32
         return fail(PIP_EINVAL, "workspace must be 256-byte aligned with >= %zu bytes", need);
     DeviceGuard g(x->ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
-    hipError_t e = pipdev::launch_locate_binned(x->qrec, x->gen, x->grid, x->cell_off, x->list, x->sf,
+    hipError_t e = pipdev::launch_locate_binned(x->rec, x->P, x->qrec, x->gen, x->grid, x->cell_off, x->list, x->sf,
                                                 x->sgx, x->nbins, Q, m, ids, workspace,
                                                 x->ctx->cu_count, stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");

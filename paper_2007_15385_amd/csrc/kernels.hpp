@@ -97,6 +97,8 @@ struct alignas(16) LocRec {
     float bx0, by0, bx1, by1;  // widened, outward-rounded box
     int status;            // pip_status of the polygon
     int usable;            // 0: contains no point; 1: in the grid cells; 2: global list
+    float rfar;            // binary64 calls no point inside beyond the box within this
+                           // distance of (ox, oy) (rounded down)
 };
 // Cell-list entry: the polygon's box, index, query-record offset (float4
 // units) and edge counts: record = {ox, oy, KQ, KA}, {KB, KC, n | n4 << 16,
@@ -110,21 +112,24 @@ struct LocGrid {
     float inv_w, inv_h;    // cells per unit length
     int gx, gy;            // grid shape (gx * gy <= requested cells)
     int any;               // some polygon is cell-listed
+    float fx0, fy0, fx1, fy1;  // near region: beyond it a point tests every polygon
 };
 hipError_t index_prepare(int64_t P, const int64_t* vtx_off, const double* V, LocRec* rec,
                          float4* qrec, double2* gen, int32_t* status, int32_t* flags,
                          hipStream_t stream);
-hipError_t index_grid(int64_t P, const LocRec* rec, int64_t cells, LocGrid* grid, int32_t* cnt,
+hipError_t index_grid(int64_t P, LocRec* rec, int64_t cells, LocGrid* grid, int32_t* cnt,
                       unsigned long long* total, hipStream_t stream);
 hipError_t index_fill(int64_t P, const LocRec* rec, const LocGrid* grid, int64_t cells,
                       int32_t* cnt, int32_t* cell_off, LocEntry* list, hipStream_t stream);
-hipError_t launch_locate(const float4* qrec, const double2* gen, const LocGrid* grid,
-                         const int32_t* cell_off, const LocEntry* list, const float* Q, int64_t m,
-                         int32_t* ids, int max_blocks, hipStream_t stream);
+hipError_t launch_locate(const LocRec* rec, int64_t P, const float4* qrec, const double2* gen,
+                         const LocGrid* grid, const int32_t* cell_off, const LocEntry* list,
+                         const float* Q, int64_t m, int32_t* ids, int max_blocks,
+                         hipStream_t stream);
 hipError_t locate_max_blocks_per_cu(int* out);
 size_t locate_binned_workspace(int nbins, int64_t m, size_t* o_cnt, size_t* o_off, size_t* o_fill,
                                size_t* o_pts);
-hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const LocGrid* grid,
+hipError_t launch_locate_binned(const LocRec* rec, int64_t P, const float4* qrec,
+                                const double2* gen, const LocGrid* grid,
                                 const int32_t* cell_off, const LocEntry* list, int sf, int sgx,
                                 int nbins, const float* Q, int64_t m, int32_t* ids, void* ws,
                                 int cus, hipStream_t stream);

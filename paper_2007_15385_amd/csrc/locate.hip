@@ -10,26 +10,50 @@
 //
 // Exactness of the index.  Binary64 rounding can put a point just outside a
 // polygon inside it, so a polygon's box is its vertex bounds widened by a
-// bound on that distance: the binary64 evaluation of Algorithm 5 differs
-// from the exact margin m_i = 2 |h_i| s_i (s_i the signed distance past edge
-// line i, h_i = p_i - p_0) by at most E64 = 24.01 v |p - o|^2 +
-// 4.0001 v (6 d2 + 2 H2) (the band's binary64 part), so every point it calls
-// inside lies in the polygon with each edge moved out by
-// t = E64 / (2 min |h_i|); such an offset moves a vertex of interior angle
-// theta by t / sin(theta / 2).  The box is widened by twice
-// t / min sin(theta_i / 2), with |p - o| bounded by twice the largest vertex
-// distance, and rounded outwards to float32; a polygon without a finite,
-// small widening (degenerate or non-convex input, or non-finite vertices)
-// goes to a global list that every query tests as well (binary64 decides;
-// normally empty).  A box corner and a query point are mapped to
-// cells by the same float32 function, monotone in the coordinate, so a point
-// inside a box is in a cell of the box's range.  The answer is the minimum
-// containing index, so the order of a cell's list does not matter.
+// bound on that distance.  Two errors add up.  (1) The evaluation of
+// Algorithm 5 with the stored generators differs from their exact margin
+// by at most E64 = 24.01 v |p - o|^2 + 4.0001 v (6 d2 + 2 H2) (the band's
+// binary64 part).  (2) The stored generator p_i differs from the exact
+// mirror image R_i of the stored p_0 across edge line i by some delta_i
+// (the rounding of Algorithm 4): a, b, c and the products of Eq. 8 are
+// rounded relative to the coordinate scale S = max |coordinate| over the
+// vertices and p_0, and a first-order count of those roundings gives
+// |delta_i| <= 40 v S; the index uses 64 v S (exact rational reflections of
+// random polygons measure at most 7 v S).  Against the exact edge line the
+// margin changes by at most 2 |p - R_i| delta + delta^2.  With
+// m_i = 2 |R_i - p_0| s_i (s_i the signed distance past edge line i), every
+// point binary64 calls inside lies in the polygon with each edge moved out
+// by t(rho) = (E64 + 2 (rho + sqrt(d2) + sqrt(H2) + delta) delta + delta^2)
+// / (2 (min |h_i| - delta)), rho = |p - o|; such an offset moves a vertex of
+// interior angle theta by t / sin(theta / 2).  The box is widened by twice
+// t(2 r) / min sin(theta_i / 2) (r the largest vertex distance from o) and
+// rounded outwards to float32.  For rho > 2 r the same offset polygon lies
+// within r + t(rho) / smin of o, so binary64 calls no point inside for
+// r + t(rho) / smin < rho: a quadratic in rho, negative between two roots;
+// the polygon is cell-listed only if 2 r lies between them, and the larger
+// root (rounded down) is its far radius.  The grid's near region is the
+// box of the cell-listed boxes and local origins, widened by its diagonal
+// on each side; a polygon whose far radius does not exceed four times
+// that diagonal goes to the global list, so within the near region a point
+// outside a cell-listed polygon's box is outside it in binary64 too.  A
+// point beyond the near region tests every polygon in index order (such
+// points are far from all of them; at distances beyond the far radii
+// Algorithm 5's rounding can call them inside: at 1e30 from a unit polygon
+// every squared distance rounds to the same value).  A polygon without a
+// finite, small widening (degenerate or non-convex input, non-finite
+// vertices, or a centroid that binary64 rounding put outside the polygon)
+// goes to the global list, which every query tests as well
+// (binary64 decides; normally empty).  A box corner and a query point are
+// mapped to cells by the same float32 function, monotone in the coordinate,
+// so a point inside a box is in a cell of the box's range.  The answer is
+// the minimum containing index, so the order of a cell's list does not
+// matter.
 //
 //   k_index_prepare   one wave per polygon: generators (Algorithms 3-4),
 //                     float32 table in the polygon's local frame, band
 //                     constants, outward-rounded box; n > 64 is flagged.
-//   k_index_bounds    one block: union box of the usable polygons, grid
+//   k_index_bounds    one block: near region, demotions, union box of the
+//                     cell-listed polygons, grid
 //                     shape (about the requested cell count, square cells).
 //   k_index_count /   one thread per polygon: its cell range, counted, then
 //   k_index_fill      written into the cell lists (after an exclusive scan).
@@ -100,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_index_prepare(int64_t P,
     const double ylo = -wave_max(-v.y), yhi = wave_max(v.y);
     const bool all_fin = __ballot(!(isfinite(v.x) && isfinite(v.y))) == 0;
     // widening: binary64 misclassification distance (see the file comment)
-    double widen = __builtin_huge_val();
+    double widen = __builtin_huge_val(), rfar = 0.0;
     {
         const double g0x = L.gen[0].x, g0y = L.gen[0].y;
         const double hx = L.gen[1 + i].x - g0x, hy = L.gen[1 + i].y - g0y;
@@ -116,9 +140,35 @@ __global__ __launch_bounds__(kBlock) void k_index_prepare(int64_t P,
         const double ox = (double)L.ox, oy = (double)L.oy;
         const double rv = wave_max(sqrt((v.x - ox) * (v.x - ox) + (v.y - oy) * (v.y - oy)));
         const double d2 = (g0x - ox) * (g0x - ox) + (g0y - oy) * (g0y - oy);
-        const double e64 = 24.01 * kU64 * (4.0 * rv * rv) + 4.0001 * kU64 * (6.0 * d2 + 2.0 * H2);
-        const double w = 2.0 * e64 / (2.0 * hmin * smin) * 1.01;
-        if (L.status == 0 && hmin > 0.0 && smin > 0.0 && w <= rv && w == w) widen = w;
+        const double S = fmax(wave_max(fmax(fabs(v.x), fabs(v.y))), fmax(fabs(g0x), fabs(g0y)));
+        const double dl = 64.0 * kU64 * S;                 // generator error bound
+        const double hs = (hmin - dl) * smin;              // > 0 for a usable polygon
+        const double e0 = 4.0001 * kU64 * (6.0 * d2 + 2.0 * H2);
+        const double lev = sqrt(d2) + sqrt(H2) + dl;       // |p - R_i| - rho
+        // t(rho) and the far quadratic qa rho^2 - qb rho + qc < 0
+        const double rho2 = 2.0 * rv;
+        const double t2 = (24.01 * kU64 * rho2 * rho2 + e0 + 2.0 * (rho2 + lev) * dl + dl * dl) /
+                          (2.0 * (hmin - dl));
+        const double w = 2.0 * t2 / smin * 1.01;
+        const double qa = 24.01 * kU64 * 1.01;
+        const double qb = (2.0 * hs - 2.0 * dl) * 0.99;
+        const double qc = (2.0 * hs * rv + e0 + 2.0 * lev * dl + dl * dl) * 1.01;
+        const double disc = qb * qb - 4.0 * qa * qc;
+        const bool near_ok = qa * rho2 * rho2 - qb * rho2 + qc < 0.0 && disc > 0.0;
+        // p_0 strictly on the inner side of every edge line (its orientation
+        // against edge i, with 8 v |e| |r| for the rounding of the cross
+        // product): Algorithm 3 in the global frame can place the centroid
+        // of a small polygon far from the origin outside it, and then the
+        // set Algorithm 5 accepts is not the polygon
+        const double ex = v.x - vp.x, ey = v.y - vp.y, rx = g0x - vp.x, ry = g0y - vp.y;
+        const double cr = ex * ry - ey * rx;
+        const double crb = 8.0 * kU64 * sqrt(ex * ex + ey * ey) * sqrt(rx * rx + ry * ry);
+        const bool g0_in = -wave_max(-(cr - crb)) > 0.0 || wave_max(cr + crb) < 0.0;
+        if (L.status == 0 && g0_in && hmin > 2.0 * dl && smin > 0.0 && w <= rv && w == w &&
+            near_ok) {
+            widen = w;
+            rfar = (qb + sqrt(disc)) / (2.0 * qa) * 0.999;
+        }
     }
     const double wx = widen + 4.0 * kU64 * fmax(fabs(xlo), fabs(xhi));
     const double wy = widen + 4.0 * kU64 * fmax(fabs(ylo), fabs(yhi));
@@ -149,42 +199,78 @@ __global__ __launch_bounds__(kBlock) void k_index_prepare(int64_t P,
         R.by0 = round_out_lo(ylo - wy);
         R.bx1 = round_out_hi(xhi + wx);
         R.by1 = round_out_hi(yhi + wy);
+        R.rfar = round_out_lo(rfar);
         rec[k] = R;
         if (status) status[k] = L.status;
     }
 }
 
-// One block: union of the usable boxes and the grid shape.
-__global__ __launch_bounds__(1024) void k_index_bounds(int64_t P, const LocRec* __restrict__ rec,
-                                                     int64_t cells, LocGrid* __restrict__ grid) {
-    __shared__ float red[4][1024];
+// One block: the near region (the box of the cell-listed boxes and local
+// origins, widened by its diagonal on each side, rounded inwards), the
+// demotion to the global list of polygons whose far radius does not cover
+// it, then the union of the remaining cell-listed boxes and the grid shape.
+__device__ __forceinline__ void block_min4(float (&v)[4], float (*red)[1024]) {
     const int t = threadIdx.x;
-    float x0 = __builtin_huge_valf(), y0 = __builtin_huge_valf();
-    float x1 = -__builtin_huge_valf(), y1 = -__builtin_huge_valf();
-    for (int64_t k = t; k < P; k += blockDim.x) {
-        const LocRec& R = rec[k];
-        if (R.usable != 1) continue;
-        x0 = fminf(x0, R.bx0);
-        y0 = fminf(y0, R.by0);
-        x1 = fmaxf(x1, R.bx1);
-        y1 = fmaxf(y1, R.by1);
-    }
-    red[0][t] = x0;
-    red[1][t] = y0;
-    red[2][t] = -x1;
-    red[3][t] = -y1;
+    for (int c = 0; c < 4; ++c) red[c][t] = v[c];
     __syncthreads();
     for (int s = blockDim.x / 2; s > 0; s >>= 1) {
         if (t < s)
             for (int c = 0; c < 4; ++c) red[c][t] = fminf(red[c][t], red[c][t + s]);
         __syncthreads();
     }
+    for (int c = 0; c < 4; ++c) v[c] = red[c][0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void k_index_bounds(int64_t P, LocRec* __restrict__ rec,
+                                                     int64_t cells, LocGrid* __restrict__ grid) {
+    __shared__ float red[4][1024];
+    const int t = threadIdx.x;
+    // near region from the cell-listed boxes and their local origins
+    float u[4] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(),
+                  __builtin_huge_valf()};  // x0, y0, -x1, -y1
+    for (int64_t k = t; k < P; k += blockDim.x) {
+        const LocRec& R = rec[k];
+        if (R.usable != 1) continue;
+        u[0] = fminf(u[0], fminf(R.bx0, R.ox));
+        u[1] = fminf(u[1], fminf(R.by0, R.oy));
+        u[2] = fminf(u[2], -fmaxf(R.bx1, R.ox));
+        u[3] = fminf(u[3], -fmaxf(R.by1, R.oy));
+    }
+    block_min4(u, red);
+    const bool any_u = u[0] <= -u[2] && u[1] <= -u[3];
+    // the region's diagonal (rounded up) and the near region U widened by it
+    double diag = 0.0;
+    if (any_u) {
+        const double wx = (double)(-u[2]) - (double)u[0], wy = (double)(-u[3]) - (double)u[1];
+        diag = sqrt(wx * wx + wy * wy) * (1.0 + 1e-12);
+    }
+    const float fx0 = round_out_hi((double)u[0] - diag), fy0 = round_out_hi((double)u[1] - diag);
+    const float fx1 = round_out_lo((double)(-u[2]) + diag), fy1 = round_out_lo((double)(-u[3]) + diag);
+    // a point of the near region is within (1 + 2 sqrt 2) diag < 4 diag of
+    // every local origin
+    const double need = 4.0 * diag * (1.0 + 1e-9);
+    float x[4] = {__builtin_huge_valf(), __builtin_huge_valf(), __builtin_huge_valf(),
+                  __builtin_huge_valf()};
+    for (int64_t k = t; k < P; k += blockDim.x) {
+        LocRec& R = rec[k];
+        if (R.usable != 1) continue;
+        if (!((double)R.rfar > need)) {
+            R.usable = 2;
+            continue;
+        }
+        x[0] = fminf(x[0], R.bx0);
+        x[1] = fminf(x[1], R.by0);
+        x[2] = fminf(x[2], -R.bx1);
+        x[3] = fminf(x[3], -R.by1);
+    }
+    block_min4(x, red);
     if (t == 0) {
         LocGrid G;
-        G.x0 = red[0][0];
-        G.y0 = red[1][0];
-        G.x1 = -red[2][0];
-        G.y1 = -red[3][0];
+        G.x0 = x[0];
+        G.y0 = x[1];
+        G.x1 = -x[2];
+        G.y1 = -x[3];
         const bool any = G.x0 <= G.x1 && G.y0 <= G.y1;
         const double w = any ? (double)G.x1 - (double)G.x0 : 0.0;
         const double h = any ? (double)G.y1 - (double)G.y0 : 0.0;
@@ -202,6 +288,11 @@ __global__ __launch_bounds__(1024) void k_index_bounds(int64_t P, const LocRec* 
         G.inv_w = w > 0.0 ? (float)((double)gx / w) : 0.0f;
         G.inv_h = h > 0.0 ? (float)((double)gy / h) : 0.0f;
         G.any = any ? 1 : 0;
+        // no cell-listed polygon: every point takes the global list only
+        G.fx0 = any_u ? fx0 : -__builtin_huge_valf();
+        G.fy0 = any_u ? fy0 : -__builtin_huge_valf();
+        G.fx1 = any_u ? fx1 : __builtin_huge_valf();
+        G.fy1 = any_u ? fy1 : __builtin_huge_valf();
         *grid = G;
     }
 }
@@ -305,13 +396,17 @@ constexpr int kScanBatch = 8;  // cell entries per round trip (a cell holds ~5 o
 // Smallest index of a polygon containing p, or -1: the candidates of p's
 // cell (their boxes first: only box hits read a record), then the global
 // list.  Each candidate: float32 screen, binary64 replay inside the band; a
-// NaN box (non-finite vertices) never rejects.
+// NaN box (non-finite vertices) never rejects.  A point beyond the near
+// region tests every polygon in index order; a non-finite point is outside
+// every polygon.
 __device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
                                             const int32_t* __restrict__ cell_off,
                                             const LocEntry* __restrict__ list,
                                             const float4* __restrict__ qrec,
-                                            const double2* __restrict__ gen, int gbeg, int gend) {
+                                            const double2* __restrict__ gen, int gbeg, int gend,
+                                            const LocRec* __restrict__ rec, int64_t P) {
     int id = -1;
+    if (!(isfinite(p.x) && isfinite(p.y))) return -1;
     // polygon k (record at qoff) contains p: float32 screen, binary64 inside the band
     auto inside = [&](int qoff, int nn) -> bool {
         const float4* r = qrec + qoff;
@@ -375,7 +470,15 @@ __device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
             }
         }
     };
-    // outside the union of the cell boxes (or NaN): only the global list
+    if (!(p.x >= G.fx0 && p.x <= G.fx1 && p.y >= G.fy0 && p.y <= G.fy1)) {
+        // beyond the near region: every polygon, in index order
+        for (int64_t k = 0; k < P; ++k) {
+            const LocRec& R = rec[k];
+            if (R.usable != 0 && inside((int)R.qoff, R.n | (R.n4 << 16))) return (int)k;
+        }
+        return -1;
+    }
+    // outside the union of the cell boxes: only the global list
     if (G.any && p.x >= G.x0 && p.x <= G.x1 && p.y >= G.y0 && p.y <= G.y1) {
         const int64_t c =
             (int64_t)cell_of(p.y, G.y0, G.inv_h, G.gy) * G.gx + cell_of(p.x, G.x0, G.inv_w, G.gx);
@@ -385,7 +488,8 @@ __device__ __forceinline__ int locate_point(float2 p, const LocGrid& G,
     return id;
 }
 
-__global__ __launch_bounds__(kBlock) void k_locate(const float4* __restrict__ qrec,
+__global__ __launch_bounds__(kBlock) void k_locate(const LocRec* __restrict__ rec, int64_t P,
+                                                 const float4* __restrict__ qrec,
                                                  const double2* __restrict__ gen,
                                                  const LocGrid* __restrict__ grid,
                                                  const int32_t* __restrict__ cell_off,
@@ -398,7 +502,8 @@ __global__ __launch_bounds__(kBlock) void k_locate(const float4* __restrict__ qr
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
         const vfloat2 pv = __builtin_nontemporal_load(reinterpret_cast<const vfloat2*>(Q) + i);
-        ids[i] = locate_point(make_float2(pv.x, pv.y), G, cell_off, list, qrec, gen, gbeg, gend);
+        ids[i] = locate_point(make_float2(pv.x, pv.y), G, cell_off, list, qrec, gen, gbeg, gend,
+                              rec, P);
     }
 }
 
@@ -502,7 +607,7 @@ constexpr int kMaxKeys = 1025;                 // sf <= 32
 constexpr int kScanPer = (kMaxKeys + kLocBlock - 1) / kLocBlock;
 
 __global__ __launch_bounds__(kLocBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_locate_binned(
-    const float4* __restrict__ qrec, const double2* __restrict__ gen,
+    const LocRec* __restrict__ rec, int64_t P, const float4* __restrict__ qrec, const double2* __restrict__ gen,
     const LocGrid* __restrict__ grid, const int32_t* __restrict__ cell_off,
     const LocEntry* __restrict__ list, const BinnedPt* __restrict__ binned, int64_t m, int sf,
     int32_t* __restrict__ ids) {
@@ -573,7 +678,7 @@ __global__ __launch_bounds__(kLocBlock) __attribute__((amdgpu_waves_per_eu(4))) 
         for (int q = tid; q < cnt; q += kLocBlock) {
             const BinnedPt b = sorted_s[q];
             const int id =
-                locate_point(make_float2(b.x, b.y), G, cell_off, list, qrec, gen, gbeg, gend);
+                locate_point(make_float2(b.x, b.y), G, cell_off, list, qrec, gen, gbeg, gend, rec, P);
             ids[(int64_t)b.pad * kBinTile + b.idx] = id;
         }
         __syncthreads();  // the tile's LDS is reused
@@ -597,7 +702,7 @@ hipError_t index_prepare(int64_t P, const int64_t* vtx_off, const double* V, Loc
 
 // cnt: cells + 1 counters (cell counts, then the global list at gx * gy);
 // total: entries of all lists (unsigned long long).
-hipError_t index_grid(int64_t P, const LocRec* rec, int64_t cells, LocGrid* grid, int32_t* cnt,
+hipError_t index_grid(int64_t P, LocRec* rec, int64_t cells, LocGrid* grid, int32_t* cnt,
                       unsigned long long* total, hipStream_t stream) {
     hipLaunchKernelGGL(k_index_bounds, dim3(1), dim3(1024), 0, stream, P, rec, cells, grid);
     hipLaunchKernelGGL(k_index_zero, dim3((unsigned)((cells + 1 + 255) / 256)), dim3(256), 0,
@@ -624,13 +729,14 @@ hipError_t index_fill(int64_t P, const LocRec* rec, const LocGrid* grid, int64_t
     return hipGetLastError();
 }
 
-hipError_t launch_locate(const float4* qrec, const double2* gen, const LocGrid* grid,
-                         const int32_t* cell_off, const LocEntry* list, const float* Q, int64_t m,
-                         int32_t* ids, int max_blocks, hipStream_t stream) {
+hipError_t launch_locate(const LocRec* rec, int64_t P, const float4* qrec, const double2* gen,
+                         const LocGrid* grid, const int32_t* cell_off, const LocEntry* list,
+                         const float* Q, int64_t m, int32_t* ids, int max_blocks,
+                         hipStream_t stream) {
     if (m == 0) return hipSuccess;
     const int64_t want = (m + kBlock - 1) / kBlock;
     const int grid_blocks = (int)(want < max_blocks ? want : max_blocks);
-    hipLaunchKernelGGL(k_locate, dim3(grid_blocks), dim3(kBlock), 0, stream, qrec, gen, grid,
+    hipLaunchKernelGGL(k_locate, dim3(grid_blocks), dim3(kBlock), 0, stream, rec, P, qrec, gen, grid,
                        cell_off, list, reinterpret_cast<const float2*>(Q), m, ids);
     return hipGetLastError();
 }
@@ -651,7 +757,8 @@ size_t locate_binned_workspace(int nbins, int64_t m, size_t* o_cnt, size_t* o_of
     return off;
 }
 
-hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const LocGrid* grid,
+hipError_t launch_locate_binned(const LocRec* rec, int64_t P, const float4* qrec,
+                                const double2* gen, const LocGrid* grid,
                                 const int32_t* cell_off, const LocEntry* list, int sf, int sgx,
                                 int nbins, const float* Q, int64_t m, int32_t* ids, void* ws,
                                 int cus, hipStream_t stream) {
@@ -678,7 +785,8 @@ hipError_t launch_locate_binned(const float4* qrec, const double2* gen, const Lo
     // one block per tile (m < 2^31: fewer than 2^20 tiles): more blocks than
     // fit on the chip at once even out the end of the launch
     const int64_t tiles = (m + kLocTile - 1) / kLocTile;
-    hipLaunchKernelGGL(k_locate_binned, dim3((unsigned)tiles), dim3(kLocBlock), 0, stream, qrec, gen,
+    hipLaunchKernelGGL(k_locate_binned, dim3((unsigned)tiles), dim3(kLocBlock), 0, stream, rec, P,
+                       qrec, gen,
                        grid, cell_off, list, pts, m, sf, ids);
     return hipGetLastError();
 }

@@ -564,6 +564,24 @@ def pin_cost_argmin(o):
     assert h1[0] != h0[0] and h2[0] == h0[0]
 
 
+def pin_locate_far_rounding(o):
+    """Far beyond a polygon, Algorithm 5's binary64 squared distances all
+    round to one value: for p = (2^100, 2^100) and generators of magnitude
+    below 2^40, every p - g rounds to 2^100 and every squared distance to
+    2^201, so M_0 <= M_i holds for every edge and the smallest index wins
+    (the y terms of (2^100, 2^20), about 2^40, are absorbed below the
+    spacing 2^148 of 2^200, so that point is inside too).  At (2^20, 2^20)
+    the margins (about 2^21) dwarf the rounding (about 2^-12): outside."""
+    polys = [np.array([[2.0, 0], [3, 0], [3, 1], [2, 1]]), np.array([[0.0, 0], [1, 0], [0, 1]])]
+    off = np.array([0, 4, 7])
+    V = np.concatenate(polys)
+    Q = np.array([[2.0 ** 100, 2.0 ** 100], [-(2.0 ** 100), 2.0 ** 100]])
+    assert o.locate(off, V, Q).tolist() == [0, 0]
+    assert o.voronoi(polys[1], Q).tolist() == [True, True]
+    assert o.voronoi(polys[1], np.array([[2.0 ** 100, 2.0 ** 20]])).tolist() == [True]
+    assert o.locate(off, V, np.array([[2.0 ** 20, 2.0 ** 20]])).tolist() == [-1]
+
+
 ALL_PINS = [
     pin_square_and_triangle,
     pin_raster_exact,
@@ -571,6 +589,7 @@ ALL_PINS = [
     pin_locate_hand_worked,
     pin_locate_partition,
     pin_locate_overlapping,
+    pin_locate_far_rounding,
     pin_regular_ngon,
     pin_generators_exact_rational,
     pin_generator_invariants,

@@ -158,6 +158,82 @@ def test_locate_far_from_origin(P, oracle, origin):
     check(P, oracle, part.vtx_off, part.V, Q, tag=f"far {origin}")
 
 
+def _float32_rows_through_vertices(V, rng, xs=5, ys=1):
+    """Points on the float32 rows through each vertex: y the float32 values
+    nearest to the vertex's y (and ys neighbours each way), x the float32
+    values nearest to its x (and xs neighbours each way)."""
+    out = []
+    for vx, vy in V:
+        x32 = np.float32(vx)
+        y32 = np.float32(vy)
+        xv = [x32]
+        for _ in range(xs):
+            xv.append(np.nextafter(xv[-1], np.float32(np.inf)))
+        x = x32
+        for _ in range(xs):
+            x = np.nextafter(x, np.float32(-np.inf))
+            xv.append(x)
+        yv = [y32]
+        for _ in range(ys):
+            yv.append(np.nextafter(yv[-1], np.float32(np.inf)))
+        y = y32
+        for _ in range(ys):
+            y = np.nextafter(y, np.float32(-np.inf))
+            yv.append(y)
+        for a in xv:
+            for b in yv:
+                out.append((a, b))
+    return np.array(out, dtype=np.float32)
+
+
+def test_locate_partition_across_axis_far_in_y(P, oracle):
+    """A jittered partition at (-25, 1e5) that crosses x = 0: small x
+    coordinates and large y coordinates, where the rounding of the stored
+    generators (scaled by the largest coordinate) exceeds the evaluation
+    error scaled by x; points on the float32 rows through every vertex."""
+    rng = np.random.default_rng(31)
+    part = W.jittered_partition(25, 20, cell=2.0, split=0.5, origin=(-25.0, 1.0e5), seed_salt=6)
+    Q = np.concatenate([partition_points(rng, part, 20_000).astype(np.float32),
+                        _float32_rows_through_vertices(part.V, rng)])
+    check(P, oracle, part.vtx_off, part.V, Q, tag="across x=0 at y=1e5")
+
+
+def test_locate_thin_polygons_at_large_y(P, oracle):
+    """Small polygons with x in 1e-9..1e-3 and y in 1e5..1e7 (x-extent far
+    below the float32 spacing of y): points on the float32 rows through
+    their vertices, each polygon indexed on its own and all together."""
+    rng = np.random.default_rng(37)
+    polys = []
+    for _ in range(300):
+        cx = rng.choice([-1.0, 1.0]) * 10 ** rng.uniform(-9, -3)
+        cy = rng.choice([-1.0, 1.0]) * 10 ** rng.uniform(5, 7)
+        r = 10 ** rng.uniform(-9, -3)
+        polys.append(W.circle_polygon(int(rng.integers(3, 12)), r, (cx, cy), rng))
+    Q = np.concatenate([_float32_rows_through_vertices(p, rng, xs=8, ys=1) for p in polys])
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])])
+    check(P, oracle, off, np.concatenate(polys), Q, tag="thin at large y, together")
+    for k in range(0, 300, 30):
+        q = _float32_rows_through_vertices(polys[k], rng, xs=12, ys=2)
+        check(P, oracle, [0, len(polys[k])], polys[k], q, tag=f"thin at large y, polygon {k}")
+
+
+def test_locate_points_beyond_the_near_region(P, oracle):
+    """Points so far from every polygon that Algorithm 5's binary64 squared
+    distances round to equal values (the oracle then calls them inside):
+    they take the every-polygon path and get the oracle's ids; far points
+    where rounding still decides outside get -1."""
+    rng = np.random.default_rng(41)
+    part = W.jittered_partition(12, 10, cell=1.0, split=0.5, origin=(-6.0, -5.0), seed_salt=2)
+    far = np.array([[1e30, 1e30], [-1e25, 3e38], [2.0 ** 80, -2.0 ** 80], [1e15, 0.0],
+                    [-3e38, -3e38], [1e7, 1e7], [0.0, 1e20], [5e18, -7e17]], dtype=np.float32)
+    Q = np.concatenate([partition_points(rng, part, 5_000).astype(np.float32), far,
+                        (rng.standard_normal((4000, 2)) * 10 ** rng.uniform(0, 38, (4000, 1)))
+                        .astype(np.float32)])
+    Q = Q[np.isfinite(Q).all(axis=1)]
+    want, _ = check(P, oracle, part.vtx_off, part.V, Q, tag="beyond the near region")
+    say(f"[stat] far points located by rounding: {int((want[-4000:] >= 0).sum())}")
+
+
 def test_locate_empty_and_errors(P):
     V = np.array([[0, 0], [1, 0], [1, 1], [0, 1]], float)
     got, _ = locate_gpu(P, [0, 4], V, np.zeros((0, 2)))
