@@ -6,14 +6,19 @@ Workload (one "step"): the streaming sweep -- six convex polygons with 3, 4,
 8, 16, 32 and 64 vertices on a circle of radius 1, each tested against its
 own 2^28 float32 points uniform in [-1.5, 1.5]^2 of which 1% lie within 1e-6
 of an edge.  Each polygon is one call of the C ABI's pip_voronoi (binary64
-generator derivation, float32 screen with proven band, binary64 recheck,
-packed labels), all on one stream with the inputs resident in HBM.
+generator derivation, float32 screen of every edge's margin with a proven
+band, binary64 recheck, packed labels), all on one stream with the inputs
+resident in HBM.  Every point meets every edge, as in the paper's own
+comparison of the tests (Section 6.2); the radial pre-screen, a culling
+layer in front of the test, is timed and reported apart.
 
 Prints one JSON line: whole-step throughput in G point-polygon tests/s, the
 roofline of the dominant kernel (measured with HIP events on the launch
-stream), per-polygon figures, sign-of-offset and float32-only kernels for
-comparison, label mismatches against the FP64 oracle on a sample, and the
-oracle's own throughput on the host cores.
+stream), per-polygon figures (with the float32 margin error against the
+binary64 one and the share of points the band sends to binary64), sign of
+offset, ray crossing and the float32-only kernel for comparison, label
+mismatches of all three tests against the FP64 oracle over the whole sweep,
+and the oracle's own throughput on the host cores.
 """
 from __future__ import annotations
 
@@ -130,6 +135,40 @@ def annulus_fraction(P, torch, V, Q, sample=1 << 20):
     return round(float(1.0 - decided.mean()), 5)
 
 
+def margin_statistics(P, torch, o, V, Vt, Qt, Q, matrix, sample=1 << 22):
+    """Float32 screen against binary64 on the first `sample` points (about
+    1% of them within 1e-6 of an edge): the largest |M_hat - D| in units of
+    u (alpha|X| + beta|Y| + gamma), u = 2^-24 (M_hat the float32 largest
+    margin of the vector screen, pip_voronoi_max_margin; D the binary64 one
+    of Algorithm 5, the oracle; alpha, beta, gamma the largest |A_i|, |B_i|,
+    |C_i| of the screen table), the largest share of the band E it uses, and
+    the share of points whose margin lies inside the band of the screen the
+    launch takes (`matrix`: the matrix-core screen's wider band), i.e. the
+    points sent to the binary64 recheck (estimated with the vector M_hat)."""
+    S = int(min(sample, len(Q)))
+    mh = P.pip_voronoi_max_margin(Vt, Qt[:S]).cpu().numpy().astype(np.float64)
+    D = o.voronoi_max_margin(V, Q[:S].astype(np.float64))
+    tab = P.pip_screen_table(Vt, 0, 0).cpu().numpy()
+    ox, oy = np.float32(tab[0]), np.float32(tab[1])
+    n4 = int(tab[6])
+    rows = tab[8:8 + 4 * n4].reshape(n4, 4).astype(np.float64)
+    X = (Q[:S, 0] - ox).astype(np.float64)  # float32 subtraction, as the screen
+    Y = (Q[:S, 1] - oy).astype(np.float64)
+    al, be, ga = np.abs(rows[:, 0]).max(), np.abs(rows[:, 1]).max(), np.abs(rows[:, 2]).max()
+    err = np.abs(mh - D)
+    scale = al * np.abs(X) + be * np.abs(Y) + ga
+
+    def band(t):
+        return (float(t[2]) * (X * X + Y * Y) + float(t[3]) * np.abs(X) + float(t[4]) * np.abs(Y)
+                + float(t[5]))
+    E = band(tab)
+    Eb = band(P.pip_screen_table(Vt, 0, 1).cpu().numpy()) if matrix else E
+    return {"sample_points": S,
+            "max_err_u": round(float((err / scale).max() / 2.0 ** -24), 4),
+            "max_err_over_band": round(float((err / E).max()), 4),
+            "band_frac": round(float((~((mh < -Eb) | (mh > Eb))).mean()), 6)}
+
+
 def _time(torch, stream, fn, reps=5, warm=1):
     for _ in range(warm):
         fn()
@@ -199,14 +238,14 @@ def run_extras(P, W, torch, stream, check):
     out["uneven_batch"] = entry
     plan.close()
 
-    # a batch of 32-edge polygons: the radial pre-screen (default from 20
-    # edges) against the per-edge screen, each in its own autotuned plan
+    # a batch of 32-edge polygons: the per-edge screen (default) and the
+    # radial pre-screen (reported apart), each in its own autotuned plan
     B32 = W.uneven_batch(n_lo=32, n_hi=32)
     t32 = [torch.from_numpy(a).to(dev) for a in (B32.vtx_off, B32.V, B32.pt_off, B32.Q,
                                                    B32.lbl_word_off)]
     e32 = {"polygons": B32.num_polygons, "tests": B32.num_tests}
     radial_min = int(P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES))
-    for key, rmin in (("graph_ms", radial_min), ("per_edge_graph_ms", 0)):
+    for key, rmin in (("graph_ms", radial_min), ("radial_graph_ms", 20)):
         P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, rmin)
         try:
             pl = P.BatchedPlan(*t32)
@@ -314,6 +353,15 @@ def run_extras(P, W, torch, stream, check):
         e = {"ms": round(ms_r, 4), "gpixels_per_s": round(N * N / ms_r / 1e6, 1),
              "fp32_tflops": round(tfl, 2), "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4)}
         radial_min = int(P.get_option(P.PIP_OPT_RADIAL_MIN_EDGES))
+        if n >= 20 and not (radial_min > 0 and n >= radial_min):
+            # the radial pre-screen (off by default), reported apart
+            P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 20)
+            try:
+                e["radial_ms"] = round(_time(torch, stream, lambda: P.pip_voronoi_raster(
+                    Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N, labels=lab_r), reps=10), 4)
+            finally:
+                P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, radial_min)
+            lab_r = P.pip_voronoi_raster(Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N, labels=lab_r)
         if radial_min > 0 and n >= radial_min:
             # the radial pre-screen decides most pixels from r2; the 4n flop
             # figure above is the per-edge work it replaces.  The per-edge
@@ -592,6 +640,15 @@ def main() -> int:
             # only the annulus points meet the 4n flop per-edge screen
             r["per_edge_equivalent_tflops"] = r.pop("fp32_tflops")
             r["fp32_frac"] = None
+    if not args.no_cpu:
+        # float32 margin error against binary64 and the share rechecked
+        from oracle import Oracle
+        o_stat = Oracle()
+        for r in kernels:
+            n = r["n"]
+            V, Qs = host_q[n]
+            r["margin_vs_binary64"] = margin_statistics(P, torch, o_stat, V, polys[n], pts[n], Qs,
+                                                        r["screen"] == "mfma")
     dom = max(kernels, key=lambda r: r["ms"])
     # binding roofline of the dominant launch: bytes vs flops at peak
     t_hbm = BYTES_PER_TEST * m / (HBM_PEAK_GBS * 1e9)
@@ -632,19 +689,28 @@ def main() -> int:
         return a.elapsed_time(b) / reps
 
     soo = {n: time_fn(P.pip_sign_of_offset, n) for n in NS}
-    # the per-edge screens alone (radial pre-screen off), as the paper's
-    # comparison runs every test on every edge
-    P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 0)
-    try:
-        full = {n: time_fn(P.pip_voronoi, n) for n in NS}
-    finally:
-        P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, radial_min)
     plain = {n: time_fn(P.pip_voronoi_fp32_plain, n) for n in NS}
     ray = {n: time_fn(P.pip_ray_crossing, n, reps=1) for n in NS}
+    # the radial pre-screen (a culling layer in front of the test: points
+    # between two radii per octant meet the per-edge screen, the others are
+    # decided from their distance to p_0), reported apart from the dense
+    # sweep; its labels must equal the dense ones word for word
+    radial = {}
+    for n in (16, 32, 64):
+        dense = labels[n].clone()
+        P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, 3)
+        try:
+            ms_r = time_fn(P.pip_voronoi, n)
+            same = bool(torch.equal(labels[n], dense))
+        finally:
+            P.set_option(P.PIP_OPT_RADIAL_MIN_EDGES, radial_min)
+        radial[str(n)] = {"ms": round(ms_r, 4), "speedup_vs_dense": round(per_n_ms[n] / ms_r, 2),
+                          "dense_equivalent_gtests_per_s": round(m / ms_r / 1e6, 1),
+                          "annulus_frac": annulus_fraction(P, torch, *host_q[n]),
+                          "labels_equal_dense": same}
+        del dense
     comparisons = {
-        "voronoi_per_edge_screen_gtests_per_s":
-            round(tests_per_step / (sum(full.values()) * 1e-3) / 1e9, 2),
-        "voronoi_per_edge_screen_ms": {str(n): round(v, 4) for n, v in full.items()},
+        "voronoi_radial_prescreen": radial,
         "sign_of_offset_gtests_per_s": round(tests_per_step / (sum(soo.values()) * 1e-3) / 1e9, 2),
         "sign_of_offset_ms": {str(n): round(v, 4) for n, v in soo.items()},
         "fp32_plain_gtests_per_s": round(tests_per_step / (sum(plain.values()) * 1e-3) / 1e9, 2),
@@ -664,18 +730,26 @@ def main() -> int:
         cpu_t = 0.0
         mismatches = 0
         plain_mismatches = 0
+        ref_mismatches = {"sign_of_offset": 0, "ray_crossing": 0}
+
+        def diff_bits(fn, n, want):
+            fn(polys[n], pts[n], labels[n])
+            got = labels[n][: (S + 31) // 32].cpu().numpy().view(np.uint32)
+            return int(np.unpackbits((got ^ pack_bits(want)).view(np.uint8)).sum())
         for n in NS:
             V, Qs = host_q[n]
             Q64 = Qs.astype(np.float64)
             c0 = time.perf_counter()
             want = o.voronoi(V, Q64)
             cpu_t += time.perf_counter() - c0
-            P.pip_voronoi(polys[n], pts[n], labels[n])
-            got = labels[n][: (S + 31) // 32].cpu().numpy().view(np.uint32)
-            mismatches += int(np.unpackbits((got ^ pack_bits(want)).view(np.uint8)).sum())
-            P.pip_voronoi_fp32_plain(polys[n], pts[n], labels[n])
-            got = labels[n][: (S + 31) // 32].cpu().numpy().view(np.uint32)
-            plain_mismatches += int(np.unpackbits((got ^ pack_bits(want)).view(np.uint8)).sum())
+            mismatches += diff_bits(P.pip_voronoi, n, want)
+            plain_mismatches += diff_bits(P.pip_voronoi_fp32_plain, n, want)
+            ref_mismatches["sign_of_offset"] += diff_bits(P.pip_sign_of_offset, n,
+                                                          o.sign_of_offset(V, Q64))
+            ref_mismatches["ray_crossing"] += diff_bits(P.pip_ray_crossing, n,
+                                                        o.ray_crossing(V, Q64))
+            del Q64, want
+            print(f"[bench] parity n={n} done", file=sys.stderr, flush=True)
         threads = o.num_threads()
         # one thread on 1/64 of the sample
         s1 = max(S // 64, 1)
@@ -703,13 +777,15 @@ def main() -> int:
                "single_thread_sample": f"first {s1} points of each polygon",
                "cpu_model": model, "host_cpus": os.cpu_count()}
         comparisons["fp32_plain_mismatches_on_sample"] = plain_mismatches
+        comparisons["sign_of_offset_mismatches_on_sample"] = ref_mismatches["sign_of_offset"]
+        comparisons["ray_crossing_mismatches_on_sample"] = ref_mismatches["ray_crossing"]
 
     extras = {} if args.no_extras else run_extras(P, W, torch, stream, not args.no_cpu)
     gpu = gpu_info(torch)
 
     out = {
-        "metric": "G point-polygon tests/s (Voronoi, certified float32 screen + binary64 "
-                  "recheck, labels bit-identical to the FP64 oracle)",
+        "metric": "G point-polygon tests/s (Voronoi, every edge of every point: certified "
+                  "float32 screen + binary64 recheck, labels bit-identical to the FP64 oracle)",
         "value": round(value, 2),
         "unit": "G tests/s",
         "n_gpus": 1,

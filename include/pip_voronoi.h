@@ -152,10 +152,12 @@ typedef struct pip_index_s *pip_index;
  *     screen for every 512-pixel segment that holds a pixel between the
  *     radii) and by pip_voronoi_batched and batched plans for every polygon
  *     of the batch that has this many edges (a plan or workspace takes the
- *     setting when it is created or launched); 0 disables it.  Default 20 (measured: the per-edge screen is faster for
- *     fewer edges, where more points fall between the radii).  Not from the
- *     paper: a screen in front of its test, from the nearest-generator
- *     reading of Section 4. */
+ *     setting when it is created or launched); 0 disables it.  Default 0 (off:
+ *     every point meets every edge, as in the paper's own comparison of the
+ *     tests, Section 6.2).  Measured: from about 20 edges it is faster than
+ *     the per-edge screen (fewer edges leave more points between the radii).
+ *     Not from the paper: a screen in front of its test, from the
+ *     nearest-generator reading of Section 4. */
 typedef enum {
     PIP_OPT_MFMA_MIN_EDGES = 1,
     PIP_OPT_ALLPAIRS_CULL = 2,
@@ -194,6 +196,27 @@ pip_status polygon_to_generators(pip_ctx ctx, const double *V, int32_t n, double
  */
 pip_status pip_voronoi_radial_bounds(pip_ctx ctx, const double *V, int32_t n, float *out,
                                      hipStream_t stream);
+
+/*
+ * The float32 screen table of one polygon, as pip_voronoi (test 0) or
+ * pip_sign_of_offset (test 1) derive it for the vector screen (matrix 0) or
+ * the matrix-core screen (matrix 1), for tests and diagnostics (the error
+ * band is not in the paper; it keeps Algorithm 5's binary64 answer while
+ * the margins of Eq. 11 are computed in float32).
+ *   V    [n][2] binary64 vertices, 3 <= n <= PIP_MAX_EDGES.
+ *   out  [8 + 4 n4] float32 (device), n4 = n rounded up to a multiple of 4:
+ *        out[0..8) = o_x, o_y (the local origin, fl32(p_0)), KQ, KA, KB, KC
+ *        (the band E = KQ (X^2 + Y^2) + KA |X| + KB |Y| + KC, X, Y the
+ *        point's float32 local coordinates), n4, the polygon's pip_status;
+ *        then n4 rows (A_i, B_i, -C_i, 0) with margin
+ *        m_i = A_i X + B_i Y - C_i (Voronoi; rows past n repeat edge 0) or
+ *        (-dV_y, dV_x, -R_i, 0) (sign of offset).  A point is decided in
+ *        float32 only when its largest margin clears the band.
+ * Asynchronous on `stream`; allocates nothing.  Errors: PIP_EINVAL for a bad
+ * argument, PIP_EUNSUPPORTED for n > PIP_MAX_EDGES.
+ */
+pip_status pip_screen_table(pip_ctx ctx, int32_t test, int32_t matrix, const double* V, int32_t n,
+                            float* out, hipStream_t stream);
 
 /*
  * Voronoi point-inclusion test (Section 4, Algorithm 5) of m points against

@@ -19,6 +19,7 @@ from .api import get_option, set_option
 from .api import (AllpairsPlan, BatchedPlan, LocateIndex, allpairs_workspace_bytes, batched_workspace_bytes, label_word_offsets, pip_poses_to_polygons,
                   pip_ray_crossing, pip_sign_of_offset, pip_voronoi, pip_voronoi_allpairs,
                   pip_voronoi_batched, pip_voronoi_fp32_plain, pip_voronoi_max_margin, pip_voronoi_radial_bounds, pip_voronoi_raster,
+                  pip_screen_table,
                   polygon_to_generators, unpack_labels)
 from .autograd import CollisionCost, CostPlan, collision_cost, pip_cost_bwd, pip_cost_fwd
 
@@ -26,6 +27,7 @@ __all__ = [
     "PIP_F32", "PIP_F64", "PipError", "lib_path", "load_library", "num_label_words",
     "status_name", "polygon_to_generators", "pip_voronoi", "pip_sign_of_offset",
     "pip_ray_crossing", "pip_voronoi_fp32_plain", "pip_voronoi_max_margin", "pip_voronoi_radial_bounds", "pip_voronoi_raster", "unpack_labels",
+    "pip_screen_table",
     "pip_voronoi_batched", "batched_workspace_bytes", "label_word_offsets", "BatchedPlan",
     "LocateIndex", "AllpairsPlan",
     "pip_poses_to_polygons", "pip_voronoi_allpairs", "allpairs_workspace_bytes", "pip_cost_fwd", "pip_cost_bwd",

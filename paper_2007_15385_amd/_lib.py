@@ -55,6 +55,7 @@ SIGNATURES = {
     "polygon_to_generators": (_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
     "pip_voronoi": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_voronoi_radial_bounds": (_int, [_vp, _vp, _i32, _vp, _vp]),
+    "pip_screen_table": (_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp]),
     "pip_sign_of_offset": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_ray_crossing": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_voronoi_fp32_plain": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),

@@ -19,7 +19,7 @@ struct pip_ctx_s {
     int raster_blocks[2] = {};     // persistent grid of the raster kernel (per-edge, radial)
     int batched_blocks_per_cu = 0;
     int mfma_min_edges = 25;       // polygons with at least this many edges use the matrix cores
-    int radial_min_edges = 20;     // Voronoi polygons with at least this many edges: radial pre-screen
+    int radial_min_edges = 0;      // Voronoi polygons with at least this many edges: radial pre-screen (0: off)
     int radial_blocks = 0;         // persistent grid of the radial kernel
     int allpairs_cull = 0;         // skip (polygon, wave) pairs whose bounding disk misses the points
     int cost_cull = 0;             // skip (pose, wave) pairs of the collision cost likewise
@@ -304,6 +304,23 @@ pip_status pip_voronoi_radial_bounds(pip_ctx ctx, const double* V, int32_t n, fl
     DeviceGuard g(ctx->device);
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     hipError_t e = pipdev::launch_radial_bounds(V, n, out, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+pip_status pip_screen_table(pip_ctx ctx, int32_t test, int32_t matrix, const double* V, int32_t n,
+                            float* out, hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    pip_status s = check_polygon(V, n);
+    if (s != PIP_OK) return s;
+    if (test != 0 && test != 1) return fail(PIP_EINVAL, "test = %d must be 0 or 1", (int)test);
+    if (matrix != 0 && matrix != 1) return fail(PIP_EINVAL, "matrix = %d must be 0 or 1", (int)matrix);
+    if (!out || !aligned(out, 4)) return fail(PIP_EINVAL, "out is NULL or not 4-byte aligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_screen_table(V, n, test ? pipdev::K_SOO : pipdev::K_VORONOI,
+                                               matrix ? pipdev::kMfmaScreenFactor : 4.05, out,
+                                               stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }

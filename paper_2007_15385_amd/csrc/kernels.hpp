@@ -154,6 +154,11 @@ hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, 
                        int pair, hipStream_t stream);
 hipError_t launch_count_diff(const uint32_t* a, const uint32_t* b, int64_t nwords,
                              unsigned long long* out, hipStream_t stream);
+// float32 screen table as the streaming screens derive it (factor: 4.05 for
+// the vector screen, kMfmaScreenFactor for the matrix cores)
+constexpr double kMfmaScreenFactor = 6.05;
+hipError_t launch_screen_table(const double* V, int n, int kind, double factor, float* out,
+                               hipStream_t stream);
 hipError_t launch_generators_one(const double* V, int n, double* P, int32_t* status,
                                  hipStream_t stream);
 hipError_t stream_max_blocks_per_cu(int kind, int qdt, int* out);

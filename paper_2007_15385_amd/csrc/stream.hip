@@ -681,6 +681,38 @@ __global__ __launch_bounds__(kWave) void k_radial_bounds(const double* __restric
 }
 
 // polygon_to_generators: one wave derives p_0 and the n outer generators.
+// The float32 screen table of one polygon as the streaming screens derive
+// it: out[0..8) = ox, oy, KQ, KA, KB, KC, n4, status; then n4 rows
+// (A, B, -C, 0) (Voronoi) or (-dV_y, dV_x, -R, 0) (sign of offset).
+__global__ __launch_bounds__(kWave) void k_screen_table(const double* __restrict__ V, int n,
+                                                       int kind, double factor,
+                                                       float* __restrict__ out) {
+    __shared__ PolyLds S;
+    const int lane = threadIdx.x;
+    if (lane < n) S.vtx[lane] = make_double2(V[2 * lane], V[2 * lane + 1]);
+    if (lane == 0) S.n = n;
+    __syncthreads();
+    prepare_polygon(S, kind, lane, false, factor);
+    __syncthreads();
+    if (lane == 0) {
+        out[0] = S.ox;
+        out[1] = S.oy;
+        out[2] = S.KQ;
+        out[3] = S.KA;
+        out[4] = S.KB;
+        out[5] = S.KC;
+        out[6] = (float)S.n4;
+        out[7] = (float)S.status;
+    }
+    for (int r = lane; r < S.n4; r += kWave) {
+        const float4 c = S.coef[r];
+        out[8 + 4 * r] = c.x;
+        out[9 + 4 * r] = c.y;
+        out[10 + 4 * r] = c.z;
+        out[11 + 4 * r] = c.w;
+    }
+}
+
 __global__ __launch_bounds__(kWave) void k_generators_one(const double* __restrict__ V, int n,
                                                          double* __restrict__ P,
                                                          int32_t* __restrict__ status) {
@@ -752,6 +784,12 @@ hipError_t launch_stream(const StreamLaunch& L) {
         default:
             return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_screen_table(const double* V, int n, int kind, double factor, float* out,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(k_screen_table, dim3(1), dim3(kWave), 0, stream, V, n, kind, factor, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_generators_one(const double* V, int n, double* P, int32_t* status,

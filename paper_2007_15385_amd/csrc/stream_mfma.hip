@@ -36,7 +36,7 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr double kMfmaFactor = 6.05;
+constexpr double kMfmaFactor = kMfmaScreenFactor;
 
 // max / min of the first R accumulator registers of one product, written as
 // a chain whose every step combines three values, so it compiles to v_max3 /

@@ -162,6 +162,22 @@ def test_all_points_undecided(P, oracle, test):
     assert_same(got, expect(oracle, otest, V, Q), len(Q), test)
 
 
+@pytest.mark.parametrize("test", ["voronoi", "sign_of_offset"])
+def test_all_points_undecided_float32_many_chunks(P, oracle, test):
+    """8M float32 points on the edges of an 8-gon (every one inside the
+    band): each wave of the float32 screens walks several 512-point chunks
+    and flushes its recheck queue on every one, so queue codes of later
+    chunks are exercised."""
+    rng = np.random.default_rng(18)
+    fn, otest = TESTS[test]
+    V = W.circle_polygon(8, 1.0, (0.01, -0.02), rng)
+    m = 8 << 20
+    Q = near_edge(rng, V, m, [0.0])[:m].astype(np.float32)
+    say(f"[case] {test} float32 all undecided m={m}")
+    got = run_gpu(P, fn, V, Q)
+    assert_same(got, expect(oracle, otest, V, Q), m, test)
+
+
 @pytest.mark.parametrize("test", list(TESTS))
 def test_nonfinite_points(P, oracle, test):
     fn, otest = TESTS[test]
@@ -300,6 +316,44 @@ def test_streaming_full_size_sampled(P, oracle, n):
         f"inside fraction {got.mean():.4f}")
     assert len(bad) == 0
     assert labels.size == W.STREAM_M // 32
+
+
+@pytest.mark.parametrize("n", W.STREAM_NS)
+def test_reference_tests_full_size_sampled(P, oracle, screen, n):
+    """Sign of offset (Algorithm 2) and ray crossing (Algorithm 1) on the
+    benchmark's 2^28-point launches: a 3M-point sample, the first and last
+    100k points and every point whose Voronoi margin is small (the near-edge
+    points) against the oracle.  Sign of offset takes the vector and the
+    matrix-core screens (the radial pre-screen is Voronoi's only); ray
+    crossing has no float32 screen and runs once."""
+    tests = {"valu": ["sign_of_offset", "ray_crossing"], "mfma": ["sign_of_offset"]}.get(screen)
+    if not tests:
+        pytest.skip("the same launches as the vector-screen run")
+    V = W.streaming_polygon(n)
+    say(f"[case] reference tests n={n} ({screen}): generating 2^28 points")
+    Q = W.streaming_points(V, W.STREAM_M)
+    Vt = torch.from_numpy(V).cuda()
+    Qt = torch.from_numpy(Q).cuda()
+    mm = P.pip_voronoi_max_margin(Vt, Qt)
+    rng = np.random.default_rng(200 + n)
+    idx = np.unique(np.concatenate([
+        rng.integers(0, W.STREAM_M, 3_000_000),
+        np.arange(0, 100_000), np.arange(W.STREAM_M - 100_000, W.STREAM_M),
+        torch.nonzero(mm.abs() < 1e-5).flatten()[:2_000_000].cpu().numpy()]))
+    del mm
+    Qs = Q[idx].astype(np.float64)
+    for test in tests:
+        fn, otest = TESTS[test]
+        say(f"[case] {test} n={n} 2^28 points, GPU")
+        lab = getattr(P, fn)(Vt, Qt)
+        torch.cuda.synchronize()
+        labels = lab.cpu().numpy().view(np.uint32)
+        assert labels.size == W.STREAM_M // 32
+        want = getattr(oracle, otest)(V, Qs)
+        got = ((labels[idx >> 5] >> (idx & 31).astype(np.uint32)) & 1).astype(bool)
+        bad = np.nonzero(got != want)[0]
+        say(f"[stat] {test} n={n}: checked {len(idx)} sampled points, {len(bad)} mismatches")
+        assert len(bad) == 0
 
 
 @pytest.mark.parametrize("qdt", [np.float32, np.float64])
