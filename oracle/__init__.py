@@ -54,6 +54,7 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "oracle_centroid": (ctypes.c_int, [_D, _i64, _D, _D]),
         "oracle_generators": (ctypes.c_int, [_D, _i64, _D]),
         "oracle_voronoi": (ctypes.c_int, [_D, _i64, _D, _i64, _U8]),
+        "oracle_voronoi_pieces": (ctypes.c_int, [_D, _i64, _I64, _i64, _I64, _D, _i64, _U8]),
         "oracle_locate": (ctypes.c_int, [_I64, _i64, _D, _D, _i64, _I32]),
         "oracle_voronoi_raster": (ctypes.c_int, [_D, _i64, ctypes.c_double, ctypes.c_double,
                                                  ctypes.c_double, ctypes.c_double, _i64, _i64,
@@ -136,6 +137,23 @@ class Oracle:
         out = np.zeros(len(Q), dtype=np.uint8)
         self.lib.oracle_voronoi(_p(V), len(V), _p(Q), len(Q), _p(out, _U8))
         return out.astype(bool)
+
+    def voronoi_pieces(self, V, piece_off, piece_idx, Q, with_status: bool = False):
+        """Non-convex polygon V as the union of convex pieces (piece k is
+        V[piece_idx[piece_off[k]:piece_off[k+1]]]): inside iff the closed
+        Voronoi test of some piece says inside."""
+        V = _f64(V).reshape(-1, 2)
+        Q = _f64(Q).reshape(-1, 2)
+        off = np.ascontiguousarray(piece_off, dtype=np.int64)
+        idx = np.ascontiguousarray(piece_idx, dtype=np.int64)
+        if len(idx) == 0:
+            idx = np.zeros(1, np.int64)
+        out = np.zeros(len(Q), dtype=np.uint8)
+        rc = self.lib.oracle_voronoi_pieces(_p(V), len(V), _p(off, _I64), len(off) - 1,
+                                            _p(idx, _I64), _p(Q), len(Q), _p(out, _U8))
+        if rc == -3:
+            raise ValueError("a piece vertex index lies outside the polygon")
+        return (out.astype(bool), int(rc)) if with_status else out.astype(bool)
 
     def voronoi_raster(self, V, x0, y0, dx, dy, width, height) -> np.ndarray:
         """[height, width] bool: pixel (i, j) is the point (x0 + i dx, y0 + j dy)."""

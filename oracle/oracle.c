@@ -163,6 +163,66 @@ int oracle_voronoi(const double *V, int64_t n, const double *Q, int64_t m, uint8
 }
 
 /*
+ * Non-convex polygons as a union of convex pieces (Section 7 names the
+ * extension; the test itself, Section 4, needs a convex polygon).  The
+ * polygon's vertices V ([n][2]) are split into K convex pieces whose
+ * vertices are vertices of V: piece k is V[idx[j]] for j in
+ * [off[k], off[k+1]), in cyclic order.  Every piece gets its own generators
+ * (Algorithms 3-4) and isin[q] = 1 iff the closed Voronoi test (Algorithm 5)
+ * of at least one piece puts point q inside.  A piece of fewer than 3
+ * vertices contains no point.  Returns 0, the first nonzero generator status
+ * of a piece, or -3 when a vertex index lies outside [0, n).
+ */
+int oracle_voronoi_pieces(const double *V, int64_t n, const int64_t *off, int64_t K,
+                          const int64_t *idx, const double *Q, int64_t m, uint8_t *isin)
+{
+    int64_t total = off[K];
+    for (int64_t j = 0; j < total; ++j)
+        if (idx[j] < 0 || idx[j] >= n) return -3;
+    double *G = (double *)malloc(sizeof(double) * 2 * (size_t)(total + K + 1));
+    double *W = (double *)malloc(sizeof(double) * 2 * (size_t)(total + 1));
+    if (!G || !W) {
+        free(G);
+        free(W);
+        return -100;
+    }
+    int rc = 0;
+    for (int64_t k = 0; k < K; ++k) {
+        int64_t nk = off[k + 1] - off[k];
+        if (nk < 3) continue;
+        for (int64_t j = 0; j < nk; ++j) {
+            W[2 * j] = V[2 * idx[off[k] + j]];
+            W[2 * j + 1] = V[2 * idx[off[k] + j] + 1];
+        }
+        int r = oracle_generators(W, nk, G + 2 * (off[k] + k));
+        if (rc == 0) rc = r;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < m; ++q) {
+        double px = Q[2 * q], py = Q[2 * q + 1];
+        int in = 0;
+        if (isfinite(px) && isfinite(py)) {
+            for (int64_t k = 0; k < K && !in; ++k) {
+                int64_t nk = off[k + 1] - off[k];
+                if (nk < 3) continue;
+                const double *Pk = G + 2 * (off[k] + k);
+                double M0 = sqdist(px, py, Pk[0], Pk[1]);
+                int all = 1;
+                for (int64_t i = 0; i < nk; ++i) {
+                    double Mi = sqdist(px, py, Pk[2 * (i + 1)], Pk[2 * (i + 1) + 1]);
+                    if (!(M0 <= Mi)) all = 0;
+                }
+                if (all) in = 1;
+            }
+        }
+        isin[q] = (uint8_t)in;
+    }
+    free(G);
+    free(W);
+    return rc;
+}
+
+/*
  * Coverage raster (the graphics use of Section 1: every pixel's membership
  * decided by a point inclusion test).  Pixel (i, j) of a width x height grid
  * stands for the point (x0 + i*dx, y0 + j*dy), each coordinate one binary64

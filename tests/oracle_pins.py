@@ -16,6 +16,7 @@ import os
 import numpy as np
 
 import exact
+import polydecomp
 from oracle import pack_bits, unpack_bits
 import workloads as W
 
@@ -582,7 +583,140 @@ def pin_locate_far_rounding(o):
     assert o.locate(off, V, np.array([[2.0 ** 20, 2.0 ** 20]])).tolist() == [-1]
 
 
+
+def _pieces_exact_union(V, off, idx, p):
+    """Exact union-of-pieces label: some piece's exact Voronoi predicate
+    (Eq. 1 in rationals) holds."""
+    for k in range(len(off) - 1):
+        piece = [tuple(V[i]) for i in idx[off[k]:off[k + 1]]]
+        if exact.voronoi(piece, p):
+            return True
+    return False
+
+
+def pin_pieces_L_shape_exact(o):
+    """L-shaped polygon (a collinear vertex at (0, 2) closes the cut) split
+    into a 4 x 2 rectangle and a 2 x 2 square: every centroid, generator and
+    squared distance is dyadic, so on a dyadic grid the float64 union of the
+    two closed Voronoi tests is exactly the closed L: the points with
+    0 <= x <= 4, 0 <= y <= 2 or 0 <= x <= 2, 0 <= y <= 4 (boundary and cut
+    included)."""
+    V = np.array([[0, 0], [4, 0], [4, 2], [2, 2], [2, 4], [0, 4], [0, 2]], dtype=np.float64)
+    off = np.array([0, 5, 9], np.int64)
+    idx = np.array([0, 1, 2, 3, 6, 6, 3, 4, 5], np.int64)
+    g = np.arange(-4, 21) / 4.0
+    X, Y = np.meshgrid(g, g)
+    Q = np.stack([X.ravel(), Y.ravel()], 1)
+    got = o.voronoi_pieces(V, off, idx, Q)
+    x, y = Q[:, 0], Q[:, 1]
+    want = ((x >= 0) & (x <= 4) & (y >= 0) & (y <= 2)) | ((x >= 0) & (x <= 2) & (y >= 0) & (y <= 4))
+    assert np.array_equal(got, want), int((got != want).sum())
+    assert int(want.sum()) == 17 * 9 + 9 * 8
+    # piece order does not matter; a reversed index list (other orientation) neither
+    off2 = np.array([0, 4, 9], np.int64)
+    idx2 = np.array([5, 4, 3, 6, 6, 3, 2, 1, 0], np.int64)
+    assert np.array_equal(o.voronoi_pieces(V, off2, idx2, Q), want)
+
+
+def pin_pieces_exact_rational(o):
+    """Small-integer simple non-convex polygons, decomposed exactly (ear
+    clipping, merged and unmerged): the exact union of the pieces' closed
+    Voronoi predicates is the closed polygon (exact brute force), and the
+    float64 label equals it wherever no piece's exact largest margin lies
+    within float64 reach of zero."""
+    rng = _rng(21)
+    checked = 0
+    for t in range(8):
+        V = polydecomp.star_polygon(rng, 7 + t % 5, r_lo=0.35, r_hi=1.0, integer_scale=9)
+        if t % 2:
+            V = V[::-1].copy()
+        off, idx = polydecomp.decompose(V, merged=t % 3 != 0)
+        Vl = [tuple(v) for v in V.tolist()]
+        pts = rng.integers(-44, 45, size=(120, 2)) / 4.0
+        mids = [0.5 * (V[i] + V[i - 1]) for i in range(len(V))]
+        diag = [0.5 * (V[idx[off[k] + a]] + V[idx[off[k] + (a + 1) % (off[k + 1] - off[k])]])
+                for k in range(len(off) - 1) for a in range(off[k + 1] - off[k])]
+        pts = np.concatenate([pts, V, np.array(mids), np.array(diag)])
+        got = o.voronoi_pieces(V, off, idx, pts)
+        gens = []
+        for k in range(len(off) - 1):
+            piece = [Vl[i] for i in idx[off[k]:off[k + 1]]]
+            gens.append((piece, exact.generators(piece)))
+        for q, p in enumerate(pts.tolist()):
+            ex = any(exact.voronoi(pc, p, Pe) for pc, Pe in gens)
+            assert ex == polydecomp.closed_contains(Vl, p), (t, p)
+            near = False
+            for pc, Pe in gens:
+                mm = max(exact.voronoi_margins(Pe, p))
+                r2 = max((p[0] - float(gx)) ** 2 + (p[1] - float(gy)) ** 2 for gx, gy in Pe)
+                if abs(float(mm)) <= 1e-13 * r2 + 1e-12 * (np.abs(V).max() + abs(p[0]) + abs(p[1]) + 1) ** 2:
+                    near = True
+            if not near:
+                assert bool(got[q]) == ex, (t, p)
+                checked += 1
+    assert checked > 800
+
+
+def pin_pieces_single_and_fan(o):
+    """A convex polygon given as one piece is Algorithm 5 itself (labels
+    bit-identical to the convex test); split into a fan of triangles from
+    vertex 0 it has the same labels away from the fan's diagonals."""
+    rng = _rng(22)
+    for t in range(4):
+        n = 5 + 4 * t
+        V = W.circle_polygon(n, 1.0, rng.uniform(-0.2, 0.2, 2), rng)
+        Q = rng.uniform(-1.3, 1.3, (20000, 2))
+        one = o.voronoi_pieces(V, np.array([0, n]), np.arange(n), Q)
+        assert np.array_equal(one, o.voronoi(V, Q))
+        off = 3 * np.arange(n - 1)
+        idx = np.array([[0, i, i + 1] for i in range(1, n - 1)]).ravel()
+        fan = o.voronoi_pieces(V, off, idx, Q)
+        segs = [(V[0], V[i]) for i in range(2, n - 1)] + [(V[i - 1], V[i]) for i in range(n)]
+        d = np.full(len(Q), np.inf)
+        for a, b in segs:
+            e = b - a
+            dd = np.abs(e[0] * (Q[:, 1] - a[1]) - e[1] * (Q[:, 0] - a[0])) / np.hypot(*e)
+            d = np.minimum(d, dd)
+        far = d > 1e-9
+        assert np.array_equal(fan[far], one[far])
+        assert far.sum() > 19000
+
+
+def pin_pieces_agree_with_ray_crossing(o):
+    """Random star-shaped non-convex polygons (float vertices): away from
+    every edge and every diagonal of the decomposition (1e-9), the union of
+    the pieces' Voronoi tests equals ray crossing (Algorithm 1, which
+    handles simple polygons directly)."""
+    rng = _rng(23)
+    for t in range(6):
+        n = int(rng.integers(8, 40))
+        V = polydecomp.star_polygon(rng, n, center=tuple(rng.uniform(-5, 5, 2)))
+        if t % 2:
+            V = V[::-1].copy()
+        off, idx = polydecomp.decompose(V, merged=t % 3 != 2)
+        c = V.mean(0)
+        Q = c + rng.uniform(-1.2, 1.2, (20000, 2))
+        got = o.voronoi_pieces(V, off, idx, Q)
+        ray = o.ray_crossing(V, Q)
+        d = np.full(len(Q), np.inf)
+        for k in range(len(off) - 1):
+            pc = idx[off[k]:off[k + 1]]
+            for a_, b_ in zip(pc, np.roll(pc, -1)):
+                a, b = V[a_], V[b_]
+                e = b - a
+                t_ = np.clip(((Q - a) @ e) / (e @ e), 0, 1)
+                dd = np.hypot(*(Q - (a + t_[:, None] * e)).T)
+                d = np.minimum(d, dd)
+        far = d > 1e-9
+        assert np.array_equal(got[far], ray[far]), int((got[far] != ray[far]).sum())
+        assert 0.1 < got.mean() < 0.7
+
+
 ALL_PINS = [
+    pin_pieces_L_shape_exact,
+    pin_pieces_exact_rational,
+    pin_pieces_single_and_fan,
+    pin_pieces_agree_with_ray_crossing,
     pin_square_and_triangle,
     pin_raster_exact,
     pin_raster_area,

@@ -61,6 +61,13 @@ MUTANTS = [
      "\n            if (i == 0 || d <= best) {"),
     ("grad_argmin_tie_last", "\n                if (i == 0 || d < best) {",
      "\n                if (i == 0 || d <= best) {"),
+    ("pieces_first_decides", "                if (all) in = 1;", "                in = all;\n                break;"),
+    ("pieces_skip_last", "for (int64_t k = 0; k < K && !in; ++k) {",
+     "for (int64_t k = 0; k + 1 < K && !in; ++k) {"),
+    ("pieces_generator_offset", "const double *Pk = G + 2 * (off[k] + k);",
+     "const double *Pk = G + 2 * off[k];"),
+    ("pieces_gather_index", "W[2 * j] = V[2 * idx[off[k] + j]];", "W[2 * j] = V[2 * (off[k] + j)];"),
+    ("pieces_open", "if (!(M0 <= Mi)) all = 0;", "if (!(M0 < Mi)) all = 0;"),
     ("cost_state_off_by_one", "if (state) state[j] = (int32_t)arg;",
      "if (state) state[j] = (int32_t)arg + 1;"),
 ]
