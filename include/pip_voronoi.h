@@ -362,6 +362,33 @@ pip_status pip_voronoi_batched(pip_ctx ctx, int32_t P, const int64_t *vtx_off, c
                                size_t workspace_bytes, const pip_batched_config *config,
                                hipStream_t stream);
 
+/*
+ * pip_voronoi_batched for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, labels and status without the workspace.
+ * The polygon tables and chunk descriptors go to a static device array of
+ * the library, PIP_BATCHED_SCRATCH_BYTES bytes on every GPU the library
+ * runs on, held until the process ends; the call allocates nothing.
+ *   Limit: a request whose pip_voronoi_batched_workspace_bytes(P,
+ *   total_vertices, total_points) exceeds PIP_BATCHED_SCRATCH_BYTES returns
+ *   PIP_EUNSUPPORTED (32 MiB holds about 9e8 points over 4096 polygons of
+ *   up to 32 edges); such a batch needs pip_voronoi_batched with a workspace.
+ *   Sharing: every call on one GPU uses that GPU's one array, whose contents
+ *   are those of the last call (every word a launch reads is written earlier
+ *   in the same launch).  Calls that overlap on one GPU -- on different
+ *   streams, or from several host threads without ordering -- race on the
+ *   array and give wrong labels; serialise them (one stream, or events).
+ *   Errors: as pip_voronoi_batched; PIP_EHIP if the array's device address
+ *   could not be obtained when the context was created.
+ */
+#define PIP_BATCHED_SCRATCH_BYTES ((size_t)32 << 20)
+pip_status pip_voronoi_batched_noalloc(pip_ctx ctx, int32_t P, const int64_t *vtx_off,
+                                       const double *V, int64_t total_vertices,
+                                       const int64_t *pt_off, const float *Q,
+                                       int64_t total_points, const int64_t *lbl_word_off,
+                                       uint32_t *labels, int32_t *status,
+                                       const pip_batched_config *config, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Plans: a batched request bound to its buffers, with a workspace the plan
  * allocates (pip_plan_create_batched is the only call that allocates device

@@ -16,6 +16,7 @@ PIP_OPT_COST_CULL = 3
 PIP_OPT_ALLPAIRS_PAIR = 4
 PIP_OPT_COST_PAIR = 5
 PIP_OPT_RADIAL_MIN_EDGES = 6
+PIP_BATCHED_SCRATCH_BYTES = 32 << 20  # static scratch array of pip_voronoi_batched_noalloc
 
 STATUS_NAMES = {
     0: "PIP_OK", 1: "PIP_EINVAL", 2: "PIP_EDEGENERATE", 3: "PIP_ENONCONVEX", 4: "PIP_EHIP",
@@ -71,6 +72,8 @@ SIGNATURES = {
     "pip_voronoi_batched_workspace_bytes": (_c.c_size_t, [_i32, _i64, _i64]),
     "pip_voronoi_batched": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                                    _c.c_size_t, _vp, _vp]),
+    "pip_voronoi_batched_noalloc": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp,
+                                           _vp, _vp, _vp]),
     "pip_plan_create_batched": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp,
                                        _c.POINTER(_vp)]),
     "pip_plan_autotune": (_int, [_vp, _i32, _vp]),

@@ -287,6 +287,24 @@ def pip_voronoi_batched(vtx_off, V, pt_off, Q, lbl_word_off=None, labels=None, s
     return a.labels, a.lbl, a.status
 
 
+def pip_voronoi_batched_noalloc(vtx_off, V, pt_off, Q, lbl_word_off=None, labels=None,
+                                status=None, config=None):
+    """pip_voronoi_batched on the library's static scratch array (no
+    workspace; the library call allocates nothing).  Pass ``labels`` and
+    ``status`` (and ``lbl_word_off``) to keep this wrapper from allocating
+    them.  Returns (labels, lbl_word_off, status)."""
+    a = _BatchedArgs(vtx_off, V, pt_off, Q, lbl_word_off, labels, status)
+    cfg = None
+    if config is not None:
+        cfg = BatchedConfig(int(config[0]), int(config[1]))
+    ctx = context(a.device)
+    s = _lib().pip_voronoi_batched_noalloc(ctx, *a.ptrs(),
+                                           ctypes.byref(cfg) if cfg is not None else None,
+                                           _stream(a.device))
+    _check(s, "pip_voronoi_batched_noalloc", ctx)
+    return a.labels, a.lbl, a.status
+
+
 class BatchedPlan:
     """Autotuned, graph-captured batched launch bound to fixed buffers."""
 

@@ -25,6 +25,8 @@ struct pip_ctx_s {
     int cost_cull = 0;             // skip (pose, wave) pairs of the collision cost likewise
     int allpairs_pair = 0;         // antipodal edge pairs for centrally symmetric polygons
     int cost_pair = 0;             // the same for the collision cost's footprint
+    void* scratch = nullptr;       // this device's copy of the static scratch array (no-alloc calls)
+    hipError_t scratch_err = hipSuccess;  // why `scratch` is null, if it is
 };
 
 // A plan: one batched request bound to its buffers, its own workspace, the
@@ -124,6 +126,37 @@ struct DeviceGuard {
 };
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Workspace of pip_voronoi_batched_noalloc.  Every GPU the library runs on
+// holds its own copy at its own address until the process ends.  In host
+// code `scratch` is only a host-side stand-in: kernels, copies and fills take
+// the device address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[PIP_BATCHED_SCRATCH_BYTES];
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current.
+hipError_t scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
 
 pip_status check_polygon(const double* V, int32_t n) {
     if (!V) return fail(PIP_EINVAL, "V is NULL");
@@ -273,6 +306,11 @@ pip_status pip_create(int hip_device, pip_ctx* out) {
     if (!c) return fail(PIP_ENOMEM, "out of host memory");
     c->device = hip_device;
     c->cu_count = cus;
+    {  // this device's scratch array (only pip_voronoi_batched_noalloc needs it)
+        DeviceGuard g(hip_device);
+        c->scratch_err = g.err != hipSuccess ? g.err : scratch_address(hip_device, &c->scratch);
+        if (c->scratch_err != hipSuccess) c->scratch = nullptr;
+    }
     *out = c;
     return PIP_OK;
 }
@@ -516,6 +554,34 @@ pip_status pip_voronoi_batched(pip_ctx ctx, int32_t P, const int64_t* vtx_off, c
     if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
     const pipdev::BatchedDev D = make_dev(P, vtx_off, V, total_vertices, pt_off, Q, total_points,
                                           lbl_word_off, labels, status, workspace,
+                                          ctx->radial_min_edges);
+    return launch_batched_cfg(ctx, D, c, stream);
+}
+
+pip_status pip_voronoi_batched_noalloc(pip_ctx ctx, int32_t P, const int64_t* vtx_off,
+                                       const double* V, int64_t total_vertices,
+                                       const int64_t* pt_off, const float* Q,
+                                       int64_t total_points, const int64_t* lbl_word_off,
+                                       uint32_t* labels, int32_t* status,
+                                       const pip_batched_config* config, hipStream_t stream) {
+    pip_status s = check_batched(ctx, P, vtx_off, V, total_vertices, pt_off, Q, total_points,
+                                 lbl_word_off, labels, status);
+    if (s != PIP_OK) return s;
+    if (P == 0) return PIP_OK;
+    const size_t need = pip_voronoi_batched_workspace_bytes(P, total_vertices, total_points);
+    if (need > PIP_BATCHED_SCRATCH_BYTES)
+        return fail(PIP_EUNSUPPORTED,
+                    "the batch needs %zu workspace bytes, more than the %zu of the library's "
+                    "scratch array; use pip_voronoi_batched with a workspace",
+                    need, (size_t)PIP_BATCHED_SCRATCH_BYTES);
+    if (!ctx->scratch)
+        return hip_fail(ctx->scratch_err, "device address of the scratch array (at pip_create)");
+    pip_batched_config c;
+    if ((s = resolve_config(ctx, config, &c)) != PIP_OK) return s;
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    const pipdev::BatchedDev D = make_dev(P, vtx_off, V, total_vertices, pt_off, Q, total_points,
+                                          lbl_word_off, labels, status, ctx->scratch,
                                           ctx->radial_min_edges);
     return launch_batched_cfg(ctx, D, c, stream);
 }
