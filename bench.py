@@ -420,6 +420,39 @@ def run_extras(P, W, torch, stream, check):
     out["locate"] = e
     print("[bench] locate done", file=sys.stderr, flush=True)
 
+    # non-convex polygon: a 64-vertex star polygon as the union of the convex
+    # pieces of the library's decomposition, 2^27 float32 points in
+    # [-1.5, 1.5]^2 (1% within 1e-6 of an edge); every point meets every piece
+    Vn = W.star_polygon(64)
+    off_n, idx_n = P.convex_decompose(Vn, 64)
+    mn = 1 << 27
+    Qn = W.streaming_points(Vn, mn, seed_salt=77)
+    Vnt, Qnt = torch.from_numpy(Vn).to(dev), torch.from_numpy(Qn).to(dev)
+    offt, idxt = torch.from_numpy(off_n).to(dev), torch.from_numpy(idx_n).to(dev)
+    labn = torch.empty((mn + 31) // 32, dtype=torch.int32, device=dev)
+    stn = torch.empty(len(off_n) - 1, dtype=torch.int32, device=dev)
+    wsn = torch.empty(max(P.pieces_workspace_bytes(len(off_n) - 1, len(idx_n)), 256),
+                      dtype=torch.uint8, device=dev)
+    ms_n = _time(torch, stream, lambda: P.pip_voronoi_pieces(Vnt, offt, idxt, Qnt, labels=labn,
+                                                             status=stn, workspace=wsn), reps=10)
+    rows = int(sum(((off_n[k + 1] - off_n[k] + 3) // 4) * 4 for k in range(len(off_n) - 1)))
+    tfl = 4.0 * len(idx_n) * mn / (ms_n * 1e-3) / 1e12
+    e = {"n": len(Vn), "pieces": len(off_n) - 1, "piece_edges": int(len(idx_n)),
+         "padded_rows": rows, "points": mn, "ms": round(ms_n, 4),
+         "gtests_per_s": round(mn / ms_n / 1e6, 2),
+         "fp32_tflops_piece_edges": round(tfl, 2),
+         "fp32_frac": round(tfl / FP32_VALU_PEAK_TFLOPS, 4),
+         "hbm_frac": round(BYTES_PER_TEST * mn / (ms_n * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if check:
+        got = unpack_bits(labn.cpu().numpy().view(np.uint32), mn)
+        sel = np.sort(rng.choice(mn, 2_000_000, replace=False))
+        want = o.voronoi_pieces(Vn, off_n, idx_n, Qn[sel].astype(np.float64))
+        e["mismatches_2M_sample"] = int((got[sel] != want).sum())
+    out["nonconvex"] = e
+    del Qnt, Vnt, labn, wsn
+    torch.cuda.empty_cache()
+    print("[bench] non-convex done", file=sys.stderr, flush=True)
+
     # differentiable cost: 1024 trajectories x 64 poses x 65,536 points
     F32 = F.astype(np.float32)
     Qd = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)

@@ -390,6 +390,69 @@ pip_status pip_voronoi_batched_noalloc(pip_ctx ctx, int32_t P, const int64_t *vt
                                        const pip_batched_config *config, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Non-convex polygons (the extension Section 7 names; the test of Section 4
+ * needs a convex polygon): a simple polygon split into convex pieces whose
+ * vertices are vertices of the polygon.  Each piece gets its own generators
+ * (Section 3, Algorithms 3-4) and a point is inside iff the closed Voronoi
+ * test (Algorithm 5, binary64) of at least one piece puts it inside.  In
+ * exact arithmetic the union of the closed pieces is the closed polygon; in
+ * binary64 the label can depend on the decomposition within rounding reach
+ * of the pieces' boundaries, so it is always "the union of these pieces".
+ *
+ * pip_convex_decompose: one decomposition, on the host (no device work):
+ *   ear clipping with exact orientation signs, then removal of every
+ *   diagonal whose two sides merge into a piece that is strictly convex at
+ *   both ends of the diagonal and has at most max_piece_vertices vertices
+ *   (Hertel-Mehlhorn: at most four times the fewest convex pieces).  Vertices
+ *   collinear with both neighbours may be left out of every piece (they lie
+ *   on an edge of a piece).
+ *   V            [n][2] HOST binary64, a simple polygon, either orientation,
+ *                3 <= n <= 2^20 (self-intersection is not detected in
+ *                general; an input with no ear left returns PIP_EINVAL).
+ *   max_piece_vertices  3..PIP_MAX_EDGES.
+ *   piece_off    HOST int32 [n - 1]: receives K + 1 offsets.
+ *   piece_idx    HOST int32 [3 (n - 2)]: receives the pieces' vertex
+ *                indices, each piece in the polygon's cyclic order.
+ *   num_pieces   receives K; idx_count receives piece_off[K].
+ *   Errors: PIP_EINVAL (NULL pointer, n out of range, non-finite vertex,
+ *   zero area, not simple).  Runs on the calling thread; thread-safe.
+ *
+ * pip_voronoi_pieces: labels of m points against the union of K pieces.
+ *   V            [n][2] binary64 vertices (device).
+ *   piece_off    [K + 1] int32 (device), non-decreasing, piece_off[K] =
+ *                idx_count; piece_idx [idx_count] int32 (device), values in
+ *                [0, n).  A piece of 3..PIP_MAX_EDGES vertices, in cyclic
+ *                order (either orientation).
+ *   Q, qdt, m, labels  as pip_voronoi.
+ *   status       optional [K] int32 (device): per piece, PIP_OK or the
+ *                generator status of pip_voronoi (a non-convex piece gives
+ *                PIP_ENONCONVEX and still takes part with Algorithm 5's
+ *                answer for it); PIP_EINVAL for a piece with fewer than 3
+ *                vertices or an index / offset out of range, PIP_EUNSUPPORTED
+ *                for more than PIP_MAX_EDGES vertices: such a piece contains
+ *                no point.
+ *   workspace    device, 256-byte aligned, pip_voronoi_pieces_workspace_bytes
+ *                (K, idx_count) bytes, caller-owned, not shared by
+ *                overlapping calls.
+ *   The piece tables (32 bytes per piece plus 16 per row, rows = idx_count
+ *   + 3 K) live in each workgroup's LDS: at most PIP_PIECES_MAX_TABLE_BYTES,
+ *   else PIP_EUNSUPPORTED.  Margins are screened in float32 in one frame
+ *   shared by the pieces (origin fl32(v_0)) with the proven band of
+ *   pip_voronoi; undecided points are re-decided in binary64 against every
+ *   piece.
+ */
+#define PIP_PIECES_MAX_TABLE_BYTES 65536
+pip_status pip_convex_decompose(const double *V, int32_t n, int32_t max_piece_vertices,
+                                int32_t *piece_off, int32_t *piece_idx, int32_t *num_pieces,
+                                int64_t *idx_count);
+size_t pip_voronoi_pieces_workspace_bytes(int32_t K, int64_t idx_count);
+pip_status pip_voronoi_pieces(pip_ctx ctx, const double *V, int64_t n, int32_t K,
+                              const int32_t *piece_off, const int32_t *piece_idx,
+                              int64_t idx_count, const void *Q, pip_dtype qdt, int64_t m,
+                              uint32_t *labels, int32_t *status, void *workspace,
+                              size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Plans: a batched request bound to its buffers, with a workspace the plan
  * allocates (pip_plan_create_batched is the only call that allocates device
  * memory, besides pip_plan_autotune's comparison buffers), a tile shape

@@ -74,6 +74,10 @@ SIGNATURES = {
                                    _c.c_size_t, _vp, _vp]),
     "pip_voronoi_batched_noalloc": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp,
                                            _vp, _vp, _vp]),
+    "pip_convex_decompose": (_int, [_vp, _i32, _i32, _vp, _vp, _c.POINTER(_i32), _c.POINTER(_i64)]),
+    "pip_voronoi_pieces_workspace_bytes": (_c.c_size_t, [_i32, _i64]),
+    "pip_voronoi_pieces": (_int, [_vp, _vp, _i64, _i32, _vp, _vp, _i64, _vp, _int, _i64, _vp, _vp,
+                                  _vp, _c.c_size_t, _vp]),
     "pip_plan_create_batched": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _vp, _vp,
                                        _c.POINTER(_vp)]),
     "pip_plan_autotune": (_int, [_vp, _i32, _vp]),

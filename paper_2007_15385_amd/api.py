@@ -546,3 +546,56 @@ def pip_voronoi_allpairs(V, Q, labels=None, counts=None, status=None, workspace=
                                     workspace.data_ptr(), workspace.numel(), _stream(d))
     _check(s, "pip_voronoi_allpairs", ctx)
     return labels, counts[:Pn], status[:Pn]
+
+
+# -- non-convex polygons: union of convex pieces ------------------------------
+def convex_decompose(V, max_piece_vertices: int = 64):
+    """Convex pieces of a simple polygon (the library's host routine):
+    ``V`` is a host float64 array [n, 2]; returns (piece_off, piece_idx) as
+    int32 numpy arrays (K + 1 offsets, vertex indices of each piece)."""
+    import numpy as np
+    Vn = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1, 2))
+    n = Vn.shape[0]
+    if n < 3:
+        raise ValueError("a polygon needs at least 3 vertices")
+    off = np.zeros(max(n - 1, 1), dtype=np.int32)
+    idx = np.zeros(max(3 * (n - 2), 1), dtype=np.int32)
+    K = ctypes.c_int32()
+    cnt = ctypes.c_int64()
+    s = _lib().pip_convex_decompose(Vn.ctypes.data, n, int(max_piece_vertices), off.ctypes.data,
+                                    idx.ctypes.data, ctypes.byref(K), ctypes.byref(cnt))
+    _check(s, "pip_convex_decompose", None)
+    return off[:K.value + 1].copy(), idx[:cnt.value].copy()
+
+
+def pieces_workspace_bytes(K: int, idx_count: int) -> int:
+    return int(_lib().pip_voronoi_pieces_workspace_bytes(int(K), int(idx_count)))
+
+
+def pip_voronoi_pieces(V, piece_off, piece_idx, Q, labels=None, status=None, workspace=None):
+    """Labels of Q against the union of the convex pieces (device int32
+    piece_off [K+1] and piece_idx) of polygon V; returns (labels, status)."""
+    V = _polygon(V)
+    Q, qdt = _points(Q)
+    d = _dev(V)
+    for t, name in ((piece_off, "piece_off"), (piece_idx, "piece_idx")):
+        if t.dtype != torch.int32 or t.dim() != 1 or not t.is_contiguous() or _dev(t) != d:
+            raise ValueError(f"{name} must be a contiguous int32 vector on V's device")
+    K = piece_off.numel() - 1
+    cnt = piece_idx.numel()
+    m = Q.shape[0]
+    if labels is None:
+        labels = torch.zeros(max(num_label_words(m), 1), dtype=torch.int32, device=V.device)
+    if status is None:
+        status = torch.zeros(max(K, 1), dtype=torch.int32, device=V.device)
+    need = pieces_workspace_bytes(K, cnt)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=V.device)
+    ctx = context(d)
+    s = _lib().pip_voronoi_pieces(ctx, V.data_ptr(), V.shape[0], K, piece_off.data_ptr(),
+                                  piece_idx.data_ptr() if cnt else None, cnt,
+                                  Q.data_ptr() if m else None, qdt, m, labels.data_ptr(),
+                                  status.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                  _stream(d))
+    _check(s, "pip_voronoi_pieces", ctx)
+    return labels, status

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 #include "pip_voronoi.h"
@@ -584,6 +585,91 @@ pip_status pip_voronoi_batched_noalloc(pip_ctx ctx, int32_t P, const int64_t* vt
                                           lbl_word_off, labels, status, ctx->scratch,
                                           ctx->radial_min_edges);
     return launch_batched_cfg(ctx, D, c, stream);
+}
+
+// ---------------------------------------------------------------------------
+// non-convex polygons: union of convex pieces
+// ---------------------------------------------------------------------------
+size_t pip_voronoi_pieces_workspace_bytes(int32_t K, int64_t idx_count) {
+    if (K < 1 || idx_count < 0) return 0;
+    pipdev::PiecesLayout L;
+    return pipdev::pieces_workspace_layout(K, idx_count, &L);
+}
+
+pip_status pip_voronoi_pieces(pip_ctx ctx, const double* V, int64_t n, int32_t K,
+                              const int32_t* piece_off, const int32_t* piece_idx,
+                              int64_t idx_count, const void* Q, pip_dtype qdt, int64_t m,
+                              uint32_t* labels, int32_t* status, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (!V || !aligned(V, 8)) return fail(PIP_EINVAL, "V is NULL or not 8-byte aligned");
+    if (n < 3 || n > (int64_t(1) << 30)) return fail(PIP_EINVAL, "n = %lld is out of range", (long long)n);
+    if (K < 1) return fail(PIP_EINVAL, "K = %d: at least one piece", (int)K);
+    if (idx_count < 0) return fail(PIP_EINVAL, "idx_count is negative");
+    if (!piece_off || !aligned(piece_off, 4)) return fail(PIP_EINVAL, "piece_off is NULL or misaligned");
+    if (idx_count > 0 && (!piece_idx || !aligned(piece_idx, 4)))
+        return fail(PIP_EINVAL, "piece_idx is NULL or misaligned");
+    pip_status s = check_points(Q, qdt, m);
+    if (s != PIP_OK) return s;
+    if (m > 0 && (!labels || !aligned(labels, 4))) return fail(PIP_EINVAL, "labels is NULL or misaligned");
+    if (status && !aligned(status, 4)) return fail(PIP_EINVAL, "status is not 4-byte aligned");
+    const size_t lds = pipdev::pieces_lds_bytes(K, idx_count);
+    if (lds > PIP_PIECES_MAX_TABLE_BYTES)
+        return fail(PIP_EUNSUPPORTED,
+                    "%d pieces with %lld vertex entries need %zu bytes of piece tables "
+                    "(limit %d): split the polygon", (int)K, (long long)idx_count, lds,
+                    (int)PIP_PIECES_MAX_TABLE_BYTES);
+    const size_t need = pip_voronoi_pieces_workspace_bytes(K, idx_count);
+    if (!workspace || !aligned(workspace, 256) || workspace_bytes < need)
+        return fail(PIP_EINVAL, "workspace of %zu bytes (256-byte aligned) needed, got %zu", need,
+                    workspace_bytes);
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    int per_cu = 0;
+    if (pipdev::pieces_max_blocks_per_cu((int)qdt, lds, &per_cu) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    pipdev::PiecesLaunch A;
+    A.V = V;
+    A.n = n;
+    A.K = K;
+    A.off = piece_off;
+    A.idx = piece_idx;
+    A.idx_count = idx_count;
+    A.Q = Q;
+    A.qdt = (int)qdt;
+    A.m = m;
+    A.labels = labels;
+    A.status = status;
+    A.ws = workspace;
+    A.max_blocks = per_cu * ctx->cu_count;
+    // recheck queue codes hold 2^23 chunks per wave
+    const int64_t waves = 4 * (int64_t)A.max_blocks;
+    if (((m + 511) / 512 + waves - 1) / waves >= (int64_t(1) << 23))
+        return fail(PIP_EUNSUPPORTED, "m = %lld points is too large for one launch", (long long)m);
+    hipError_t e = pipdev::launch_pieces(A, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
+pip_status pip_convex_decompose(const double* V, int32_t n, int32_t max_piece_vertices,
+                                int32_t* piece_off, int32_t* piece_idx, int32_t* num_pieces,
+                                int64_t* idx_count) {
+    if (!V || !piece_off || !piece_idx || !num_pieces || !idx_count)
+        return fail(PIP_EINVAL, "a pointer argument is NULL");
+    if (n < 3 || n > (1 << 20)) return fail(PIP_EINVAL, "n = %d is out of range [3, 2^20]", (int)n);
+    if (max_piece_vertices < 3 || max_piece_vertices > PIP_MAX_EDGES)
+        return fail(PIP_EINVAL, "max_piece_vertices must lie in [3, %d]", PIP_MAX_EDGES);
+    std::vector<int32_t> off, idx;
+    const int r = pipdev::convex_decompose_host(V, n, max_piece_vertices, off, idx);
+    if (r == 1) return fail(PIP_EINVAL, "non-finite vertex or zero area");
+    if (r == 2) return fail(PIP_EINVAL, "the polygon is not simple (no ear left to cut)");
+    if (r != 0 || off.size() > (size_t)n - 1 || idx.size() > 3 * (size_t)(n - 2))
+        return fail(PIP_EINVAL, "decomposition failed");
+    for (size_t i = 0; i < off.size(); ++i) piece_off[i] = off[i];
+    for (size_t i = 0; i < idx.size(); ++i) piece_idx[i] = idx[i];
+    *num_pieces = (int32_t)off.size() - 1;
+    *idx_count = (int64_t)idx.size();
+    return PIP_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -196,8 +196,11 @@ __device__ inline int validate_polygon(const double2* vtx, int n, int lane, doub
 // when the margin comes from a matrix-core multiply-add (exact products, up to
 // two roundings of the sum, measured <= 1.96 u of the sum of |terms|, bounded
 // here by 4 u, plus the same coefficient and coordinate rounding).
+// given_frame: the local frame is (gox, goy) instead (one frame shared by
+// several polygons); the band holds for any float32 origin.
 __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool global_frame = false,
-                                       double f32_factor = 4.05) {
+                                       double f32_factor = 4.05, bool given_frame = false,
+                                       float gox = 0.0f, float goy = 0.0f) {
     const int n = S.n;
     double g0x, g0y, area, gx, gy, den;
     derive_generators(S.vtx, n, lane, &g0x, &g0y, &area, &gx, &gy, &den);
@@ -207,8 +210,8 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
 
     // Local frame o = fl32(p_0), or the global frame (o = 0, so X = p_x
     // exactly); the band below holds for either.
-    const float ox = global_frame ? 0.0f : (float)g0x;
-    const float oy = global_frame ? 0.0f : (float)g0y;
+    const float ox = given_frame ? gox : global_frame ? 0.0f : (float)g0x;
+    const float oy = given_frame ? goy : global_frame ? 0.0f : (float)g0y;
     const double dox = (double)ox, doy = (double)oy;
     const int i = lane < n ? lane : 0;
     const double d2x = g0x - dox, d2y = g0y - doy;

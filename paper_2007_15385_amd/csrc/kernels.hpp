@@ -87,6 +87,34 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws, int cull,
                            int pair, hipStream_t stream);
+// Non-convex polygon as a union of convex pieces (pieces.hip).
+struct PiecesLayout {
+    size_t hdr, rows, gens;
+};
+struct PiecesLaunch {
+    const double* V;      // device [n][2]
+    int64_t n;
+    int K;                // pieces
+    const int32_t* off;   // device [K+1]
+    const int32_t* idx;   // device [idx_count]
+    int64_t idx_count;
+    const void* Q;        // device [m][2] float32 or binary64
+    int qdt;
+    int64_t m;
+    uint32_t* labels;
+    int32_t* status;      // device [K] or null
+    void* ws;
+    int max_blocks;
+};
+size_t pieces_workspace_layout(int64_t K, int64_t idx_count, PiecesLayout* L);
+size_t pieces_lds_bytes(int64_t K, int64_t idx_count);
+hipError_t pieces_max_blocks_per_cu(int qdt, size_t lds, int* out);
+hipError_t launch_pieces(const PiecesLaunch& A, hipStream_t stream);
+}  // namespace pipdev
+#include <vector>
+namespace pipdev {
+int convex_decompose_host(const double* V, int n, int max_piece, std::vector<int32_t>& off,
+                          std::vector<int32_t>& idx);
 // Point-location index: one record per polygon (64 bytes), the grid.
 struct alignas(16) LocRec {
     float ox, oy;          // float32 local origin

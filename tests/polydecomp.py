@@ -162,14 +162,12 @@ def closed_contains(V, p) -> bool:
 
 
 def star_polygon(rng, n, r_lo=0.4, r_hi=1.0, center=(0.0, 0.0), integer_scale=None):
-    """Simple polygon, star-shaped about `center`: sorted distinct angles
-    (every gap below pi), random radii.  With integer_scale, integer
+    """Simple polygon, star-shaped about `center`: increasing angles, one
+    per sector of 2 pi / n (n >= 3, so every gap is below pi), random radii.  With integer_scale, integer
     vertices whose exact angular order is strictly increasing."""
     for _ in range(1000):
-        th = np.sort(rng.uniform(0, 2 * np.pi, n))
-        gaps = np.diff(np.concatenate([th, [th[0] + 2 * np.pi]]))
-        if gaps.max() >= 0.9 * np.pi or gaps.min() < 1e-3:
-            continue
+        # one angle per sector of 2 pi / n, away from the sector ends
+        th = (np.arange(n) + rng.uniform(0.1, 0.9, n)) * (2 * np.pi / n) + rng.uniform(0, 2 * np.pi)
         r = rng.uniform(r_lo, r_hi, n)
         V = np.stack([center[0] + r * np.cos(th), center[1] + r * np.sin(th)], 1)
         if integer_scale is None:

@@ -111,6 +111,16 @@ def streaming_points(V: np.ndarray, m: int, near_frac: float = 0.01, near_offset
     return Q
 
 
+def star_polygon(n: int = 64, r_lo: float = 0.4, r_hi: float = 1.0, seed_salt: int = 0) -> np.ndarray:
+    """Simple non-convex polygon (float64 [n][2], counter-clockwise), star-
+    shaped about the origin: one angle per sector of 2 pi / n, away from the
+    sector ends, radii uniform in [r_lo, r_hi]."""
+    rng = rng_for(7, 1000 * n + seed_salt)
+    th = (np.arange(n) + rng.uniform(0.1, 0.9, n)) * (2 * np.pi / n)
+    r = rng.uniform(r_lo, r_hi, n)
+    return np.stack([r * np.cos(th), r * np.sin(th)], 1)
+
+
 # ---------------------------------------------------------------------------
 # uneven batch: thousands of polygons, each with its own point set
 # ---------------------------------------------------------------------------
