@@ -539,6 +539,29 @@ pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double 
                                 int64_t m, uint32_t *labels, int32_t *counts, int32_t *status,
                                 void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/*
+ * pip_voronoi_allpairs_csr: the same all-pairs test for P convex polygons of
+ * uneven vertex counts (Section 4, Algorithm 5 per polygon; Section 1's
+ * collision check against many different shapes).
+ *   vtx_off  [P+1] int64 (device), non-decreasing: polygon k has vertices
+ *            V[vtx_off[k] .. vtx_off[k+1]) of V ([total_vertices][2]
+ *            binary64).  total_vertices + 3 P < 2^31.
+ *   Q, m, labels [P][ceil(m/32)], counts, status: as pip_voronoi_allpairs.
+ *            A polygon with fewer than 3 vertices or a range outside
+ *            [0, total_vertices] gets PIP_EINVAL, one with more than
+ *            PIP_MAX_EDGES PIP_EUNSUPPORTED; its labels and count are 0.
+ *   workspace  pip_voronoi_allpairs_csr_workspace_bytes(P, total_vertices)
+ *            bytes (device, 256-byte aligned, caller-owned).
+ * The options PIP_OPT_ALLPAIRS_CULL and PIP_OPT_ALLPAIRS_PAIR apply as for
+ * pip_voronoi_allpairs; labels and counts never depend on them.
+ */
+size_t pip_voronoi_allpairs_csr_workspace_bytes(int32_t P, int64_t total_vertices);
+pip_status pip_voronoi_allpairs_csr(pip_ctx ctx, int32_t P, const int64_t *vtx_off,
+                                    const double *V, int64_t total_vertices, const float *Q,
+                                    int64_t m, uint32_t *labels, int32_t *counts,
+                                    int32_t *status, void *workspace, size_t workspace_bytes,
+                                    hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Differentiable collision cost.  For edge i of a convex footprint the
  * Voronoi margin (Eq. 11) divided by -2|p_i - p_0| is the signed distance of

@@ -95,6 +95,9 @@ SIGNATURES = {
     "pip_voronoi_allpairs_workspace_bytes": (_c.c_size_t, [_i32, _i32]),
     "pip_voronoi_allpairs": (_int, [_vp, _i32, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp,
                                     _c.c_size_t, _vp]),
+    "pip_voronoi_allpairs_csr_workspace_bytes": (_c.c_size_t, [_i32, _i64]),
+    "pip_voronoi_allpairs_csr": (_int, [_vp, _i32, _vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp,
+                                        _c.c_size_t, _vp]),
     "pip_cost_workspace_bytes": (_c.c_size_t, [_i32, _i64, _i64]),
     "pip_cost_fwd": (_int, [_vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp, _c.c_size_t, _vp]),
     "pip_cost_bwd": (_int, [_vp, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp, _vp,

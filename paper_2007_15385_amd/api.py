@@ -548,6 +548,43 @@ def pip_voronoi_allpairs(V, Q, labels=None, counts=None, status=None, workspace=
     return labels, counts[:Pn], status[:Pn]
 
 
+def allpairs_csr_workspace_bytes(P: int, total_vertices: int) -> int:
+    return int(_lib().pip_voronoi_allpairs_csr_workspace_bytes(int(P), int(total_vertices)))
+
+
+def pip_voronoi_allpairs_csr(vtx_off, V, Q, labels=None, counts=None, status=None,
+                             workspace=None):
+    """Polygons of uneven vertex counts (vtx_off [P+1] int64, V [total, 2]
+    float64) against all points Q [m, 2] float32 -> (labels [P, ceil(m/32)]
+    int32, counts [P] int32, status [P] int32)."""
+    vtx_off = _i64(vtx_off, "vtx_off")
+    V = _polygon(V) if V.shape[0] else V
+    if V.dtype != torch.float64 or V.dim() != 2 or V.shape[1] != 2 or not V.is_contiguous():
+        raise ValueError("V must be a contiguous float64 tensor of shape [total_vertices, 2]")
+    if Q.dtype != torch.float32 or Q.dim() != 2 or Q.shape[1] != 2 or not Q.is_contiguous():
+        raise ValueError("Q must be a contiguous float32 tensor of shape [m, 2]")
+    d = _dev(Q)
+    Pn = vtx_off.numel() - 1
+    m = Q.shape[0]
+    words = num_label_words(m)
+    if labels is None:
+        labels = torch.empty((max(Pn, 1), max(words, 1)), dtype=torch.int32, device=Q.device)
+    if counts is None:
+        counts = torch.empty(max(Pn, 1), dtype=torch.int32, device=Q.device)
+    if status is None:
+        status = torch.empty(max(Pn, 1), dtype=torch.int32, device=Q.device)
+    need = allpairs_csr_workspace_bytes(Pn, V.shape[0])
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=Q.device)
+    ctx = context(d)
+    s = _lib().pip_voronoi_allpairs_csr(ctx, Pn, vtx_off.data_ptr(),
+                                        V.data_ptr() if V.shape[0] else None, V.shape[0],
+                                        Q.data_ptr() if m else None, m, labels.data_ptr(),
+                                        counts.data_ptr(), status.data_ptr(),
+                                        workspace.data_ptr(), workspace.numel(), _stream(d))
+    _check(s, "pip_voronoi_allpairs_csr", ctx)
+    return labels[:Pn], counts[:Pn], status[:Pn]
+
 # -- non-convex polygons: union of convex pieces ------------------------------
 def convex_decompose(V, max_piece_vertices: int = 64):
     """Convex pieces of a simple polygon (the library's host routine):

@@ -53,8 +53,14 @@ __global__ void k_poses_to_polygons(const double* __restrict__ F, int n,
     Wout[2 * i + 1] = (s * vx + c * vy) + ty;
 }
 
-// Table rows of polygon k: hdr[k], coef[k * n4 ...], gen[k * (n + 1) ...].
-__global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
+// Table rows of polygon k: hdr[k], coef[k * n4 ...], gen[k * (n + 1) ...]
+// for P polygons of n vertices each (V [P][n][2]); with vtx_off (CSR, polygon
+// k = V[vtx_off[k] .. vtx_off[k+1]), 3..64 vertices) the rows start at
+// vtx_off[k] + 3 k and the generators at vtx_off[k] + k, and a polygon with a
+// bad vertex range or count gets a status, no rows, labels 0 and count 0.
+__global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n_uniform,
+                                                          const int64_t* __restrict__ vtx_off,
+                                                          int64_t total_vertices,
                                                           const double* __restrict__ V,
                                                           PolyHdr* __restrict__ hdr,
                                                           float4* __restrict__ coef,
@@ -66,8 +72,40 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
     const int wv = threadIdx.x / kWave;
     const int64_t k = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     if (k >= P) return;
+    int64_t v0 = k * n_uniform, nk = n_uniform;
+    int64_t row0 = k * ((n_uniform + 3) & ~3), gen0 = k * (n_uniform + 1);
+    if (vtx_off) {
+        v0 = vtx_off[k];
+        nk = vtx_off[k + 1] - v0;
+        row0 = v0 + 3 * k;
+        gen0 = v0 + k;
+        int bad = 0;
+        if (v0 < 0 || nk < 0 || v0 + nk > total_vertices || nk < 3) bad = 1;  // PIP_EINVAL
+        else if (nk > kMaxEdges) bad = 6;                                   // PIP_EUNSUPPORTED
+        if (bad) {
+            if (lane == 0) {
+                PolyHdr H;
+                H.ox = H.oy = 0.f;
+                H.KQ = H.KA = H.KB = H.KC = __builtin_huge_valf();
+                H.n = 0;
+                H.n4 = 0;
+                H.status = bad;
+                H.cx = H.cy = 0.f;
+                H.rad = __builtin_huge_valf();
+                H.npair = 0;
+                H.radial = 0;
+                H.row = 0;
+                H.gen = 0;
+                hdr[k] = H;
+                if (status) status[k] = bad;
+                if (counts) counts[k] = 0;
+            }
+            return;
+        }
+    }
+    const int n = (int)nk;
     PolyLds& L = S[wv];
-    if (lane < n) L.vtx[lane] = make_double2(V[2 * (k * n + lane)], V[2 * (k * n + lane) + 1]);
+    if (lane < n) L.vtx[lane] = make_double2(V[2 * (v0 + lane)], V[2 * (v0 + lane) + 1]);
     if (lane == 0) L.n = n;
     __builtin_amdgcn_wave_barrier();
     prepare_polygon(L, K_VORONOI, lane, /*global_frame=*/true);
@@ -137,11 +175,11 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
     }
     const int np4 = (npair + 3) & ~3;
     if (npair > 0) {
-        if (lane < np4) coef[k * n4 + lane] = prow;  // rows past n/2 repeat pair 0
+        if (lane < np4) coef[row0 + lane] = prow;  // rows past n/2 repeat pair 0
     } else if (lane < n4) {
-        coef[k * n4 + lane] = L.coef[lane];
+        coef[row0 + lane] = L.coef[lane];
     }
-    for (int i = lane; i <= n; i += kWave) gen[k * (n + 1) + i] = L.gen[i];
+    for (int i = lane; i <= n; i += kWave) gen[gen0 + i] = L.gen[i];
     if (lane == 0) {
         PolyHdr H;
         H.ox = L.ox;
@@ -158,7 +196,9 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n,
         const double ce = fabs((double)H.cx - g0x) + fabs((double)H.cy - g0y);
         H.rad = round_up_f32((rmax + ce) * (1.0 + 1.0 / 65536.0) + 1e-30);  // NaN -> +inf
         H.npair = npair;
-        for (int i = 0; i < 3; ++i) H.pad[i] = 0;
+        H.radial = 0;
+        H.row = (int)row0;
+        H.gen = (int)gen0;
         hdr[k] = H;
         if (status) status[k] = L.status;
         if (counts) counts[k] = 0;  // k_allpairs accumulates into it
@@ -174,27 +214,45 @@ __device__ __forceinline__ float wave_max_f(float v) {
 // grid: x = point tiles of 2048, y = polygon groups of PG (<= 16).  CULL:
 // skip (polygon, wave) pairs whose bounding disk misses the wave's points.
 // PAIR: polygons whose table holds antipodal pairs take the paired loop.
-template <bool CULL, bool PAIR>
+// CSR: polygons of uneven vertex counts (n4, row and generator offset from
+// each polygon's header; LDS rows at a fixed stride of kCsrStride per polygon).
+constexpr int kCsrStride = kMaxEdges + 4;
+
+template <bool CULL, bool PAIR, bool CSR>
 __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__ hdr,
                                                    const float4* __restrict__ coef,
                                                    const double2* __restrict__ gen, int64_t P,
                                                    int n, int PG, const float2* __restrict__ Q,
                                                    int64_t m, uint32_t* __restrict__ labels,
                                                    int32_t* __restrict__ counts) {
-    extern __shared__ float4 coef_s[];  // [PG][n4]
+    extern __shared__ float4 coef_s[];  // [PG][n4], CSR: [PG][kCsrStride]
     __shared__ int32_t cnt_s[kMaxGroup];
     __shared__ float band_s[kWavesPerBlock][kMaxGroup];  // per (wave, polygon)
     __shared__ int skip_s[kWavesPerBlock][kMaxGroup];    // polygon's disk misses the wave's points
     __shared__ int npair_s[kMaxGroup];                   // antipodal pair rows (0: edge rows)
+    __shared__ int n_s[kMaxGroup], n4_s[kMaxGroup];      // CSR: edges and rows per polygon
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int n4 = (n + 3) & ~3;
+    const int n4u = (n + 3) & ~3;
     const int64_t k0 = (int64_t)blockIdx.y * PG;
     const int pg = (int)((P - k0) < PG ? (P - k0) : PG);
     const int64_t words = (m + 31) / 32;
 
-    for (int i = tid; i < pg * n4; i += kBlock) coef_s[i] = coef[k0 * n4 + i];
+    if constexpr (CSR) {
+        for (int p = wv; p < pg; p += kWavesPerBlock) {  // one wave per polygon
+            const PolyHdr& H = hdr[k0 + p];
+            const int r4 = __builtin_amdgcn_readfirstlane(H.n4);
+            const int row = __builtin_amdgcn_readfirstlane(H.row);
+            if (lane < r4) coef_s[p * kCsrStride + lane] = coef[row + lane];
+            if (lane == 0) {
+                n_s[p] = H.n;
+                n4_s[p] = r4;
+            }
+        }
+    } else {
+        for (int i = tid; i < pg * n4u; i += kBlock) coef_s[i] = coef[k0 * n4u + i];
+    }
     for (int i = tid; i < pg; i += kBlock) cnt_s[i] = 0;
 
     // this wave's 512 points (lane l holds points l + 64 j); past the end and
@@ -281,12 +339,14 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
         const int nw = (rem + 31) / 32;
         for (int p = 0; p < pg; ++p) {
             const int64_t k = k0 + p;
-            if (CULL && __builtin_amdgcn_readfirstlane(skip_s[wv][p])) {  // all outside
+            const int n4 = CSR ? __builtin_amdgcn_readfirstlane(n4_s[p]) : n4u;
+            if ((CULL && __builtin_amdgcn_readfirstlane(skip_s[wv][p])) || n4 == 0) {
+                // all outside (or a polygon that contains no point)
                 if (lane < nw) labels[k * words + base / 32 + lane] = 0u;
                 continue;
             }
             const float E = band_s[wv][p];
-            const float4* cf = coef_s + p * n4;
+            const float4* cf = coef_s + p * (CSR ? kCsrStride : n4u);
             float M[kP32];
             const int np = PAIR ? __builtin_amdgcn_readfirstlane(npair_s[p]) : 0;
             if (PAIR && np > 0) {
@@ -356,7 +416,8 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
                 }
             }
             if (any_unc) {  // rare: re-decide in binary64 (Algorithm 5)
-                const double2* G = gen + k * (n + 1);
+                const int nk = CSR ? n_s[p] : n;
+                const double2* G = gen + (CSR ? (int64_t)hdr[k].gen : k * (n + 1));
 #pragma unroll
                 for (int j = 0; j < kP32; ++j) {
                     const uint64_t unc = ~(inm[j] | __ballot(M[j] > E)) & live[j];
@@ -370,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
 #if defined(__HIP_DEVICE_COMPILE__)
                             asm volatile("" : "+v"(px), "+v"(py));
 #endif
-                            r = voronoi64((double)px, (double)py, G, n);
+                            r = voronoi64((double)px, (double)py, G, nk);
                         }
                         inm[j] = (inm[j] & ~unc) | (__ballot(r) & unc);
                     }
@@ -432,8 +493,9 @@ hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, in
     float4* coef = reinterpret_cast<float4*>(b + L.coef);
     double2* gen = reinterpret_cast<double2*>(b + L.gen);
     const unsigned pblocks = (unsigned)((P + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL(k_prepare_uniform, dim3(pblocks), dim3(kBlock), 0, stream, P, n, V, hdr,
-                       coef, gen, status, counts, pair);
+    hipLaunchKernelGGL(k_prepare_uniform, dim3(pblocks), dim3(kBlock), 0, stream, P, n,
+                       (const int64_t*)nullptr, (int64_t)0, V, hdr, coef, gen, status, counts,
+                       pair);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (m == 0) return hipSuccess;
@@ -442,9 +504,48 @@ hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, in
     dim3 grid((unsigned)((m + kTilePoints - 1) / kTilePoints), (unsigned)((P + pg - 1) / pg));
     const size_t lds = (size_t)pg * n4 * 16;
     const float2* Q2 = reinterpret_cast<const float2*>(Q);
-    auto kern = cull ? (pair ? k_allpairs<true, true> : k_allpairs<true, false>)
-                     : (pair ? k_allpairs<false, true> : k_allpairs<false, false>);
+    auto kern = cull ? (pair ? k_allpairs<true, true, false> : k_allpairs<true, false, false>)
+                     : (pair ? k_allpairs<false, true, false> : k_allpairs<false, false, false>);
     hipLaunchKernelGGL(kern, grid, dim3(kBlock), lds, stream, hdr, coef, gen, P, n, pg, Q2, m,
+                       labels, counts);
+    return hipGetLastError();
+}
+
+size_t allpairs_csr_workspace_layout(int64_t P, int64_t total_vertices, AllpairsLayout* L) {
+    auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t off = 0;
+    L->hdr = off;
+    off = up(off + sizeof(PolyHdr) * (size_t)P);
+    L->coef = off;
+    off = up(off + 16 * (size_t)(total_vertices + 3 * P));
+    L->gen = off;
+    off = up(off + 16 * (size_t)(total_vertices + P));
+    return off;
+}
+
+hipError_t launch_allpairs_csr(int64_t P, const int64_t* vtx_off, const double* V,
+                               int64_t total_vertices, const float* Q, int64_t m,
+                               uint32_t* labels, int32_t* counts, int32_t* status, void* ws,
+                               int cull, int pair, hipStream_t stream) {
+    AllpairsLayout L;
+    allpairs_csr_workspace_layout(P, total_vertices, &L);
+    char* b = static_cast<char*>(ws);
+    PolyHdr* hdr = reinterpret_cast<PolyHdr*>(b + L.hdr);
+    float4* coef = reinterpret_cast<float4*>(b + L.coef);
+    double2* gen = reinterpret_cast<double2*>(b + L.gen);
+    const unsigned pblocks = (unsigned)((P + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL(k_prepare_uniform, dim3(pblocks), dim3(kBlock), 0, stream, P, 0, vtx_off,
+                       total_vertices, V, hdr, coef, gen, status, counts, pair);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (m == 0) return hipSuccess;
+    const int pg = kLdsCoefBytes / (16 * kCsrStride);  // 15 polygons of up to 64 edges
+    dim3 grid((unsigned)((m + kTilePoints - 1) / kTilePoints), (unsigned)((P + pg - 1) / pg));
+    const size_t lds = (size_t)pg * kCsrStride * 16;
+    const float2* Q2 = reinterpret_cast<const float2*>(Q);
+    auto kern = cull ? (pair ? k_allpairs<true, true, true> : k_allpairs<true, false, true>)
+                     : (pair ? k_allpairs<false, true, true> : k_allpairs<false, false, true>);
+    hipLaunchKernelGGL(kern, grid, dim3(kBlock), lds, stream, hdr, coef, gen, P, 0, pg, Q2, m,
                        labels, counts);
     return hipGetLastError();
 }

@@ -1124,6 +1124,45 @@ pip_status pip_voronoi_allpairs(pip_ctx ctx, int32_t P, int32_t n, const double*
 }
 
 
+size_t pip_voronoi_allpairs_csr_workspace_bytes(int32_t P, int64_t total_vertices) {
+    if (P < 0 || total_vertices < 0) return 0;
+    pipdev::AllpairsLayout L;
+    return pipdev::allpairs_csr_workspace_layout(P, total_vertices, &L);
+}
+
+pip_status pip_voronoi_allpairs_csr(pip_ctx ctx, int32_t P, const int64_t* vtx_off,
+                                    const double* V, int64_t total_vertices, const float* Q,
+                                    int64_t m, uint32_t* labels, int32_t* counts,
+                                    int32_t* status, void* workspace, size_t workspace_bytes,
+                                    hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (P < 0) return fail(PIP_EINVAL, "P = %d is negative", (int)P);
+    if (total_vertices < 0) return fail(PIP_EINVAL, "total_vertices is negative");
+    if (total_vertices + 3 * (int64_t)P >= (int64_t(1) << 31))
+        return fail(PIP_EUNSUPPORTED, "total_vertices + 3 P must stay below 2^31");
+    if (P > 0 && (!vtx_off || !aligned(vtx_off, 8)))
+        return fail(PIP_EINVAL, "vtx_off is NULL or not 8-byte aligned");
+    if (total_vertices > 0 && (!V || !aligned(V, 8))) return fail(PIP_EINVAL, "V is NULL or misaligned");
+    pip_status s = check_points(Q, PIP_F32, m);
+    if (s != PIP_OK) return s;
+    if (P > 0 && m > 0 && (!labels || !aligned(labels, 4)))
+        return fail(PIP_EINVAL, "labels is NULL or not 4-byte aligned");
+    if (counts && !aligned(counts, 4)) return fail(PIP_EINVAL, "counts is not 4-byte aligned");
+    if (status && !aligned(status, 4)) return fail(PIP_EINVAL, "status is not 4-byte aligned");
+    if (P == 0) return PIP_OK;
+    const size_t need = pip_voronoi_allpairs_csr_workspace_bytes(P, total_vertices);
+    if (!workspace || workspace_bytes < need)
+        return fail(PIP_EINVAL, "workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
+    if (!aligned(workspace, 256)) return fail(PIP_EINVAL, "workspace is not 256-byte aligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_allpairs_csr(P, vtx_off, V, total_vertices, Q, m, labels, counts,
+                                               status, workspace, ctx->allpairs_cull,
+                                               ctx->allpairs_pair, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
 // ---------------------------------------------------------------------------
 // differentiable collision cost
 // ---------------------------------------------------------------------------

@@ -39,7 +39,7 @@ struct alignas(16) PolyHdr {
     float cx, cy, rad;     // disk (float32 centre, radius rounded up) containing the polygon
     int npair;             // > 0: coefficient rows are npair antipodal edge pairs (all pairs)
     int radial;            // 1: the batched screen takes the radial pre-screen (table usable)
-    int pad[2];
+    int row, gen;          // all pairs over CSR polygons: first coefficient row and generator
 };
 
 // Device view of a batched request plus its workspace.
@@ -87,6 +87,12 @@ hipError_t launch_poses_to_polygons(const double* F, int n, const float* pose, c
 hipError_t launch_allpairs(int64_t P, int n, const double* V, const float* Q, int64_t m,
                            uint32_t* labels, int32_t* counts, int32_t* status, void* ws, int cull,
                            int pair, hipStream_t stream);
+// All pairs over CSR polygons of uneven vertex counts (vtx_off [P+1]).
+size_t allpairs_csr_workspace_layout(int64_t P, int64_t total_vertices, AllpairsLayout* L);
+hipError_t launch_allpairs_csr(int64_t P, const int64_t* vtx_off, const double* V,
+                               int64_t total_vertices, const float* Q, int64_t m,
+                               uint32_t* labels, int32_t* counts, int32_t* status, void* ws,
+                               int cull, int pair, hipStream_t stream);
 // Non-convex polygon as a union of convex pieces (pieces.hip).
 struct PiecesLayout {
     size_t hdr, rows, gens;

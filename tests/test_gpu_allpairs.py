@@ -318,3 +318,135 @@ def test_allpairs_plan_autotune_and_graph_replays(P):
         assert lib().pip_plan_set_config(plan.handle, ctypes.byref(BatchedConfig(1, 1))) == 1
     finally:
         plan.close()
+
+
+# ---------------------------------------------------------------------------
+# CSR polygons of uneven vertex counts
+# ---------------------------------------------------------------------------
+def csr_polygons(rng, P, n_lo=3, n_hi=64, extent=40.0, r_lo=0.5, r_hi=6.0):
+    polys = []
+    for _ in range(P):
+        n = int(rng.integers(n_lo, n_hi + 1))
+        polys.append(W.circle_polygon(n, float(rng.uniform(r_lo, r_hi)),
+                                      rng.uniform(-extent, extent, 2), rng))
+    vtx_off = np.concatenate([[0], np.cumsum([len(v) for v in polys])]).astype(np.int64)
+    return polys, vtx_off, np.concatenate(polys)
+
+
+def run_csr(P, vtx_off, V, Q):
+    lab, cnt, st = P.pip_voronoi_allpairs_csr(torch.from_numpy(vtx_off).cuda(),
+                                              torch.from_numpy(V).cuda(),
+                                              torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    return lab.cpu().numpy().view(np.uint32), cnt.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.fixture(params=["dense", "cull_pair"])
+def allpairs_variant(request, P):
+    """Dense, then with culling and antipodal pairing switched on (labels and
+    counts must not change)."""
+    on = 1 if request.param == "cull_pair" else 0
+    old = (P.get_option(P.PIP_OPT_ALLPAIRS_CULL), P.get_option(P.PIP_OPT_ALLPAIRS_PAIR))
+    P.set_option(P.PIP_OPT_ALLPAIRS_CULL, on)
+    P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, on)
+    yield request.param
+    P.set_option(P.PIP_OPT_ALLPAIRS_CULL, old[0])
+    P.set_option(P.PIP_OPT_ALLPAIRS_PAIR, old[1])
+
+
+@pytest.mark.parametrize("m", [1, 513, 2048, 5001])
+def test_allpairs_csr_small(P, oracle, allpairs_variant, m):
+    from oracle import pack_bits
+    rng = np.random.default_rng(300 + m)
+    polys, vtx_off, V = csr_polygons(rng, 45, extent=4.0)
+    # symmetric polygons (regular even n) exercise the paired rows
+    th = np.arange(16) * np.pi / 8
+    polys[3] = 2.0 * np.stack([np.cos(th), np.sin(th)], 1)
+    vtx_off = np.concatenate([[0], np.cumsum([len(v) for v in polys])]).astype(np.int64)
+    V = np.concatenate(polys)
+    Q = rng.uniform(-8, 8, size=(m, 2)).astype(np.float32)
+    lab, cnt, st = run_csr(P, vtx_off, V, Q)
+    for k, Vk in enumerate(polys):
+        want = oracle.voronoi(Vk, Q.astype(np.float64))
+        assert np.array_equal(lab[k], pack_bits(want)), k
+        assert int(cnt[k]) == int(want.sum()), k
+    assert (st == 0).all()
+
+
+def test_allpairs_csr_edges_and_invalid(P, oracle, allpairs_variant):
+    """Points on and within 1e-9..1e-6 of every polygon's edges; polygons
+    with 2 and 65 vertices and an empty one get PIP_EINVAL /
+    PIP_EUNSUPPORTED, zero labels and zero counts; the rest are exact."""
+    from oracle import pack_bits
+    rng = np.random.default_rng(31)
+    polys, _, _ = csr_polygons(rng, 20, extent=30.0)
+    polys.insert(5, np.array([[0.0, 0.0], [1.0, 1.0]]))
+    polys.insert(9, W.circle_polygon(65, 3.0, (1.0, 2.0), rng))
+    polys.insert(12, np.zeros((0, 2)))
+    pts = []
+    for Vk in polys:
+        if not 3 <= len(Vk) <= 64:
+            continue
+        Wr = np.roll(Vk, 1, 0)
+        e = Vk - Wr
+        L = np.hypot(e[:, 0], e[:, 1])
+        for off in (0.0, 1e-9, -1e-9, 1e-7, -1e-6):
+            i = rng.integers(len(Vk), size=30)
+            t = rng.random(30)
+            pts.append(np.stack([Wr[i, 0] + t * e[i, 0] + off * e[i, 1] / L[i],
+                                 Wr[i, 1] + t * e[i, 1] - off * e[i, 0] / L[i]], 1))
+        pts.append(Vk)
+    Q = np.concatenate(pts).astype(np.float32)
+    vtx_off = np.concatenate([[0], np.cumsum([len(v) for v in polys])]).astype(np.int64)
+    V = np.concatenate(polys)
+    lab, cnt, st = run_csr(P, vtx_off, V, Q)
+    for k, Vk in enumerate(polys):
+        if len(Vk) < 3:
+            assert st[k] == 1 and cnt[k] == 0 and not lab[k].any(), k
+            continue
+        if len(Vk) > 64:
+            assert st[k] == 6 and cnt[k] == 0 and not lab[k].any(), k
+            continue
+        want = oracle.voronoi(Vk, Q.astype(np.float64))
+        assert np.array_equal(lab[k], pack_bits(want)), k
+        assert int(cnt[k]) == int(want.sum()) and st[k] == 0, k
+
+
+def test_allpairs_csr_matches_uniform(P):
+    """Polygons of one vertex count through both entry points: identical
+    labels and counts."""
+    rng = np.random.default_rng(33)
+    polys = np.stack([W.circle_polygon(8, 2.0, rng.uniform(-20, 20, 2), rng) for _ in range(300)])
+    Q = rng.uniform(-25, 25, size=(20000, 2)).astype(np.float32)
+    Qt = torch.from_numpy(Q).cuda()
+    lab_u, cnt_u, _ = P.pip_voronoi_allpairs(torch.from_numpy(polys).cuda(), Qt)
+    vtx_off = (8 * np.arange(301)).astype(np.int64)
+    lab_c, cnt_c, _ = P.pip_voronoi_allpairs_csr(torch.from_numpy(vtx_off).cuda(),
+                                                 torch.from_numpy(polys.reshape(-1, 2)).cuda(), Qt)
+    torch.cuda.synchronize()
+    assert torch.equal(lab_u, lab_c) and torch.equal(cnt_u, cnt_c)
+
+
+def test_allpairs_csr_full_size(P, oracle):
+    """2048 polygons of 3..64 vertices (centres in [-40, 40]^2, radii
+    0.5..6) against the 131,072-point lidar cloud: 64 polygons checked in
+    full and the first 4096 points of every polygon, plus every count of the
+    checked polygons."""
+    from oracle import pack_bits, unpack_bits
+    rng = np.random.default_rng(34)
+    polys, vtx_off, V = csr_polygons(rng, 2048)
+    Q = W.lidar_cloud()
+    say(f"[case] all pairs CSR: {len(polys)} polygons x {len(Q)} points")
+    lab, cnt, st = run_csr(P, vtx_off, V, Q)
+    assert (st == 0).all()
+    Q64 = Q.astype(np.float64)
+    for k in sorted(rng.choice(len(polys), 64, replace=False)):
+        want = oracle.voronoi(polys[k], Q64)
+        assert np.array_equal(lab[k], pack_bits(want)), k
+        assert int(cnt[k]) == int(want.sum()), k
+    Qh = Q64[:4096]
+    bad = 0
+    for k in range(len(polys)):
+        want = oracle.voronoi(polys[k], Qh)
+        bad += int((unpack_bits(lab[k], len(Q))[:4096] != want).sum())
+    assert bad == 0
