@@ -569,7 +569,7 @@ pip_status pip_voronoi_allpairs_csr(pip_ctx ctx, int32_t P, const int64_t *vtx_o
  * the cloud of relu(min_i of it) -- the total penetration depth -- evaluated
  * with every point moved into the body frame, p_b = R(theta)^T (p - t).
  *
- *   footprint  [n][2] float32 body-frame vertices, 3 <= n <= 16.
+ *   footprint  [n][2] float32 body-frame vertices, 3 <= n <= PIP_MAX_EDGES.
  *   pose       [K][3] float32 (x, y, theta); cos/sin of theta are taken in
  *              binary64 and rounded to float32.
  *   Q          [m][2] float32 points (non-finite points contribute nothing).

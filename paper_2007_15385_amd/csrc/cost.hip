@@ -19,11 +19,14 @@
 //                    ties) and accumulates, for every contributing pair,
 //                    d/dt = R n, d/dtheta = -n_x p_b,y + n_y p_b,x (pose
 //                    partials) and the derivatives of d to p_i and p_0 (table
-//                    partials, per-lane LDS accumulators, no float atomics).
+//                    partials: per pose, one wave sum per edge that a point of
+//                    the wave presses on, added to the wave's LDS row; no
+//                    float atomics, a fixed order).
 //   k_cost_finish    per pose: binary64 sum of the partials in tile order.
 //   k_gen_backward   binary64 sum of the table partials, then the chain rule
 //                    through the reflection (Eq. 8) and the centroid
-//                    (Algorithm 3) to the footprint vertices.  The path
+//                    (Algorithm 3) to the footprint vertices, one lane per
+//                    edge.  The path
 //                    through p_0 cancels in exact arithmetic (d_i depends on
 //                    the edge line only); its float residual is reported.
 #include "device.hpp"
@@ -35,7 +38,7 @@ namespace {
 
 constexpr int kTile = kBlock * kPPL;  // 1024 points per workgroup
 constexpr int kPG = 64;               // poses per workgroup
-constexpr int kCostMaxEdges = 16;     // footprint size limit of the cost path
+constexpr int kCostMaxEdges = kMaxEdges;  // footprint size limit of the cost path
 
 struct CostTab {
     float4 line[kMaxEdges];  // (-n_x, -n_y, k, |h|)
@@ -141,9 +144,9 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
     __shared__ float4 pair_s[kMaxEdges / 2];
     __shared__ PoseCS pose_s[kPG];
     __shared__ float red_s[kPG][kWavesPerBlock][3];
-    // backward only: per-lane accumulators [wave][component][lane], 2(n+1)
-    // components (p_0, then p_i), each lane adding to its own slots in order
-    extern __shared__ float acc_dyn[];
+    // backward only: table partials of each wave, 2(n+1) components (p_0,
+    // then p_i), each added by lane 0 of its wave in pose order
+    __shared__ float accw[kWavesPerBlock][2 * (kMaxEdges + 1)];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -169,9 +172,9 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
         pose_s[tid] = P;
     }
     const int ncomp = 2 * (n + 1);
-    auto acc = [&](int q, int c, int l) -> float& { return acc_dyn[(q * ncomp + c) * kWave + l]; };
     if constexpr (BWD) {
-        for (int i = tid; i < kWavesPerBlock * ncomp * kWave; i += kBlock) acc_dyn[i] = 0.f;
+        for (int i = tid; i < kWavesPerBlock * 2 * (kMaxEdges + 1); i += kBlock)
+            (&accw[0][0])[i] = 0.f;
     }
     const int64_t base = (int64_t)t * kTile + (int64_t)wv * kChunk;
     float x[kPPL], y[kPPL];
@@ -295,9 +298,13 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
             if (lane == 0) red_s[p][wv][0] = sum;
         } else {
             const float w = grad_cost[k0 + p];
-            float sx = 0.f, sy = 0.f, sth = 0.f;
+            float sx = 0.f, sy = 0.f, sth = 0.f, s0x = 0.f, s0y = 0.f;
+            float ghx[kPPL], ghy[kPPL];
+            uint64_t emask = 0;  // edges this lane's points press on
 #pragma unroll
             for (int j = 0; j < kPPL; ++j) {
+                ghx[j] = 0.f;
+                ghy[j] = 0.f;
                 if (valid[j] && dmin[j] > 0.f) {
                     const float4 L = line_s[arg[j]];
                     const float nx = -L.x, ny = -L.y, len = L.w;
@@ -309,11 +316,11 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
                     const float un = fmaf(ux, nx, uy * ny);
                     const float dhx = 0.5f * nx - (ux - un * nx) / len;
                     const float dhy = 0.5f * ny - (uy - un * ny) / len;
-                    const int a = arg[j];
-                    acc(wv, 2 * (1 + a), lane) += w * dhx;
-                    acc(wv, 2 * (1 + a) + 1, lane) += w * dhy;
-                    acc(wv, 0, lane) += w * (nx - dhx);
-                    acc(wv, 1, lane) += w * (ny - dhy);
+                    ghx[j] = w * dhx;
+                    ghy[j] = w * dhy;
+                    s0x += w * (nx - dhx);
+                    s0y += w * (ny - dhy);
+                    emask |= 1ull << arg[j];
                 }
             }
             sx = wave_sum(sx);
@@ -323,6 +330,38 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
                 red_s[p][wv][0] = sx;
                 red_s[p][wv][1] = sy;
                 red_s[p][wv][2] = sth;
+            }
+            // table partials: p_0, then one wave sum per edge pressed on
+            // (in increasing edge order), added by lane 0 in pose order
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) emask |= __shfl_xor(emask, o, kWave);
+            emask = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(emask >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)emask);
+            if (emask) {
+                s0x = wave_sum(s0x);
+                s0y = wave_sum(s0y);
+                if (lane == 0) {
+                    accw[wv][0] += s0x;
+                    accw[wv][1] += s0y;
+                }
+                while (emask) {
+                    const int e = __builtin_ctzll(emask);
+                    emask &= emask - 1;
+                    float ex = 0.f, ey = 0.f;
+#pragma unroll
+                    for (int j = 0; j < kPPL; ++j) {
+                        if (arg[j] == e) {  // 0 unless the point contributes
+                            ex += ghx[j];
+                            ey += ghy[j];
+                        }
+                    }
+                    ex = wave_sum(ex);
+                    ey = wave_sum(ey);
+                    if (lane == 0) {
+                        accw[wv][2 * (1 + e)] += ex;
+                        accw[wv][2 * (1 + e) + 1] += ey;
+                    }
+                }
             }
         }
     }
@@ -342,11 +381,10 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
                 part_pose[((k0 + tid) * T + t) * 3 + c] = s;
             }
         }
-        // table partials of this workgroup: lanes, then waves, in a fixed order
+        // table partials of this workgroup: waves in a fixed order
         for (int c = tid; c < ncomp; c += kBlock) {
-            float s = 0.f;
-            for (int q = 0; q < kWavesPerBlock; ++q)
-                for (int l = 0; l < kWave; ++l) s += acc(q, c, l);
+            float s = accw[0][c];
+            for (int q = 1; q < kWavesPerBlock; ++q) s += accw[q][c];
             part_gen[((int64_t)blockIdx.y * T + t) * (2 * (kMaxEdges + 1)) + c] = s;
         }
     }
@@ -381,60 +419,52 @@ __global__ void k_pose_grad_finish(const float* __restrict__ part_pose, const fl
 }
 
 // Stage 1 of the table-gradient reduction: block b sums, in binary64 and in
-// part order, its contiguous range of per-workgroup partials.
+// part order, its contiguous range of per-workgroup partials (thread c owns
+// component c).
 constexpr int kGenRedBlocks = 256;
 
 __global__ __launch_bounds__(256) void k_gen_reduce1(const float* __restrict__ part_gen, int64_t nparts,
                                                    int ncomp, double* __restrict__ stage) {
     constexpr int NC = 2 * (kMaxEdges + 1);
-    constexpr int NCC = 2 * (kCostMaxEdges + 1);
-    __shared__ double red[256];
-    const int tid = threadIdx.x;
     const int64_t per = (nparts + kGenRedBlocks - 1) / kGenRedBlocks;
     const int64_t lo = (int64_t)blockIdx.x * per;
     const int64_t hi = lo + per < nparts ? lo + per : nparts;
-    double acc[NCC];
-    for (int c = 0; c < NCC; ++c) acc[c] = 0.0;
-    for (int64_t i = lo + tid; i < hi; i += 256)
-        for (int c = 0; c < ncomp; ++c) acc[c] += (double)part_gen[i * NC + c];
-    for (int c = 0; c < ncomp; ++c) {
-        red[tid] = acc[c];
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) red[tid] += red[tid + o];
-            __syncthreads();
-        }
-        if (tid == 0) stage[(int64_t)blockIdx.x * NC + c] = red[0];
-        __syncthreads();
+    for (int c = threadIdx.x; c < ncomp; c += 256) {
+        double s = 0.0;
+        for (int64_t i = lo; i < hi; ++i) s += (double)part_gen[i * NC + c];
+        stage[(int64_t)blockIdx.x * NC + c] = s;
     }
 }
 
-// Stage 2 (one thread): sums of the stage-1 results in block order, then the
-// chain rule to the vertices.  residual (optional, [2]): |total gradient to
-// p_0| and the scale it is measured against.
-__global__ __launch_bounds__(64) void k_gen_backward(const float* __restrict__ F, int n,
-                                                   const double* __restrict__ stage,
-                                                   float* __restrict__ grad_F,
-                                                   float* __restrict__ residual) {
+// Stage 2 (one wave): sums of the stage-1 results in block order, then the
+// chain rule to the vertices, lane i taking edge i (its reflection, Eq. 8,
+// and its share of the centroid, Algorithm 3); each vertex collects the
+// terms of its two edges, and the path through p_0 is summed in edge order.
+// residual (optional, [2]): |total gradient to p_0| and the scale it is
+// measured against.
+__global__ __launch_bounds__(kWave) void k_gen_backward(const float* __restrict__ F, int n,
+                                                      const double* __restrict__ stage,
+                                                      float* __restrict__ grad_F,
+                                                      float* __restrict__ residual) {
     constexpr int NC = 2 * (kMaxEdges + 1);
-    double G[NC];
-    const int tid = threadIdx.x;
+    __shared__ double G[NC];
+    __shared__ double vx[kMaxEdges], vy[kMaxEdges];
+    __shared__ double tb[kMaxEdges][2], ta[kMaxEdges][2];  // terms to v_i and to v_{i-1}
+    __shared__ double gg0[kMaxEdges][3];                    // edge i's terms to p_0, scale
+    const int lane = threadIdx.x;
     const int ncomp = 2 * (n + 1);
-    for (int c = 0; c < ncomp; ++c) {
+    for (int c = lane; c < ncomp; c += kWave) {
         double s = 0.0;
         for (int b = 0; b < kGenRedBlocks; ++b) s += stage[b * NC + c];
         G[c] = s;
     }
-    if (tid != 0) return;
-    // forward quantities in binary64 (Algorithms 3-4, same order as the
-    // preparation kernel)
-    double vx[kMaxEdges], vy[kMaxEdges], gV[2 * kMaxEdges];
-    for (int i = 0; i < n; ++i) {
-        vx[i] = (double)F[2 * i];
-        vy[i] = (double)F[2 * i + 1];
-        gV[2 * i] = 0.0;
-        gV[2 * i + 1] = 0.0;
+    if (lane < n) {
+        vx[lane] = (double)F[2 * lane];
+        vy[lane] = (double)F[2 * lane + 1];
     }
+    __syncthreads();
+    // forward quantities in binary64 (Algorithms 3-4, same order as the
+    // preparation kernel; every lane forms the same sums)
     double S = 0.0, Sx = 0.0, Sy = 0.0;
     for (int i = 0; i < n; ++i) {
         const int j = prev_edge(i, n);
@@ -444,11 +474,9 @@ __global__ __launch_bounds__(64) void k_gen_backward(const float* __restrict__ F
         Sy = Sy + (vy[i] + vy[j]) * Ai;
     }
     const double g0x = Sx / (3.0 * S), g0y = Sy / (3.0 * S);
-    double Gg0x = G[0], Gg0y = G[1];
-    double scale = fabs(G[0]) + fabs(G[1]);
     // reflections: g = (W g0 - 2 c [a; b]) / (a^2 + b^2), edge v_{i-1} -> v_i
-    for (int i = 0; i < n; ++i) {
-        const int j = prev_edge(i, n);
+    if (lane < n) {
+        const int i = lane, j = prev_edge(i, n);
         const double bx = vx[i], by = vy[i], ax = vx[j], ay = vy[j];
         const double ea = by - ay, eb = ax - bx;
         const double ec = -(ea * bx + eb * by);
@@ -457,44 +485,59 @@ __global__ __launch_bounds__(64) void k_gen_backward(const float* __restrict__ F
         const double Nx = w11 * g0x + w12 * g0y - 2.0 * ec * ea;
         const double Ny = w12 * g0x + w22 * g0y - 2.0 * ec * eb;
         const double Gx = G[2 * (1 + i)], Gy = G[2 * (1 + i) + 1];
-        scale += fabs(Gx) + fabs(Gy);
         const double GNx = Gx / den, GNy = Gy / den;
         const double Gden = -(Gx * Nx + Gy * Ny) / (den * den);
         double Gea = 2.0 * ea * Gden, Geb = 2.0 * eb * Gden;
         Gea += GNx * (-2.0 * ea * g0x - 2.0 * eb * g0y - 2.0 * ec) + GNy * (-2.0 * eb * g0x + 2.0 * ea * g0y);
         Geb += GNx * (2.0 * eb * g0x - 2.0 * ea * g0y) + GNy * (-2.0 * ea * g0x - 2.0 * eb * g0y - 2.0 * ec);
         const double Gec = GNx * (-2.0 * ea) + GNy * (-2.0 * eb);
-        Gg0x += w11 * GNx + w12 * GNy;
-        Gg0y += w12 * GNx + w22 * GNy;
-        // ec = -(ea bx + eb by)
+        gg0[i][0] = w11 * GNx + w12 * GNy;
+        gg0[i][1] = w12 * GNx + w22 * GNy;
+        gg0[i][2] = fabs(Gx) + fabs(Gy);
+        // ec = -(ea bx + eb by); ea = by - ay, eb = ax - bx
         Gea += -bx * Gec;
         Geb += -by * Gec;
-        gV[2 * i] += -ea * Gec;
-        gV[2 * i + 1] += -eb * Gec;
-        // ea = by - ay, eb = ax - bx
-        gV[2 * i + 1] += Gea;
-        gV[2 * j + 1] -= Gea;
-        gV[2 * j] += Geb;
-        gV[2 * i] -= Geb;
+        tb[i][0] = -ea * Gec - Geb;  // to v_i
+        tb[i][1] = -eb * Gec + Gea;
+        ta[i][0] = Geb;              // to v_{i-1}
+        ta[i][1] = -Gea;
     }
-    // centroid: g0 = (Sx, Sy) / (3 S)
+    __syncthreads();
+    // path through p_0, summed in edge order (every lane the same)
+    double Gg0x = G[0], Gg0y = G[1];
+    double scale = fabs(G[0]) + fabs(G[1]);
+    for (int i = 0; i < n; ++i) {
+        Gg0x += gg0[i][0];
+        Gg0y += gg0[i][1];
+        scale += gg0[i][2];
+    }
+    // centroid: g0 = (Sx, Sy) / (3 S), edge i's partial area A_i
     const double GSx = Gg0x / (3.0 * S), GSy = Gg0y / (3.0 * S);
     const double GS = -(Gg0x * Sx + Gg0y * Sy) / (3.0 * S * S);
-    for (int i = 0; i < n; ++i) {
-        const int j = prev_edge(i, n);
+    double cb0 = 0.0, cb1 = 0.0, ca0 = 0.0, ca1 = 0.0;
+    if (lane < n) {
+        const int i = lane, j = prev_edge(i, n);
         const double Ai = vx[j] * vy[i] - vx[i] * vy[j];
         const double GA = GS + GSx * (vx[i] + vx[j]) + GSy * (vy[i] + vy[j]);
-        gV[2 * i] += GSx * Ai;
-        gV[2 * j] += GSx * Ai;
-        gV[2 * i + 1] += GSy * Ai;
-        gV[2 * j + 1] += GSy * Ai;
-        gV[2 * j] += GA * vy[i];
-        gV[2 * i + 1] += GA * vx[j];
-        gV[2 * i] -= GA * vy[j];
-        gV[2 * j + 1] -= GA * vx[i];
+        cb0 = GSx * Ai - GA * vy[j];  // to v_i
+        cb1 = GSy * Ai + GA * vx[j];
+        ca0 = GSx * Ai + GA * vy[i];  // to v_{i-1}
+        ca1 = GSy * Ai - GA * vx[i];
     }
-    for (int i = 0; i < 2 * n; ++i) grad_F[i] = (float)gV[i];
-    if (residual) {
+    __syncthreads();
+    if (lane < n) {
+        ta[lane][0] += ca0;
+        ta[lane][1] += ca1;
+        tb[lane][0] += cb0;
+        tb[lane][1] += cb1;
+    }
+    __syncthreads();
+    if (lane < n) {  // vertex v: its edge v (as v_i) and edge v + 1 (as v_{i-1})
+        const int nx = lane + 1 < n ? lane + 1 : 0;
+        grad_F[2 * lane] = (float)(tb[lane][0] + ta[nx][0]);
+        grad_F[2 * lane + 1] = (float)(tb[lane][1] + ta[nx][1]);
+    }
+    if (residual && lane == 0) {
         residual[0] = (float)sqrt(Gg0x * Gg0x + Gg0y * Gg0y);
         residual[1] = (float)scale;
     }
@@ -545,12 +588,11 @@ hipError_t launch_cost(bool backward, const float* F, int n, const float* pose, 
     if (L.T > 0 && K > 0) {
         dim3 grid((unsigned)L.T, (unsigned)L.G);
         const float2* Q2 = reinterpret_cast<const float2*>(Q);
-        const size_t lds = (size_t)kWavesPerBlock * 2 * (n + 1) * kWave * sizeof(float);
         auto kern = backward ? (cull ? (pair ? k_cost<true, true, true> : k_cost<true, true, false>)
                                      : (pair ? k_cost<true, false, true> : k_cost<true, false, false>))
                              : (cull ? (pair ? k_cost<false, true, true> : k_cost<false, true, false>)
                                      : (pair ? k_cost<false, false, true> : k_cost<false, false, false>));
-        hipLaunchKernelGGL(kern, grid, dim3(kBlock), backward ? lds : 0, stream, tab, pose, K, Q2,
+        hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, stream, tab, pose, K, Q2,
                            m, grad_cost, pc, pp, pgn, T);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     } else {

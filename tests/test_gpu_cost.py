@@ -335,3 +335,52 @@ def test_cost_plan_autotune_and_graph_replays(P, scene, backward):
             check()
     finally:
         plan.close()
+
+
+def _footprint(n, rng, symmetric):
+    """Convex footprint of n vertices around the body origin: an ellipse
+    (semi-axes 2.4 and 0.95) sampled at n angles, centrally symmetric when
+    asked (angles in antipodal pairs), else jittered."""
+    th = np.arange(n) * (2 * np.pi / n) + 0.1
+    if not symmetric:
+        th = th + rng.uniform(-0.3, 0.3, n) * (np.pi / n)
+    return np.stack([2.4 * np.cos(th), 0.95 * np.sin(th)], 1).astype(np.float32)
+
+
+@pytest.mark.parametrize("n,symmetric", [(17, False), (32, True), (40, False), (64, True)])
+def test_cost_large_footprints(P, oracle, n, symmetric):
+    """Footprints of 17 to 64 edges: cost within 1e-4 of the oracle,
+    gradients (poses and footprint vertices) against the oracle's closed
+    form, deterministic, and the antipodal pairing close to the per-edge loop
+    for the symmetric ones.  Consecutive edges of a 64-gon are nearly
+    parallel, so for points near the medial axis the float32 screen and the
+    binary64 oracle can pick different minimising edges (a kink of the min);
+    such a point moves its whole contribution between two neighbouring edges.
+    The footprint gradient is therefore held per component to 1e-3 of the
+    scale S (the sum of absolute per-point contributions) and as a whole to
+    1e-4 in norm."""
+    rng = np.random.default_rng(400 + n)
+    F = _footprint(n, rng, symmetric)
+    Q = W.lidar_cloud(points_per_ring=1024, rings=64, config=5)
+    poses = W.trajectories(T=8).reshape(-1, 3)
+    F64, Q64, p64 = F.astype(np.float64), Q.astype(np.float64), poses.astype(np.float64)
+    K = len(poses)
+    w = rng.uniform(0.5, 2.0, K).astype(np.float32)
+    c_gpu = gpu_cost(P, F, poses, Q)
+    c_ref = oracle.cost(F64, p64, Q64)
+    assert np.all(np.abs(c_gpu - c_ref) <= 1e-4 * np.abs(c_ref) + 1e-6)
+    assert (c_ref > 0).sum() >= 8, "some poses must penetrate"
+    gp, gF, res = gpu_grad(P, F, poses, Q, w)
+    gp_ref, gF_ref, ap, aF = oracle.cost_grad(F64, p64, Q64, w.astype(np.float64), with_scale=True)
+    assert np.all(np.abs(gp - gp_ref) <= 1e-4 * (np.abs(gp_ref) + ap) + 1e-7)
+    assert np.all(np.abs(gF - gF_ref) <= 1e-3 * (np.abs(gF_ref) + aF) + 1e-7)
+    assert np.linalg.norm(gF - gF_ref) <= 1e-4 * np.linalg.norm(gF_ref)
+    assert res[0] <= 1e-4 * res[1]
+    b = gpu_grad(P, F, poses, Q, w)
+    assert np.array_equal(gp, b[0]) and np.array_equal(gF, b[1])
+    if symmetric:
+        p = _cost_opts(P, F, poses, Q, w, 1, 1)
+        assert np.all(np.abs(p[0] - c_gpu) <= 1e-5 * np.abs(c_gpu) + 1e-6)
+        assert np.all(np.abs(p[1] - gp_ref) <= 1e-4 * (np.abs(gp_ref) + ap) + 1e-6)
+    say(f"[stat] footprint n={n}: {int((c_ref > 0).sum())} of {K} poses penetrate")
+
