@@ -76,10 +76,22 @@ class CostPlan:
     fixed buffers: autotune() times the cost with and without the
     bounding-disk cull, checks that both give the same outputs word for word
     and captures the faster in a hipGraph; launch() replays it.  The
-    outputs are the attributes cost, or grad_pose, grad_footprint, residual."""
+    outputs are the attributes cost, or grad_pose, grad_footprint, residual.
+
+    The plan binds the caller's footprint, poses, points and grad_cost
+    tensors themselves (no copies): each launch reads their current values,
+    so in-place updates between launches are seen.  They must therefore be
+    contiguous float32 tensors (grad_cost with one entry per pose); without
+    grad_cost the plan owns a tensor of ones, exposed as ``grad_cost``."""
 
     def __init__(self, footprint, poses, points, backward: bool = False, grad_cost=None):
         import ctypes
+        for t, name in ((footprint, "footprint"), (poses, "poses"), (points, "points")):
+            if not t.is_contiguous():
+                raise ValueError(f"CostPlan binds the caller's {name}: pass a contiguous tensor")
+        if backward and grad_cost is not None and (grad_cost.dtype != torch.float32 or
+                                                   not grad_cost.is_contiguous()):
+            raise ValueError("CostPlan binds the caller's grad_cost: pass a contiguous float32 tensor")
         self.F, self.P, self.Q = _footprint(footprint), _poses(poses), _points(points)
         self.device = _dev(self.F)
         n, K, m = self.F.shape[0], self.P.shape[0], self.Q.shape[0]
@@ -88,8 +100,8 @@ class CostPlan:
         self.cost = None if backward else torch.zeros(max(K, 1), dtype=torch.float32, device=dev)
         self.grad_cost = None
         if backward:
-            g = grad_cost if grad_cost is not None else torch.ones(K, device=dev)
-            self.grad_cost = g.reshape(-1).to(torch.float32).contiguous()
+            g = grad_cost if grad_cost is not None else torch.ones(K, dtype=torch.float32, device=dev)
+            self.grad_cost = g.reshape(-1)  # a view of a contiguous tensor: the caller's storage
             if self.grad_cost.numel() != K:
                 raise ValueError("grad_cost must have one entry per pose")
         self.grad_pose = torch.zeros((max(K, 1), 3), dtype=torch.float32, device=dev) if backward else None

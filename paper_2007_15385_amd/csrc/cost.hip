@@ -333,11 +333,11 @@ __global__ __launch_bounds__(kBlock) void k_cost(const CostTab* __restrict__ tab
             }
             // table partials: p_0, then one wave sum per edge pressed on
             // (in increasing edge order), added by lane 0 in pose order
+            if (__ballot(emask != 0)) {  // some point of the wave presses on the footprint
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) emask |= __shfl_xor(emask, o, kWave);
-            emask = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(emask >> 32)) << 32) |
-                    (uint32_t)__builtin_amdgcn_readfirstlane((int)emask);
-            if (emask) {
+                for (int o = 32; o > 0; o >>= 1) emask |= __shfl_xor(emask, o, kWave);
+                emask = ((uint64_t)__builtin_amdgcn_readfirstlane((int)(emask >> 32)) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)emask);
                 s0x = wave_sum(s0x);
                 s0y = wave_sum(s0y);
                 if (lane == 0) {

@@ -384,3 +384,32 @@ def test_cost_large_footprints(P, oracle, n, symmetric):
         assert np.all(np.abs(p[1] - gp_ref) <= 1e-4 * (np.abs(gp_ref) + ap) + 1e-6)
     say(f"[stat] footprint n={n}: {int((c_ref > 0).sum())} of {K} poses penetrate")
 
+
+def test_cost_plan_reads_callers_tensors(P, scene):
+    """A cost plan binds the caller's tensors: an in-place update of the poses
+    between launches changes the replayed cost exactly as an eager call on
+    the new poses; non-contiguous inputs and a non-float32 grad_cost are
+    refused instead of being copied."""
+    F, Q, poses = scene
+    Ft, pt, Qt = (torch.from_numpy(F).cuda(), torch.from_numpy(poses.copy()).cuda(),
+                  torch.from_numpy(Q).cuda())
+    K = len(poses)
+    plan = P.CostPlan(Ft, pt, Qt)
+    try:
+        plan.launch()
+        torch.cuda.synchronize()
+        before = plan.cost[:K].clone()
+        pt[:, 0] += 0.75
+        pt[:, 2] -= 0.1
+        plan.launch()
+        torch.cuda.synchronize()
+        after = plan.cost[:K].cpu().numpy()
+        want = gpu_cost(P, F, pt.cpu().numpy(), Q)
+        assert np.array_equal(after.view(np.uint32), want.view(np.uint32))
+        assert not np.array_equal(after, before.cpu().numpy())
+    finally:
+        plan.close()
+    with pytest.raises(ValueError):
+        P.CostPlan(Ft, pt.t().contiguous().t(), Qt)
+    with pytest.raises(ValueError):
+        P.CostPlan(Ft, pt, Qt, backward=True, grad_cost=torch.ones(K, dtype=torch.float64).cuda())
