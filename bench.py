@@ -235,6 +235,17 @@ def run_extras(P, W, torch, stream, check):
             got = unpack_bits(lab_b[w0:w0 + (p1 - p0 + 31) // 32], p1 - p0)
             bad += int((got != want).sum())
         entry["mismatches_48_polygons"] = bad
+    # chunks of 512 points whose labels are all outside: the only chunks an
+    # early break (Section 5) taken by a whole wave could cut short
+    lab_all = plan.labels.cpu().numpy().view(np.uint32)
+    nch = zero = 0
+    for k in range(B.num_polygons):
+        s_k = int(B.pt_off[k + 1] - B.pt_off[k])
+        w0 = int(B.lbl_word_off[k])
+        for c in range(0, s_k, 512):
+            nch += 1
+            zero += int(not lab_all[w0 + c // 32: w0 + (min(s_k, c + 512) + 31) // 32].any())
+    entry["chunks_all_outside"] = round(zero / max(nch, 1), 6)
     out["uneven_batch"] = entry
     plan.close()
 
@@ -378,6 +389,21 @@ def run_extras(P, W, torch, stream, check):
             lab_r = P.pip_voronoi_raster(Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N, labels=lab_r)
         else:
             e["screen"] = "per_edge"
+        # the paper's early break (Section 5) taken by whole 512-pixel
+        # segments of the per-edge screen, reported apart (labels unchanged)
+        if e["screen"] == "per_edge":
+            base_lab = lab_r.clone()
+            P.set_option(P.PIP_OPT_EARLY_EXIT, 1)
+            try:
+                e["early_exit_ms"] = round(_time(torch, stream, lambda: P.pip_voronoi_raster(
+                    Vrt, -1.5, -1.5, 3.0 / N, 3.0 / N, N, N, labels=lab_r), reps=10), 4)
+            finally:
+                P.set_option(P.PIP_OPT_EARLY_EXIT, 0)
+            e["early_exit_labels_equal"] = bool(torch.equal(lab_r, base_lab))
+            # share of segments whose pixels are all outside (where it can fire)
+            seg_words = lab_r.reshape(N, N // 512, 16)
+            e["segments_all_outside"] = round(float((seg_words == 0).all(dim=2).float().mean()), 4)
+            lab_r = base_lab
         if check:
             rows = np.sort(rr.choice(N, 64, replace=False))
             got = lab_r.cpu().numpy().view(np.uint32)[rows]
@@ -557,6 +583,9 @@ def main() -> int:
                     help="skip the batched / all-pairs / cost / binary64 workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy a 1 GiB device buffer 3 times (counter calibration)")
+    ap.add_argument("--batch-run", action="store_true",
+                    help="for counter runs: the 4096-polygon uneven batch as an autotuned, "
+                         "graph-captured plan, then one more graph launch (the dispatch to read)")
     ap.add_argument("--traffic-run", action="store_true",
                     help="only one Voronoi launch per polygon size (for counter runs)")
     ap.add_argument("--ingest-counters", nargs=4,
@@ -576,8 +605,9 @@ def main() -> int:
         print(json.dumps({"copy_probe_bytes": x.numel() * 4}), flush=True)
         return 0
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no "
-              "multi-GPU form in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): the library has no "
+              "multi-GPU launch; shard point ranges or polygons over processes instead",
+              file=sys.stderr)
         return 2
 
     import torch
@@ -587,6 +617,18 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     P.load_library()
     dev = torch.device("cuda:0")
+    if args.batch_run:
+        B = W.uneven_batch()
+        t = [torch.from_numpy(a).to(dev) for a in (B.vtx_off, B.V, B.pt_off, B.Q, B.lbl_word_off)]
+        plan = P.BatchedPlan(*t)
+        cfg, ms = plan.autotune(reps=3)
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        print(json.dumps({"batch_run": {"tests": B.num_tests, "tile_shape": list(cfg),
+                                        "autotune_ms": round(ms, 4)}}), flush=True)
+        plan.close()
+        return 0
     torch.cuda.set_device(dev)
     m = int(args.points)
 

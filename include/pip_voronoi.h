@@ -158,13 +158,23 @@ typedef struct pip_index_s *pip_index;
  *     the per-edge screen (fewer edges leave more points between the radii).
  *     Not from the paper: a screen in front of its test, from the
  *     nearest-generator reading of Section 4. */
+/*   PIP_OPT_EARLY_EXIT: 1 lets the per-edge screen of pip_voronoi_raster stop
+ *     a 512-pixel segment after every 8 edges once each of its pixels has a
+ *     partial largest margin beyond its band (the paper's early break of
+ *     Section 5, taken by a whole wave; a margin maximum only grows with more
+ *     edges, so such a pixel is outside).  Labels are unchanged.  Default 0
+ *     (every edge evaluated, as in the paper's comparison of Section 6.2).
+ *     Streaming and batched launches do not take it: their 512-point chunks
+ *     are spatially random, so all of a chunk's points are almost never
+ *     outside. */
 typedef enum {
     PIP_OPT_MFMA_MIN_EDGES = 1,
     PIP_OPT_ALLPAIRS_CULL = 2,
     PIP_OPT_COST_CULL = 3,
     PIP_OPT_ALLPAIRS_PAIR = 4,
     PIP_OPT_COST_PAIR = 5,
-    PIP_OPT_RADIAL_MIN_EDGES = 6
+    PIP_OPT_RADIAL_MIN_EDGES = 6,
+    PIP_OPT_EARLY_EXIT = 7
 } pip_option;
 pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value);
 pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t *value);
@@ -217,6 +227,20 @@ pip_status pip_voronoi_radial_bounds(pip_ctx ctx, const double *V, int32_t n, fl
  */
 pip_status pip_screen_table(pip_ctx ctx, int32_t test, int32_t matrix, const double* V, int32_t n,
                             float* out, hipStream_t stream);
+
+/*
+ * Diagnostic for tests: the float32 matrix-core multiply-add that the
+ * matrix-core screen of pip_voronoi / pip_sign_of_offset evaluates (the margin
+ * of Eq. 11 as A X + B Y + c, Section 4), on caller-chosen operands, so that
+ * its rounding can be checked against the error bound the screen's band
+ * assumes (within 4 u of |A X| + |B Y| + |c|, u = 2^-24).
+ *   in   [count][5] float32 (device): A, B, c, X, Y per entry.
+ *   out  [count] float32 (device): the sum as v_mfma_f32_32x32x2f32 forms it
+ *        (entry e is row and column e % 32 of its group's product).
+ * Asynchronous on `stream`; allocates nothing.
+ */
+pip_status pip_mfma_margin_probe(pip_ctx ctx, const float *in, int64_t count, float *out,
+                                 hipStream_t stream);
 
 /*
  * Voronoi point-inclusion test (Section 4, Algorithm 5) of m points against

@@ -13,12 +13,12 @@ The functions carry the C names: :func:`polygon_to_generators`,
 """
 from __future__ import annotations
 
-from ._lib import (PIP_BATCHED_SCRATCH_BYTES, PIP_F32, PIP_F64, PIP_OPT_ALLPAIRS_CULL, PIP_OPT_ALLPAIRS_PAIR, PIP_OPT_COST_CULL, PIP_OPT_COST_PAIR, PIP_OPT_MFMA_MIN_EDGES, PIP_OPT_RADIAL_MIN_EDGES, PipError, lib_path, load_library,
+from ._lib import (PIP_BATCHED_SCRATCH_BYTES, PIP_F32, PIP_F64, PIP_OPT_ALLPAIRS_CULL, PIP_OPT_ALLPAIRS_PAIR, PIP_OPT_COST_CULL, PIP_OPT_COST_PAIR, PIP_OPT_MFMA_MIN_EDGES, PIP_OPT_RADIAL_MIN_EDGES, PIP_OPT_EARLY_EXIT, PipError, lib_path, load_library,
                    num_label_words, status_name)
 from .api import get_option, set_option
 from .api import (AllpairsPlan, BatchedPlan, LocateIndex, allpairs_workspace_bytes, batched_workspace_bytes,
                   convex_decompose, pieces_workspace_bytes, pip_voronoi_pieces,
-                  allpairs_csr_workspace_bytes, pip_voronoi_allpairs_csr, label_word_offsets, pip_poses_to_polygons,
+                  allpairs_csr_workspace_bytes, pip_voronoi_allpairs_csr, pip_mfma_margin_probe, label_word_offsets, pip_poses_to_polygons,
                   pip_ray_crossing, pip_sign_of_offset, pip_voronoi, pip_voronoi_allpairs,
                   pip_voronoi_batched, pip_voronoi_batched_noalloc, pip_voronoi_fp32_plain, pip_voronoi_max_margin, pip_voronoi_radial_bounds, pip_voronoi_raster,
                   pip_screen_table,
@@ -33,7 +33,7 @@ __all__ = [
     "pip_voronoi_batched", "pip_voronoi_batched_noalloc", "PIP_BATCHED_SCRATCH_BYTES",
     "batched_workspace_bytes", "label_word_offsets", "BatchedPlan",
     "LocateIndex", "AllpairsPlan", "convex_decompose", "pieces_workspace_bytes",
-    "pip_voronoi_pieces", "allpairs_csr_workspace_bytes", "pip_voronoi_allpairs_csr",
+    "pip_voronoi_pieces", "allpairs_csr_workspace_bytes", "pip_voronoi_allpairs_csr", "pip_mfma_margin_probe",
     "pip_poses_to_polygons", "pip_voronoi_allpairs", "allpairs_workspace_bytes", "pip_cost_fwd", "pip_cost_bwd",
-    "CollisionCost", "CostPlan", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "PIP_OPT_COST_PAIR", "PIP_OPT_RADIAL_MIN_EDGES", "set_option", "get_option",
+    "CollisionCost", "CostPlan", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "PIP_OPT_COST_PAIR", "PIP_OPT_RADIAL_MIN_EDGES", "PIP_OPT_EARLY_EXIT", "set_option", "get_option",
 ]

@@ -16,6 +16,7 @@ PIP_OPT_COST_CULL = 3
 PIP_OPT_ALLPAIRS_PAIR = 4
 PIP_OPT_COST_PAIR = 5
 PIP_OPT_RADIAL_MIN_EDGES = 6
+PIP_OPT_EARLY_EXIT = 7
 PIP_BATCHED_SCRATCH_BYTES = 32 << 20  # static scratch array of pip_voronoi_batched_noalloc
 
 STATUS_NAMES = {
@@ -54,6 +55,7 @@ SIGNATURES = {
     "pip_status_str": (_c.c_char_p, [_int]),
     "pip_last_error": (_c.c_char_p, [_vp]),
     "polygon_to_generators": (_int, [_vp, _vp, _i32, _vp, _vp, _vp]),
+    "pip_mfma_margin_probe": (_int, [_vp, _vp, _i64, _vp, _vp]),
     "pip_voronoi": (_int, [_vp, _vp, _i32, _vp, _int, _i64, _vp, _vp, _vp]),
     "pip_voronoi_radial_bounds": (_int, [_vp, _vp, _i32, _vp, _vp]),
     "pip_screen_table": (_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp]),

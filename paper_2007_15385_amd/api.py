@@ -548,6 +548,21 @@ def pip_voronoi_allpairs(V, Q, labels=None, counts=None, status=None, workspace=
     return labels, counts[:Pn], status[:Pn]
 
 
+def pip_mfma_margin_probe(entries):
+    """entries [count, 5] float32 (A, B, c, X, Y) -> [count] float32: A X +
+    B Y + c as the matrix-core screen's multiply-add forms it (diagnostic)."""
+    if entries.dtype != torch.float32 or entries.dim() != 2 or entries.shape[1] != 5 or \
+            not entries.is_contiguous():
+        raise ValueError("entries must be a contiguous float32 tensor of shape [count, 5]")
+    d = _dev(entries)
+    count = entries.shape[0]
+    out = torch.empty(max(count, 1), dtype=torch.float32, device=entries.device)
+    ctx = context(d)
+    s = _lib().pip_mfma_margin_probe(ctx, entries.data_ptr() if count else None, count,
+                                     out.data_ptr(), _stream(d))
+    _check(s, "pip_mfma_margin_probe", ctx)
+    return out[:count]
+
 def allpairs_csr_workspace_bytes(P: int, total_vertices: int) -> int:
     return int(_lib().pip_voronoi_allpairs_csr_workspace_bytes(int(P), int(total_vertices)))
 

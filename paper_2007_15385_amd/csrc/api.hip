@@ -26,6 +26,7 @@ struct pip_ctx_s {
     int cost_cull = 0;             // skip (pose, wave) pairs of the collision cost likewise
     int allpairs_pair = 0;         // antipodal edge pairs for centrally symmetric polygons
     int cost_pair = 0;             // the same for the collision cost's footprint
+    int early_exit = 0;            // the raster's early break (Section 5) when every pixel is outside
     void* scratch = nullptr;       // this device's copy of the static scratch array (no-alloc calls)
     hipError_t scratch_err = hipSuccess;  // why `scratch` is null, if it is
 };
@@ -364,6 +365,20 @@ pip_status pip_screen_table(pip_ctx ctx, int32_t test, int32_t matrix, const dou
     return PIP_OK;
 }
 
+pip_status pip_mfma_margin_probe(pip_ctx ctx, const float* in, int64_t count, float* out,
+                                 hipStream_t stream) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (count < 0) return fail(PIP_EINVAL, "count is negative");
+    if (count > (int64_t(1) << 40)) return fail(PIP_EUNSUPPORTED, "count is too large");
+    if (count > 0 && (!in || !out || !aligned(in, 4) || !aligned(out, 4)))
+        return fail(PIP_EINVAL, "in / out is NULL or misaligned");
+    DeviceGuard g(ctx->device);
+    if (g.err != hipSuccess) return hip_fail(g.err, "hipSetDevice");
+    hipError_t e = pipdev::launch_mfma_probe(in, count, out, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return PIP_OK;
+}
+
 pip_status pip_voronoi(pip_ctx ctx, const double* V, int32_t n, const void* Q, pip_dtype qdt,
                        int64_t m, uint32_t* labels, int32_t* status, hipStream_t stream) {
     return run_stream(ctx, pipdev::K_VORONOI, V, n, Q, qdt, m, labels, nullptr, status, stream);
@@ -427,7 +442,8 @@ pip_status pip_voronoi_raster(pip_ctx ctx, const double* V, int32_t n, double x0
         blocks = ctx->raster_blocks[radial];
     }
     pipdev::RasterGrid G{x0, y0, dx, dy, empty ? 0 : width, empty ? 0 : height};
-    hipError_t e = pipdev::launch_raster(V, n, G, labels, status, radial, blocks, stream);
+    hipError_t e = pipdev::launch_raster(V, n, G, labels, status, radial, ctx->early_exit, blocks,
+                                         stream);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return PIP_OK;
 }
@@ -1483,6 +1499,10 @@ pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
                 return fail(PIP_EINVAL, "PIP_OPT_RADIAL_MIN_EDGES must be in [0, %d]", PIP_MAX_EDGES + 1);
             ctx->radial_min_edges = (int)value;
             return PIP_OK;
+        case PIP_OPT_EARLY_EXIT:
+            if (value != 0 && value != 1) return fail(PIP_EINVAL, "PIP_OPT_EARLY_EXIT must be 0 or 1");
+            ctx->early_exit = (int)value;
+            return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
@@ -1507,6 +1527,9 @@ pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
             return PIP_OK;
         case PIP_OPT_RADIAL_MIN_EDGES:
             *value = ctx->radial_min_edges;
+            return PIP_OK;
+        case PIP_OPT_EARLY_EXIT:
+            *value = ctx->early_exit;
             return PIP_OK;
     }
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);

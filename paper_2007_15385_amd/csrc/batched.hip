@@ -412,6 +412,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             }
 #pragma unroll
             for (int j = 4 * h; j < 4 * h + 4; ++j) {
+                if (unc[j] == 0) continue;  // wave-uniform: no undecided point in this slot
                 if ((unc[j] >> lane) & 1ull) {
                     const int slot = qcount + __popcll(unc[j] & lt);
                     q.k[slot] = cur_k;

@@ -25,6 +25,7 @@ struct StreamLaunch {
 
 hipError_t launch_stream_mfma(const StreamLaunch& L);
 hipError_t stream_mfma_max_blocks_per_cu(int kind, int n, int* out);
+hipError_t launch_mfma_probe(const float* in, int64_t count, float* out, hipStream_t stream);
 
 hipError_t launch_stream(const StreamLaunch& L);
 hipError_t radial_max_blocks_per_cu(int* out);
@@ -173,7 +174,8 @@ struct RasterGrid {
     int64_t width, height;
 };
 hipError_t launch_raster(const double* V, int n, const RasterGrid& G, uint32_t* labels,
-                         int32_t* status, int radial, int max_blocks, hipStream_t stream);
+                         int32_t* status, int radial, int early, int max_blocks,
+                         hipStream_t stream);
 hipError_t raster_max_blocks_per_cu(int radial, int* out);
 struct CostLayout {
     size_t tab, part_cost, part_pose, part_gen, stage;

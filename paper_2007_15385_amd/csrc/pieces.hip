@@ -250,6 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_pieces(const double* __restrict__ V,
             const uint64_t lt = lanemask_lt();
 #pragma unroll
             for (int j = 0; j < kP32; ++j) {
+                if (unc[j] == 0) continue;  // wave-uniform: no undecided point in this slot
                 if ((unc[j] >> lane) & 1ull) {
                     const int slot = qcount + __popcll(unc[j] & lt);
                     queue_c[wv][slot] = (kc << 9) | (uint32_t)(lane + kWave * j);

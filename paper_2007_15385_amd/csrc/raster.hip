@@ -48,10 +48,14 @@ using namespace pipdev;
 
 namespace {
 
+// early: the paper's early break (Section 5) in wave form -- every 8 edges
+// the per-edge screen stops once every pixel of the segment is already
+// decided outside (its partial largest margin beyond its band; the margin
+// only grows with more edges), leaving the same labels.
 template <bool RADIAL>
 __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V, int n,
                                                  RasterGrid G, uint32_t* __restrict__ labels,
-                                                 int32_t* __restrict__ status) {
+                                                 int32_t* __restrict__ status, int early) {
     __shared__ PolyLds S;
     __shared__ RadialTab R;
     __shared__ float KC_s;                                // band constant with the X term
@@ -159,6 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
         float X[kP32], M[kP32];
 #pragma unroll
         for (int j = 0; j < kP32; ++j) X[j] = fmaf((float)(i0 + lane + kWave * j), dxf, bxf);
+        // the band of every pixel, needed by the early break before the loop ends
+        const auto band = [&](int j) { return fmaf(KQ, X[j] * X[j], fmaf(KA, fabsf(X[j]), eY)); };
         uint64_t rin[kP32], ramb[kP32];  // radial decisions: inside, between the radii
         uint64_t any_amb = ~0ull;
         if constexpr (RADIAL) {
@@ -190,6 +196,12 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
                              fmaf(a.w, X[j], c.w));
         }
         for (int e = 4; e < n4; e += 4) {
+            if (early && (e & 7) == 0) {  // wave-uniform: all pixels already outside?
+                uint64_t open = 0;
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) open |= __ballot(!(M[j] > band(j)));
+                if (open == 0) break;
+            }
             const float4 a = A4[e / 4], c = C4[e / 4];
 #pragma unroll
             for (int j = 0; j < kP32; ++j) {
@@ -204,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
 #pragma unroll
         for (int j = 0; j < kP32; ++j) {
             if (any_amb) {
-                const float E = fmaf(KQ, X[j] * X[j], fmaf(KA, fabsf(X[j]), eY));
+                const float E = band(j);
                 inm[j] = __ballot(M[j] < -E);
                 unc[j] = __ballot(!(fabsf(M[j]) > E));
             } else {
@@ -251,15 +263,18 @@ __global__ __launch_bounds__(kBlock) void k_raster(const double* __restrict__ V,
 namespace pipdev {
 
 hipError_t launch_raster(const double* V, int n, const RasterGrid& G, uint32_t* labels,
-                         int32_t* status, int radial, int max_blocks, hipStream_t stream) {
+                         int32_t* status, int radial, int early, int max_blocks,
+                         hipStream_t stream) {
     const int64_t segs = (G.width + kChunk32 - 1) / kChunk32 * G.height;
     const int64_t want = (segs + kWavesPerBlock - 1) / kWavesPerBlock;
     int grid = (int)(want < max_blocks ? want : max_blocks);
     if (grid < 1) grid = 1;
     if (radial)
-        hipLaunchKernelGGL(k_raster<true>, dim3(grid), dim3(kBlock), 0, stream, V, n, G, labels, status);
+        hipLaunchKernelGGL(k_raster<true>, dim3(grid), dim3(kBlock), 0, stream, V, n, G, labels, status,
+                           early);
     else
-        hipLaunchKernelGGL(k_raster<false>, dim3(grid), dim3(kBlock), 0, stream, V, n, G, labels, status);
+        hipLaunchKernelGGL(k_raster<false>, dim3(grid), dim3(kBlock), 0, stream, V, n, G, labels, status,
+                           early);
     return hipGetLastError();
 }
 

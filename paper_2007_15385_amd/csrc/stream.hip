@@ -260,6 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
                 const uint64_t lt = lanemask_lt();
 #pragma unroll
                 for (int j = 0; j < kPPL; ++j) {
+                    if (unc[j] == 0) continue;  // wave-uniform: no undecided point in this slot
                     if ((unc[j] >> lane) & 1ull) {
                         const int slot = qcount + __popcll(unc[j] & lt);
                         queue[wv][slot] = base + lane + kWave * j;
@@ -405,6 +406,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
                 const uint64_t lt = lanemask_lt();
 #pragma unroll
                 for (int j = 0; j < kP32; ++j) {
+                    if (unc[j] == 0) continue;  // wave-uniform: no undecided point in this slot
                     if ((unc[j] >> lane) & 1ull) {
                         const int slot = qcount + __popcll(unc[j] & lt);
                         queue_c[wv][slot] = (k << 9) | (uint32_t)(lane + kWave * j);

@@ -50,6 +50,12 @@ __device__ __forceinline__ float reg_max(const floatx16& d) {
     for (int i = 3; i < R; i += 2) r = fmaxf(fmaxf(r, d[i]), d[i + 1 < R ? i + 1 : 0]);
     return r;
 }
+// the first product's max continued over the second product (one chain)
+__device__ __forceinline__ float reg_max_cont(float r, const floatx16& d) {
+#pragma unroll
+    for (int i = 0; i < 16; i += 2) r = fmaxf(fmaxf(r, d[i]), d[i + 1]);
+    return r;
+}
 template <int R>
 __device__ __forceinline__ float reg_min(const floatx16& d) {
     float r = fminf(fminf(d[0], d[1]), d[2]);
@@ -134,6 +140,9 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
 #pragma unroll
         for (int j = 0; j < kP32; ++j) {
             const float X = p[j].x - ox, Y = p[j].y - oy;
+            // the band first: X and Y are then free for the operand swap
+            const float r2 = fmaf(X, X, Y * Y);
+            const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X), fmaf(KB, fabsf(Y), KC)));
             float bA, bB;  // operands of groups A and B
             swap_halves(X, Y, bA, bB);
             float xA, xB, nA = 0.f, nB = 0.f;
@@ -162,8 +171,7 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
                     const floatx16 d1 =
                         __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[1], bop, c_op[1], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    const float x0 = reg_max<RR>(d0), x1 = reg_max<RR>(d1);
-                    mx = x0 > x1 ? x0 : x1;
+                    mx = reg_max_cont(reg_max<RR>(d0), d1);
                     if constexpr (KIND == K_SOO) {
                         const float n0 = reg_min<RR>(d0), n1 = reg_min<RR>(d1);
                         mn = n0 < n1 ? n0 : n1;
@@ -186,8 +194,6 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
                     mn = u < w ? u : w;
                 }
             }
-            const float r2 = fmaf(X, X, Y * Y);
-            const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X), fmaf(KB, fabsf(Y), KC)));
             uint64_t in, out;
             if constexpr (KIND == K_SOO) {
                 in = __ballot(mx < -E) | __ballot(mn > E);
@@ -222,6 +228,7 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
             const uint64_t lt = lanemask_lt();
 #pragma unroll
             for (int j = 0; j < kP32; ++j) {
+                if (unc[j] == 0) continue;  // wave-uniform: no undecided point in this slot
                 if ((unc[j] >> lane) & 1ull) {
                     const int slot = qcount + __popcll(unc[j] & lt);
                     queue_c[wv][slot] = (k << 9) | (uint32_t)(lane + kWave * j);
@@ -260,6 +267,37 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
                             stride);
 }
 
+// Diagnostic: the float32 matrix-core multiply-add of the screen above on
+// caller-chosen operands.  Entry e (5 floats: A, B, c, X, Y) is row e % 32 of
+// the A operand and column e % 32 of the B operand of its group's product,
+// with c in the accumulator row e % 32; out[e] is the product's diagonal
+// element, A X + B Y + c as v_mfma_f32_32x32x2f32 forms it.
+__global__ __launch_bounds__(kWave) void k_mfma_probe(const float* __restrict__ in, int64_t count,
+                                                      float* __restrict__ out) {
+    const int lane = threadIdx.x;
+    const int col = lane & 31, half = lane >> 5;
+    const int64_t g0 = (int64_t)blockIdx.x * 32;
+    const int64_t e = g0 + col;
+    const bool ok = e < count;
+    const float* r = in + 5 * (ok ? e : 0);
+    const float a = ok ? (half ? r[1] : r[0]) : 0.f;  // A[row col][k = half]
+    const float b = ok ? (half ? r[4] : r[3]) : 0.f;  // B[k = half][column col]
+    floatx16 c;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int64_t row = g0 + 8 * (q / 4) + 4 * half + (q % 4);
+        c[q] = row < count ? in[5 * row + 2] : 0.f;
+    }
+    const floatx16 d = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    // the diagonal element (row col, column col) sits in the lane of column
+    // col whose half holds row col, register 4 (col / 8) + col % 4
+    const int q = 4 * (col / 8) + col % 4;
+    float v = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v = i == q ? d[i] : v;
+    if (ok && half == (col % 8) / 4) out[e] = v;
+}
+
 template <int KIND, int R>
 hipError_t launch_t(const StreamLaunch& L) {
     const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
@@ -293,6 +331,13 @@ namespace pipdev {
 
 hipError_t launch_stream_mfma(const StreamLaunch& L) {
     return L.kind == K_SOO ? launch_kind<K_SOO>(L) : launch_kind<K_VORONOI>(L);
+}
+
+hipError_t launch_mfma_probe(const float* in, int64_t count, float* out, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mfma_probe, dim3((unsigned)((count + 31) / 32)), dim3(kWave), 0, stream,
+                       in, count, out);
+    return hipGetLastError();
 }
 
 hipError_t stream_mfma_max_blocks_per_cu(int kind, int n, int* out) {

@@ -164,3 +164,26 @@ def test_raster_full_size_64_edges_rows(P, oracle):
         img = oracle.voronoi_raster(V, -1.5, -1.5 + int(j) * (3.0 / N), 3.0 / N, 3.0 / N, N, 1)
         want = np.packbits(img[0], bitorder="little").view(np.uint32)
         assert np.array_equal(got[j], want), f"row {j}"
+
+
+@pytest.mark.parametrize("n", [8, 24, 64])
+def test_raster_early_exit_same_labels(P, oracle, screen, n):
+    """The early break of the per-edge screen (PIP_OPT_EARLY_EXIT) leaves
+    every pixel label unchanged: a polygon covering part of a 4096 x 512
+    raster (rows above, below and beside it are all outside), a raster far
+    from the polygon, and one whose every pixel is inside."""
+    rng = np.random.default_rng(700 + n)
+    V = W.circle_polygon(n, 1.0, (0.05, -0.1), rng)
+    grids = [(-3.0, -1.5, 6.0 / 4096, 3.0 / 512, 4096, 512),
+             (5.0, 5.0, 1e-3, 1e-3, 3000, 64),
+             (-0.3, -0.3, 0.6 / 1024, 0.6 / 64, 1024, 64)]
+    for g in grids:
+        P.set_option(P.PIP_OPT_EARLY_EXIT, 0)
+        base = raster_gpu(P, V, *g)
+        P.set_option(P.PIP_OPT_EARLY_EXIT, 1)
+        try:
+            early = raster_gpu(P, V, *g)
+        finally:
+            P.set_option(P.PIP_OPT_EARLY_EXIT, 0)
+        assert np.array_equal(early, base), g
+        assert np.array_equal(base, raster_want(oracle, V, *g)), g
