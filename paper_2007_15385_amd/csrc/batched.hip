@@ -227,6 +227,9 @@ __device__ __forceinline__ void load_chunk_b(const float2* __restrict__ Q, const
     }
 }
 
+// RADIAL: the batch holds polygons that take the radial pre-screen; without
+// them the kernel carries no radial state (fewer scalar registers live).
+template <bool RADIAL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_batched_voronoi(
     const ChunkDesc* __restrict__ desc, const PolyHdr* __restrict__ hdr,
     const float4* __restrict__ coef, const double2* __restrict__ gen,
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     load_chunk_b(Q, d, lane, pa);
     int cb = 0;  // LDS table of the current polygon; rows past n4 are never read
     coefs[wv][1][lane] = coef[coef_base(vtx_off, d.k) + lane];
-    if (lane < kRadialRow) rtab[wv][1][lane] = radial[(int64_t)d.k * kRadialRow + lane];
+    if (RADIAL && lane < kRadialRow) rtab[wv][1][lane] = radial[(int64_t)d.k * kRadialRow + lane];
 
     int cur_k = -1;
     float ox = 0.f, oy = 0.f, KQ = 0.f, KA = 0.f, KB = 0.f, KC = 0.f;
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         const int cnt = __builtin_amdgcn_readfirstlane(cd.count);
         const bool full = cnt >= kChunk32;
         uint64_t inm[kP32], unc[kP32];
-        if (use_radial) {
+        if (RADIAL && use_radial) {
             // Radial pre-screen (radial.hpp): most points are decided from r2
             // against their octant's radii; the rest are compacted one per lane
             // and screened against every edge, 64 at a time.
@@ -437,7 +440,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         KB = H.KB;
         KC = H.KC;
         n4 = __builtin_amdgcn_readfirstlane(H.n4);
-        use_radial = __builtin_amdgcn_readfirstlane(H.radial);
+        use_radial = RADIAL ? __builtin_amdgcn_readfirstlane(H.radial) : 0;
         ptk = pt_off[k];
         wk = lbl_word_off[k];
         cb ^= 1;
@@ -487,10 +490,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
             float rn = 0.f;
             if (newpoly) cn = coef[coef_base(vtx_off, d2.k) + lane];
-            if (newpoly && lane < kRadialRow) rn = radial[(int64_t)d2.k * kRadialRow + lane];
+            if (RADIAL && newpoly && lane < kRadialRow) rn = radial[(int64_t)d2.k * kRadialRow + lane];
             load_chunk_b(Q, d2, lane, pb);
             if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
-            if (newpoly && lane < kRadialRow) rtab[wv][cb ^ 1][lane] = rn;
+            if (RADIAL && newpoly && lane < kRadialRow) rtab[wv][cb ^ 1][lane] = rn;
         }
         int64_t g3 = more ? next_chunk(g2, pos2) : g2;
         bool more3 = more && g3 < nchunks;
@@ -508,10 +511,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
             float4 cn = make_float4(0.f, 0.f, 0.f, 0.f);
             float rn = 0.f;
             if (newpoly) cn = coef[coef_base(vtx_off, d2.k) + lane];
-            if (newpoly && lane < kRadialRow) rn = radial[(int64_t)d2.k * kRadialRow + lane];
+            if (RADIAL && newpoly && lane < kRadialRow) rn = radial[(int64_t)d2.k * kRadialRow + lane];
             load_chunk_b(Q, d2, lane, pa);
             if (newpoly) coefs[wv][cb ^ 1][lane] = cn;
-            if (newpoly && lane < kRadialRow) rtab[wv][cb ^ 1][lane] = rn;
+            if (RADIAL && newpoly && lane < kRadialRow) rtab[wv][cb ^ 1][lane] = rn;
         }
         g3 = more ? next_chunk(g2, pos2) : g2;
         more3 = more && g3 < nchunks;
@@ -562,7 +565,8 @@ hipError_t launch_batched(const BatchedDev& D, int G, int blocks, hipStream_t st
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_fill_chunks, dim3(pblocks), dim3(kBlock), 0, stream, D);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batched_voronoi, dim3(blocks), dim3(kBlock), 0, stream,
+    auto kern = D.radial_min > 0 ? k_batched_voronoi<true> : k_batched_voronoi<false>;
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kBlock), 0, stream,
                        reinterpret_cast<const ChunkDesc*>(D.desc), D.hdr, D.coef, D.gen, D.vtx_off,
                        D.pt_off, D.lbl_word_off, reinterpret_cast<const float2*>(D.Q), D.labels,
                        D.misc, D.radial, G);
@@ -570,7 +574,8 @@ hipError_t launch_batched(const BatchedDev& D, int G, int blocks, hipStream_t st
 }
 
 hipError_t batched_max_blocks_per_cu(int* out) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)k_batched_voronoi, kBlock, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(out, (const void*)k_batched_voronoi<true>,
+                                                        kBlock, 0);
 }
 
 }  // namespace pipdev
