@@ -151,18 +151,29 @@ def margin_statistics(P, torch, o, V, Vt, Qt, Q, matrix, sample=1 << 22):
     tab = P.pip_screen_table(Vt, 0, 0).cpu().numpy()
     ox, oy = np.float32(tab[0]), np.float32(tab[1])
     n4 = int(tab[6])
-    rows = tab[8:8 + 4 * n4].reshape(n4, 4).astype(np.float64)
-    X = (Q[:S, 0] - ox).astype(np.float64)  # float32 subtraction, as the screen
-    Y = (Q[:S, 1] - oy).astype(np.float64)
+    rows = tab[12:12 + 4 * n4].reshape(n4, 4).astype(np.float64)
+    X32 = Q[:S, 0] - ox  # float32 subtraction, as the screen
+    Y32 = Q[:S, 1] - oy
+    X = X32.astype(np.float64)
+    Y = Y32.astype(np.float64)
     al, be, ga = np.abs(rows[:, 0]).max(), np.abs(rows[:, 1]).max(), np.abs(rows[:, 2]).max()
     err = np.abs(mh - D)
     scale = al * np.abs(X) + be * np.abs(Y) + ga
 
-    def band(t):
-        return (float(t[2]) * (X * X + Y * Y) + float(t[3]) * np.abs(X) + float(t[4]) * np.abs(Y)
+    def band(t, fold):
+        full = (float(t[2]) * (X * X + Y * Y) + float(t[3]) * np.abs(X) + float(t[4]) * np.abs(Y)
                 + float(t[5]))
-    E = band(tab)
-    Eb = band(P.pip_screen_table(Vt, 0, 1).cpu().numpy()) if matrix else E
+        if not fold:
+            return full
+        # the vector screen's band: in 512-point chunks whose float32
+        # |X| + |Y| are all within RQ, max(KA, KB) (|X| + |Y|) + KC
+        s32 = (np.abs(X32) + np.abs(Y32)).astype(np.float64)
+        lin = max(float(t[3]), float(t[4])) * s32 + float(t[5])
+        ok = np.repeat((s32[: S // 512 * 512].reshape(-1, 512) <= float(t[8])).all(axis=1), 512)
+        ok = np.concatenate([ok, np.zeros(S - ok.size, dtype=bool)])
+        return np.where(ok, lin, full)
+    E = band(tab, not matrix)
+    Eb = band(P.pip_screen_table(Vt, 0, 1).cpu().numpy(), False) if matrix else E
     return {"sample_points": S,
             "max_err_u": round(float((err / scale).max() / 2.0 ** -24), 4),
             "max_err_over_band": round(float((err / E).max()), 4),

@@ -214,11 +214,13 @@ pip_status pip_voronoi_radial_bounds(pip_ctx ctx, const double *V, int32_t n, fl
  * band is not in the paper; it keeps Algorithm 5's binary64 answer while
  * the margins of Eq. 11 are computed in float32).
  *   V    [n][2] binary64 vertices, 3 <= n <= PIP_MAX_EDGES.
- *   out  [8 + 4 n4] float32 (device), n4 = n rounded up to a multiple of 4:
- *        out[0..8) = o_x, o_y (the local origin, fl32(p_0)), KQ, KA, KB, KC
+ *   out  [12 + 4 n4] float32 (device), n4 = n rounded up to a multiple of 4:
+ *        out[0..12) = o_x, o_y (the local origin, fl32(p_0)), KQ, KA, KB, KC
  *        (the band E = KQ (X^2 + Y^2) + KA |X| + KB |Y| + KC, X, Y the
- *        point's float32 local coordinates), n4, the polygon's pip_status;
- *        then n4 rows (A_i, B_i, -C_i, 0) with margin
+ *        point's float32 local coordinates), n4, the polygon's pip_status,
+ *        RQ (Voronoi: where |X| + |Y| <= RQ for every point of a screened
+ *        chunk, the vector screens use E = max(KA, KB) (|X| + |Y|) + KC),
+ *        then three zeros; then n4 rows (A_i, B_i, -C_i, 0) with margin
  *        m_i = A_i X + B_i Y - C_i (Voronoi; rows past n repeat edge 0) or
  *        (-dV_y, dV_x, -R_i, 0) (sign of offset).  A point is decided in
  *        float32 only when its largest margin clears the band.

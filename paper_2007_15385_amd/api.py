@@ -143,14 +143,15 @@ def pip_voronoi_radial_bounds(V):
 
 
 def pip_screen_table(V, test: int = 0, matrix: int = 0):
-    """The float32 screen table (float32 tensor [8 + 4 n4]): o_x, o_y, KQ,
-    KA, KB, KC, n4, status, then n4 rows (A, B, -C, 0) for the Voronoi test
-    (test 0) or the sign-of-offset rows (test 1), as the vector (matrix 0)
-    or matrix-core (matrix 1) screen derives them."""
+    """The float32 screen table (float32 tensor [12 + 4 n4]): o_x, o_y, KQ,
+    KA, KB, KC, n4, status, RQ (the band's fold radius), 0, 0, 0, then n4
+    rows (A, B, -C, 0) for the Voronoi test (test 0) or the sign-of-offset
+    rows (test 1), as the vector (matrix 0) or matrix-core (matrix 1) screen
+    derives them."""
     V = _polygon(V)
     d = _dev(V)
     n4 = (V.shape[0] + 3) // 4 * 4
-    out = torch.empty(8 + 4 * n4, dtype=torch.float32, device=V.device)
+    out = torch.empty(12 + 4 * n4, dtype=torch.float32, device=V.device)
     ctx = context(d)
     s = _lib().pip_screen_table(ctx, int(test), int(matrix), V.data_ptr(), V.shape[0],
                                 out.data_ptr(), _stream(d))

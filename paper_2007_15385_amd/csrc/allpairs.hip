@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n_uni
                 H.npair = 0;
                 H.radial = 0;
                 H.row = 0;
-                H.gen = 0;
+                H.RQ = 0.f;
                 hdr[k] = H;
                 if (status) status[k] = bad;
                 if (counts) counts[k] = 0;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_uniform(int64_t P, int n_uni
         H.npair = npair;
         H.radial = 0;
         H.row = (int)row0;
-        H.gen = (int)gen0;
+        H.RQ = 0.f;
         hdr[k] = H;
         if (status) status[k] = L.status;
         if (counts) counts[k] = 0;  // k_allpairs accumulates into it
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_allpairs(const PolyHdr* __restrict__
             }
             if (any_unc) {  // rare: re-decide in binary64 (Algorithm 5)
                 const int nk = CSR ? n_s[p] : n;
-                const double2* G = gen + (CSR ? (int64_t)hdr[k].gen : k * (n + 1));
+                const double2* G = gen + (CSR ? (int64_t)hdr[k].row - 2 * (int64_t)k : k * (n + 1));
 #pragma unroll
                 for (int j = 0; j < kP32; ++j) {
                     const uint64_t unc = ~(inm[j] | __ballot(M[j] > E)) & live[j];

@@ -64,6 +64,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
             H->status = bad;
             H->ox = H->oy = 0.f;
             H->KQ = H->KA = H->KB = H->KC = __builtin_huge_valf();
+            H->RQ = 0.f;
             H->radial = 0;
             D.chunk_cnt[k] = chunks;
             if (D.status) D.status[k] = bad;
@@ -106,6 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare_batched(BatchedDev D) {
         H->KA = L.KA;
         H->KB = L.KB;
         H->KC = L.KC;
+        H->RQ = L.RQ;
         H->n = n;
         H->n4 = n4;
         H->status = L.status;
@@ -263,8 +265,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
     if (RADIAL && lane < kRadialRow) rtab[wv][1][lane] = radial[(int64_t)d.k * kRadialRow + lane];
 
     int cur_k = -1;
-    float ox = 0.f, oy = 0.f, KQ = 0.f, KA = 0.f, KB = 0.f, KC = 0.f;
-    int n4 = 0;
+    // band of the current polygon: KQ r2 + KS (|X| + |Y|) + KC with
+    // KS = max(KA, KB) (at least the band), and its fold radius RQ
+    float ox = 0.f, oy = 0.f, KQ = 0.f, KS = 0.f, KC = 0.f, RQ = 0.f;
+    int n4 = 0, ne = 0;  // edge rows: padded to 4, and evaluated (n rounded up to 2)
     int use_radial = 0;
     int64_t ptk = 0, wk = 0;
     int qcount = 0;
@@ -331,7 +335,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
                         M = fmaxf(fmaxf(M, m2), m3);
                     }
                     const float r2 = fmaf(X, X, Y * Y);
-                    const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X), fmaf(KB, fabsf(Y), KC)));
+                    const float E = fmaf(KQ, r2, fmaf(KS, fabsf(X) + fabsf(Y), KC));
                     res = M < -E ? 1 : (M > E ? 0 : 2);
                 }
                 cres[wv][lane] = res;
@@ -348,7 +352,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-        } else if (n4 > 0) {
+        } else if (ne > 0) {
             float X[kP32], Y[kP32], Mx[kP32];
             {  // edges 0-3 (n4 >= 4) start the max
                 const float4* cf = coefs[wv][cb];
@@ -364,7 +368,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
                     Mx[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
                 }
             }
-            for (int e = 4; e < n4; e += 4) {
+            // rows 4.. in fours, then a last pair: n rounded up to 2 rows are
+            // evaluated (a pad row repeats edge 0 and leaves the max unchanged)
+            int e = 4;
+            for (; e + 4 <= ne; e += 4) {
                 const float4* cf = coefs[wv][cb];
                 const float4 c0 = cf[e + 0], c1 = cf[e + 1], c2 = cf[e + 2], c3 = cf[e + 3];
 #pragma unroll
@@ -377,13 +384,44 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
                     Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
                 }
             }
+            if (e < ne) {
+                const float4* cf = coefs[wv][cb];
+                const float4 c0 = cf[e + 0], c1 = cf[e + 1];
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                    const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
+                }
+            }
+            // band: when |X| + |Y| <= RQ for every point of the chunk, the
+            // quadratic term is inside the linear constants and
+            // E = max(KA, KB) (|X| + |Y|) + KC (wave-uniform branch; a NaN sum
+            // is dropped by the max and gives a NaN band: undecided)
+            float sxy[kP32];
+            float acc = 0.0f;
 #pragma unroll
             for (int j = 0; j < kP32; ++j) {
-                const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
-                const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
-                const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
-                inm[j] = in;
-                unc[j] = ~(in | out);
+                sxy[j] = fabsf(X[j]) + fabsf(Y[j]);
+                acc = fmaxf(acc, sxy[j]);
+            }
+            if (__ballot(acc > RQ) == 0) {
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const float E = fmaf(KS, sxy[j], KC);
+                    const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
+                    inm[j] = in;
+                    unc[j] = ~(in | out);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+                    const float E = fmaf(KQ, r2, fmaf(KS, sxy[j], KC));
+                    const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
+                    inm[j] = in;
+                    unc[j] = ~(in | out);
+                }
             }
         } else {
 #pragma unroll
@@ -436,10 +474,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) voi
         ox = H.ox;
         oy = H.oy;
         KQ = H.KQ;
-        KA = H.KA;
-        KB = H.KB;
+        KS = fmaxf(H.KA, H.KB);
         KC = H.KC;
+        RQ = H.RQ;
         n4 = __builtin_amdgcn_readfirstlane(H.n4);
+        ne = (__builtin_amdgcn_readfirstlane(H.n) + 1) & ~1;
         use_radial = RADIAL ? __builtin_amdgcn_readfirstlane(H.radial) : 0;
         ptk = pt_off[k];
         wk = lbl_word_off[k];

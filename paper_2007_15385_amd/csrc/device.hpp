@@ -65,6 +65,7 @@ struct alignas(32) PolyLds {
     };
     float ox, oy;                    // float32 local origin
     float KQ, KA, KB, KC;            // band E = KQ (X^2 + Y^2) + KA |X| + KB |Y| + KC
+    float RQ;                        // for |X|, |Y| <= RQ, E = KA |X| + KB |Y| + KC suffices
     int n, n4, status;
 };
 
@@ -216,7 +217,7 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
     const int i = lane < n ? lane : 0;
     const double d2x = g0x - dox, d2y = g0y - doy;
     const double d2 = d2x * d2x + d2y * d2y;
-    double qa = 0.0, qb = 0.0, qc = 0.0, KA = 0.0, KB = 0.0, KC = 0.0, KQ = 0.0;
+    double qa = 0.0, qb = 0.0, qc = 0.0, KA = 0.0, KB = 0.0, KC = 0.0, KQ = 0.0, RQ = 0.0;
     bool finite_ok = true;
     if (kind == K_VORONOI || kind == K_MARGIN) {
         const double hx = gx - g0x, hy = gy - g0y;
@@ -239,6 +240,18 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         KC = (f32_factor * kU32 * gam + 4.1 * kU64 * (G2 + d2) +
               4.0001 * kU64 * (6.0 * d2 + 2.0 * H2) + kEpsAbs * (1.0 + alpha + beta)) * infl;
         KQ = 24.01 * kU64 * infl;
+        // Fold of the quadratic term into the linear ones near the polygon:
+        // for |X|, |Y| <= RQ, KQ (X^2 + Y^2) <= KQ RQ (|X| + |Y|).  RQ is the
+        // largest power of two with KQ RQ <= 2^-8 min(KA, KB) (at most 2^60),
+        // so the linear constants grow by at most 2^-8 of themselves.
+        const double kmin = fmin(KA, KB);
+        if (kmin > 0.0 && kmin < 1e300) {
+            int e = 0;
+            (void)frexp(kmin * 0.00390625 / KQ, &e);  // value in [2^(e-1), 2^e)
+            RQ = ldexp(1.0, e - 1 < 60 ? e - 1 : 60);
+            KA += KQ * RQ;
+            KB += KQ * RQ;
+        }
         (void)qa; (void)qb; (void)qc;
     } else if (kind == K_SOO) {
         const int j = prev_edge(i, n);
@@ -282,6 +295,7 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         S.KA = round_up_f32(KA);
         S.KB = round_up_f32(KB);
         S.KC = bad ? __builtin_huge_valf() : round_up_f32(KC);
+        S.RQ = (float)RQ;  // a power of two (or 0), exact in float32
         S.n4 = (n + 3) & ~3;
         S.status = status;
     }

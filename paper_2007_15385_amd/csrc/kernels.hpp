@@ -40,7 +40,10 @@ struct alignas(16) PolyHdr {
     float cx, cy, rad;     // disk (float32 centre, radius rounded up) containing the polygon
     int npair;             // > 0: coefficient rows are npair antipodal edge pairs (all pairs)
     int radial;            // 1: the batched screen takes the radial pre-screen (table usable)
-    int row, gen;          // all pairs over CSR polygons: first coefficient row and generator
+    int row;               // all pairs over CSR polygons: first coefficient row (the
+                           // polygon's generators start at row - 2k for polygon k)
+    float RQ;              // band fold radius (batched): for |X| + |Y| <= RQ the band is
+                           // max(KA, KB) (|X| + |Y|) + KC
 };
 
 // Device view of a batched request plus its workspace.

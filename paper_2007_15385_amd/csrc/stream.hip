@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
 
     const float ox = S.ox, oy = S.oy;
-    const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC;
+    const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC, RQ = S.RQ, KS = fmaxf(KA, KB);
     const int n4 = __builtin_amdgcn_readfirstlane(S.n4);
     int qcount = 0;
 
@@ -362,24 +362,49 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
             }
         }
         uint64_t inm[kP32], unc[kP32];
+        // Voronoi: when |X| + |Y| <= RQ for every point of the chunk, the
+        // band's quadratic term is inside its linear constants and
+        // E = KS (|X| + |Y|) + KC with KS = max(KA, KB) (wave-uniform branch;
+        // a NaN sum is dropped by the max and gives a NaN band: undecided)
+        bool fold = false;
+        float sxy[kP32];
+        if constexpr (KIND == K_VORONOI) {
+            float acc = 0.0f;
 #pragma unroll
-        for (int j = 0; j < kP32; ++j) {
-            if constexpr (KIND == K_PLAIN) {
-                inm[j] = __ballot(Mx[j] <= 0.0f);
-                unc[j] = 0;
-            } else {
-                const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
-                const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
-                uint64_t in, out;
-                if constexpr (KIND == K_SOO) {
-                    in = __ballot(Mx[j] < -E) | __ballot(Mn[j] > E);
-                    out = __ballot(Mx[j] > E) & __ballot(Mn[j] < -E);
-                } else {
-                    in = __ballot(Mx[j] < -E);
-                    out = __ballot(Mx[j] > E);
-                }
+            for (int j = 0; j < kP32; ++j) {
+                sxy[j] = fabsf(X[j]) + fabsf(Y[j]);
+                acc = fmaxf(acc, sxy[j]);
+            }
+            fold = __ballot(acc > RQ) == 0;
+        }
+        if (fold) {
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                const float E = fmaf(KS, sxy[j], KC);
+                const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
                 inm[j] = in;
                 unc[j] = ~(in | out);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kP32; ++j) {
+                if constexpr (KIND == K_PLAIN) {
+                    inm[j] = __ballot(Mx[j] <= 0.0f);
+                    unc[j] = 0;
+                } else {
+                    const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+                    const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
+                    uint64_t in, out;
+                    if constexpr (KIND == K_SOO) {
+                        in = __ballot(Mx[j] < -E) | __ballot(Mn[j] > E);
+                        out = __ballot(Mx[j] > E) & __ballot(Mn[j] < -E);
+                    } else {
+                        in = __ballot(Mx[j] < -E);
+                        out = __ballot(Mx[j] > E);
+                    }
+                    inm[j] = in;
+                    unc[j] = ~(in | out);
+                }
             }
         }
         if (!full) {
@@ -684,8 +709,8 @@ __global__ __launch_bounds__(kWave) void k_radial_bounds(const double* __restric
 
 // polygon_to_generators: one wave derives p_0 and the n outer generators.
 // The float32 screen table of one polygon as the streaming screens derive
-// it: out[0..8) = ox, oy, KQ, KA, KB, KC, n4, status; then n4 rows
-// (A, B, -C, 0) (Voronoi) or (-dV_y, dV_x, -R, 0) (sign of offset).
+// it: out[0..12) = ox, oy, KQ, KA, KB, KC, n4, status, RQ, 0, 0, 0; then n4
+// rows (A, B, -C, 0) (Voronoi) or (-dV_y, dV_x, -R, 0) (sign of offset).
 __global__ __launch_bounds__(kWave) void k_screen_table(const double* __restrict__ V, int n,
                                                        int kind, double factor,
                                                        float* __restrict__ out) {
@@ -705,13 +730,15 @@ __global__ __launch_bounds__(kWave) void k_screen_table(const double* __restrict
         out[5] = S.KC;
         out[6] = (float)S.n4;
         out[7] = (float)S.status;
+        out[8] = S.RQ;
+        out[9] = out[10] = out[11] = 0.0f;
     }
     for (int r = lane; r < S.n4; r += kWave) {
         const float4 c = S.coef[r];
-        out[8 + 4 * r] = c.x;
-        out[9 + 4 * r] = c.y;
-        out[10 + 4 * r] = c.z;
-        out[11 + 4 * r] = c.w;
+        out[12 + 4 * r] = c.x;
+        out[13 + 4 * r] = c.y;
+        out[14 + 4 * r] = c.z;
+        out[15 + 4 * r] = c.w;
     }
 }
 
