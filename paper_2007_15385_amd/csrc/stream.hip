@@ -474,6 +474,107 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
 }
 
 // ----------------------------------------------------------------------------
+// Ray crossing (Section 2.1, Algorithm 1) for float32 points, in binary64
+// with exactly the plain algorithm's comparisons and products (so its labels
+// are the oracle's without a band): the vertex-above flags and each point's
+// crossing parity are kept as wave masks (one bit per lane, in scalar
+// registers), so that per edge and point the vector units run the vertex
+// comparison, the two products and the difference of the line test and one
+// comparison; the rest is scalar mask logic.  A float32 pre-screen of the
+// line test would not be cheaper here: binary64 vector operations issue at
+// the unpacked float32 rate on this device, and the screen needs as many.
+// 512-point chunks, non-temporal loads, the next chunk in flight.
+__global__ __launch_bounds__(kBlock) void k_ray32(const double* __restrict__ V, int n,
+                                                 const float2* __restrict__ Q, int64_t m,
+                                                 uint32_t* __restrict__ labels,
+                                                 int32_t* __restrict__ status) {
+    __shared__ PolyLds S;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int64_t nfull = m / kChunk32;
+    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+    int64_t chunk = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+
+    double2 vt = make_double2(0.0, 0.0);
+    if (tid < n) vt = make_double2(V[2 * tid], V[2 * tid + 1]);
+    float2 pa[kP32], pb[kP32];
+    if (nfull > 0) load_full32(Q, chunk < nfull ? chunk : nfull - 1, lane, pa);
+    if (tid < n) S.vtx[tid] = vt;
+    if (tid == 0) S.n = n;
+    __syncthreads();
+    if (wv == 0) prepare_polygon(S, K_RAY, lane);
+    __syncthreads();
+    if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
+    const int nv = __builtin_amdgcn_readfirstlane(S.n);
+    const double ylast = S.vtx[nv - 1].y;  // start vertex of edge 0
+
+    auto process = [&](const float2(&p)[kP32], int64_t ch, int rem) {
+        double x[kP32], y[kP32];
+        uint64_t above[kP32], cross[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            x[j] = (double)p[j].x;
+            y[j] = (double)p[j].y;
+            above[j] = __ballot(ylast > y[j]);
+            cross[j] = 0;
+        }
+        for (int e = 0; e < nv; ++e) {
+            const double4 r = S.ray[e];  // (V'_y, V_y, dV_x, dV_y): edge V' -> V
+            const double R = S.rhs[e];
+            if (r.y > r.x) {  // going up: on the left when LHS > RHS
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const uint64_t ab = __ballot(r.y > y[j]);
+                    const double L = y[j] * r.z - x[j] * r.w;
+                    cross[j] ^= (ab ^ above[j]) & __ballot(L > R);
+                    above[j] = ab;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const uint64_t ab = __ballot(r.y > y[j]);
+                    const double L = y[j] * r.z - x[j] * r.w;
+                    cross[j] ^= (ab ^ above[j]) & __ballot(L < R);
+                    above[j] = ab;
+                }
+            }
+        }
+        uint64_t inm[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            const bool ok = lane + kWave * j < rem && isfinite(x[j]) && isfinite(y[j]);
+            inm[j] = cross[j] & __ballot(ok);
+        }
+        const uint32_t w = chunk_word32(inm);
+        const int nw = (rem + 31) / 32;
+        if (lane < nw) labels[ch * kWords32 + lane] = w;
+    };
+
+    for (;;) {
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pb);
+        process(pa, chunk, kChunk32);
+        chunk += stride;
+        if (chunk >= nfull) break;
+        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pa);
+        process(pb, chunk, kChunk32);
+        chunk += stride;
+    }
+    if (chunk == nfull && nfull * kChunk32 < m) {  // the partial chunk
+        const int64_t base = nfull * kChunk32;
+        const int rem = (int)(m - base);
+        float2 pt[kP32];
+#pragma unroll
+        for (int j = 0; j < kP32; ++j) {
+            const int r = lane + kWave * j;
+            pt[j] = Q[base + (r < rem ? r : rem - 1)];
+        }
+        process(pt, chunk, rem);
+    }
+}
+
+// ----------------------------------------------------------------------------
 // Voronoi with the radial pre-screen (radial.hpp).  The fast path of a chunk
 // costs a few operations per point: r2 = fl32(X^2 + Y^2), the octant's two
 // thresholds from LDS and three compares decide every point closer to p_0
@@ -770,6 +871,16 @@ hipError_t launch_stream32_t(const StreamLaunch& L) {
     return hipGetLastError();
 }
 
+hipError_t launch_ray32(const StreamLaunch& L) {
+    const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
+    const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
+    int grid = (int)(want < L.max_blocks ? want : L.max_blocks);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_ray32, dim3(grid), dim3(kBlock), 0, L.stream, L.V, L.n,
+                       static_cast<const float2*>(L.Q), L.m, L.labels, L.status);
+    return hipGetLastError();
+}
+
 hipError_t launch_stream32_radial(const StreamLaunch& L) {
     const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
     const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -805,7 +916,7 @@ hipError_t launch_stream(const StreamLaunch& L) {
         case K_SOO:
             return f64 ? launch_stream_t<K_SOO, double>(L) : launch_stream32_t<K_SOO>(L);
         case K_RAY:
-            return f64 ? launch_stream_t<K_RAY, double>(L) : launch_stream_t<K_RAY, float>(L);
+            return f64 ? launch_stream_t<K_RAY, double>(L) : launch_ray32(L);
         case K_PLAIN:
             return f64 ? launch_stream_t<K_PLAIN, double>(L) : launch_stream32_t<K_PLAIN>(L);
         case K_MARGIN:
@@ -833,7 +944,7 @@ hipError_t stream_max_blocks_per_cu(int kind, int qdt, int* out) {
     switch (kind) {
         case K_VORONOI: f = f64 ? (const void*)k_stream<K_VORONOI, double> : (const void*)k_stream32<K_VORONOI>; break;
         case K_SOO: f = f64 ? (const void*)k_stream<K_SOO, double> : (const void*)k_stream32<K_SOO>; break;
-        case K_RAY: f = f64 ? (const void*)k_stream<K_RAY, double> : (const void*)k_stream<K_RAY, float>; break;
+        case K_RAY: f = f64 ? (const void*)k_stream<K_RAY, double> : (const void*)k_ray32; break;
         case K_PLAIN: f = f64 ? (const void*)k_stream<K_PLAIN, double> : (const void*)k_stream32<K_PLAIN>; break;
         case K_MARGIN: f = f64 ? (const void*)k_stream<K_MARGIN, double> : (const void*)k_stream<K_MARGIN, float>; break;
         default: return hipErrorInvalidValue;
