@@ -266,7 +266,11 @@ pip_status pip_sign_of_offset(pip_ctx ctx, const double *V, int32_t n, const voi
 
 /* Ray-crossing test (Section 2.1, Algorithm 1) with a ray towards +x; the
  * polygon may be any simple polygon (convexity is not required or checked).
- * Evaluated directly in binary64. */
+ * Labels equal Algorithm 1 in binary64.  Float64 points are evaluated in
+ * binary64 directly; for float32 points the in-range test compares Q_y with
+ * each vertex height rounded up to float32 (exact for float32 Q_y), the
+ * line test is screened in float32 against the sign-of-offset band, and the
+ * points with an undecided line test are re-decided in binary64. */
 pip_status pip_ray_crossing(pip_ctx ctx, const double *V, int32_t n, const void *Q,
                             pip_dtype qdt, int64_t m, uint32_t *labels, int32_t *status,
                             hipStream_t stream);

@@ -256,7 +256,7 @@ pip_status run_stream(pip_ctx ctx, int kind, const double* V, int32_t n, const v
                  : L.mfma   ? mfma_blocks(ctx, kind, n)
                             : persistent_blocks(ctx, kind, (int)qdt);
     L.stream = stream;
-    if (qdt == PIP_F32 && kind != pipdev::K_RAY && kind != pipdev::K_MARGIN) {
+    if (qdt == PIP_F32 && kind != pipdev::K_MARGIN) {
         // the recheck queues code a point as (chunk iteration << 9 | point):
         // every wave must walk fewer than 2^23 chunks of 512 points
         const int64_t nchunks = (m + 511) / 512;

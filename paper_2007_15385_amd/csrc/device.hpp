@@ -82,6 +82,18 @@ __device__ __forceinline__ float round_up_f32(double d) {
     return f;
 }
 
+__device__ __forceinline__ float ceil_f32(double d) {
+    // smallest float32 >= d (any sign); +-inf and NaN map to themselves
+    float f = (float)d;
+    if ((double)f < d) {
+        const uint32_t b = __float_as_uint(f);
+        f = f == 0.0f ? __uint_as_float(1u)             // smallest positive subnormal
+          : f > 0.0f  ? __uint_as_float(b + 1u)         // away from zero
+                      : __uint_as_float(b - 1u);        // towards zero
+    }
+    return f;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
@@ -253,13 +265,23 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
             KB += KQ * RQ;
         }
         (void)qa; (void)qb; (void)qc;
-    } else if (kind == K_SOO) {
+    } else if (kind == K_SOO || kind == K_RAY32) {
         const int j = prev_edge(i, n);
         const double2 v = S.vtx[i], w = S.vtx[j];
         const double dVx = v.x - w.x, dVy = v.y - w.y;
         const double R = (w.y - doy) * dVx - (w.x - dox) * dVy;
         const float p = (float)(-dVy), q = (float)dVx, r = (float)R;
-        S.coef[lane] = make_float4(p, q, -r, 0.0f);
+        // ray crossing: the row negated for an edge going down (V_y <= V'_y,
+        // on the left when LHS < RHS), so that "on the left" is s > 0 for
+        // every edge (negation is exact); and the height of the edge's end
+        // vertex rounded up to float32, c: for a float32 Q_y, V_y > Q_y
+        // exactly when c > Q_y
+        if (kind == K_RAY32) {
+            const float sg = v.y > w.y ? 1.0f : -1.0f;
+            S.coef[lane] = make_float4(sg * p, sg * q, -(sg * r), ceil_f32(v.y));
+        } else {
+            S.coef[lane] = make_float4(p, q, -r, 0.0f);
+        }
         finite_ok = isfinite(p) && isfinite(q) && isfinite(r) && fabs((double)p) < kCoefLimit &&
                     fabs((double)q) < kCoefLimit && fabs((double)r) < kCoefLimit;
         const double pm = wave_max(fabs((double)p));
@@ -278,7 +300,8 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         KC = (f32_factor * kU32 * rm + 3.1 * kU64 * kR + 2.0001 * kU64 * k64 +
               kEpsAbs * (1.0 + pm + qm)) * infl;
         KQ = kEpsAbs;  // no quadratic term; keeps X^2 overflow -> E = +inf
-    } else if (kind == K_RAY) {
+    }
+    if (kind == K_RAY || kind == K_RAY32) {
         const int j = prev_edge(i, n);
         const double2 v = S.vtx[i], w = S.vtx[j];
         const double dVx = v.x - w.x, dVy = v.y - w.y;
@@ -332,6 +355,21 @@ __device__ inline bool sign_of_offset64(double px, double py, const double2* vtx
         if (LHS < RHS) count += 1;
     }
     return ((count % n) == 0) && isfinite(px) && isfinite(py);
+}
+
+// Ray crossing of one point in binary64 (Section 2.1, Algorithm 1) from the
+// ray table (V'_y, V_y, dV_x, dV_y) and RHS of each edge V' -> V.
+__device__ inline bool ray_crossing64(double px, double py, const double4* ray, const double* rhs,
+                                      int n) {
+    bool cross = false;
+    for (int e = 0; e < n; ++e) {
+        const double4 r = ray[e];
+        const bool inr = (r.y > py) != (r.x > py);
+        const double L = py * r.z - px * r.w;
+        const bool left = r.y > r.x ? (L > rhs[e]) : (L < rhs[e]);
+        cross = cross != (inr && left);
+    }
+    return cross && isfinite(px) && isfinite(py);
 }
 
 // ----------------------------------------------------------------------------

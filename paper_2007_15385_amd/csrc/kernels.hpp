@@ -5,7 +5,9 @@
 
 namespace pipdev {
 
-enum TestKind : int { K_VORONOI = 0, K_SOO = 1, K_RAY = 2, K_PLAIN = 3, K_MARGIN = 4 };
+// K_RAY32: ray crossing with the float32 pre-screen (prepared like K_SOO, plus
+// the binary64 ray table and the rounded-up vertex heights).
+enum TestKind : int { K_VORONOI = 0, K_SOO = 1, K_RAY = 2, K_PLAIN = 3, K_MARGIN = 4, K_RAY32 = 5 };
 
 struct StreamLaunch {
     int kind;             // TestKind

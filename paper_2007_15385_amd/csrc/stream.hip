@@ -315,7 +315,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
         if constexpr (KIND == K_PLAIN)
             prepare_plain(S, lane);
         else
-            prepare_polygon(S, KIND, lane);
+            prepare_polygon(S, KIND == K_RAY ? K_RAY32 : KIND, lane);
     }
     __syncthreads();
     if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
@@ -323,87 +323,149 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     const float ox = S.ox, oy = S.oy;
     const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC, RQ = S.RQ, KS = fmaxf(KA, KB);
     const int n4 = __builtin_amdgcn_readfirstlane(S.n4);
+    const int nv = __builtin_amdgcn_readfirstlane(S.n);
     int qcount = 0;
 
     // Screen the 8 points of every lane of this wave's k-th chunk `ch`;
     // `rem` points of it exist (>= 512 for a full chunk).
     auto process = [&](const float2(&p)[kP32], int64_t ch, int64_t rem) {
         const bool full = rem >= kChunk32;
-        float X[kP32], Y[kP32], Mx[kP32], Mn[kP32];
-        {  // edges 0-3 (n4 >= 4) start the max / min
-            const float4 c0 = S.coef[0], c1 = S.coef[1], c2 = S.coef[2], c3 = S.coef[3];
+        uint64_t inm[kP32], unc[kP32];
+        if constexpr (KIND == K_RAY) {
+            // Ray crossing (Algorithm 1).  In range: the vertex-above flags
+            // c > Q_y with c the vertex height rounded up to float32 (exact
+            // for float32 Q_y).  On the left: the sign-of-offset margin s of
+            // the edge (its row negated for an edge going down) against its
+            // band, decided when |s| > E; a point with an undecided edge goes
+            // to binary64.  Flags, parities and the undecided set are wave
+            // masks, four slots per pass over the edges.
+            float X[kP32], Y[kP32], E[kP32];
+            const float clast = S.coef[nv - 1].w;  // start vertex of edge 0
 #pragma unroll
             for (int j = 0; j < kP32; ++j) {
                 X[j] = p[j].x - ox;
                 Y[j] = p[j].y - oy;
-                const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
-                const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
-                const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
-                const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
-                Mx[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
-                if constexpr (KIND == K_SOO) Mn[j] = fminf(fminf(fminf(m0, m1), m2), m3);
+                const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+                E[j] = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
             }
-        }
-        for (int e = 4; e < n4; e += 4) {
-            const float4 c0 = S.coef[e + 0], c1 = S.coef[e + 1];
-            const float4 c2 = S.coef[e + 2], c3 = S.coef[e + 3];
 #pragma unroll
-            for (int j = 0; j < kP32; ++j) {
-                const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
-                const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
-                const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
-                const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
-                Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
-                Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
-                if constexpr (KIND == K_SOO) {
-                    Mn[j] = fminf(fminf(Mn[j], m0), m1);
-                    Mn[j] = fminf(fminf(Mn[j], m2), m3);
+            for (int h = 0; h < 2; ++h) {
+                uint64_t above[4], cross[4], amb[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    above[t] = __ballot(clast > p[4 * h + t].y);
+                    cross[t] = 0;
+                    amb[t] = 0;
+                }
+                // one edge: its end vertex's above flags into `ab`; an
+                // undecided line test marks the point whether the edge is in
+                // range or not (a superset: only points within the band of
+                // an edge's line)
+                auto edge = [&](const float4& c, const uint64_t(&prev)[4], uint64_t(&ab)[4]) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int j = 4 * h + t;
+                        ab[t] = __ballot(c.w > p[j].y);
+                        const float sm = fmaf(c.x, X[j], fmaf(c.y, Y[j], c.z));
+                        amb[t] |= __ballot(!(fabsf(sm) > E[j]));
+                        cross[t] ^= (ab[t] ^ prev[t]) & __ballot(sm > E[j]);
+                    }
+                };
+                int e = 0;
+                for (; e + 2 <= nv; e += 2) {  // rows negated for edges going down
+                    uint64_t mid[4];
+                    edge(S.coef[e], above, mid);
+                    edge(S.coef[e + 1], mid, above);
+                }
+                if (e < nv) {
+                    uint64_t last[4];
+                    edge(S.coef[e], above, last);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int j = 4 * h + t;
+                    // a non-finite point is outside (never queued)
+                    const uint64_t fin = __ballot(isfinite(p[j].x) && isfinite(p[j].y));
+                    unc[j] = amb[t] & fin;
+                    inm[j] = cross[t] & fin & ~amb[t];
                 }
             }
-        }
-        uint64_t inm[kP32], unc[kP32];
-        // Voronoi: when |X| + |Y| <= RQ for every point of the chunk, the
-        // band's quadratic term is inside its linear constants and
-        // E = KS (|X| + |Y|) + KC with KS = max(KA, KB) (wave-uniform branch;
-        // a NaN sum is dropped by the max and gives a NaN band: undecided)
-        bool fold = false;
-        float sxy[kP32];
-        if constexpr (KIND == K_VORONOI) {
-            float acc = 0.0f;
-#pragma unroll
-            for (int j = 0; j < kP32; ++j) {
-                sxy[j] = fabsf(X[j]) + fabsf(Y[j]);
-                acc = fmaxf(acc, sxy[j]);
-            }
-            fold = __ballot(acc > RQ) == 0;
-        }
-        if (fold) {
-#pragma unroll
-            for (int j = 0; j < kP32; ++j) {
-                const float E = fmaf(KS, sxy[j], KC);
-                const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
-                inm[j] = in;
-                unc[j] = ~(in | out);
-            }
         } else {
-#pragma unroll
-            for (int j = 0; j < kP32; ++j) {
-                if constexpr (KIND == K_PLAIN) {
-                    inm[j] = __ballot(Mx[j] <= 0.0f);
-                    unc[j] = 0;
-                } else {
-                    const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
-                    const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
-                    uint64_t in, out;
+            float X[kP32], Y[kP32], Mx[kP32], Mn[kP32];
+            {  // edges 0-3 (n4 >= 4) start the max / min
+                const float4 c0 = S.coef[0], c1 = S.coef[1], c2 = S.coef[2], c3 = S.coef[3];
+    #pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    X[j] = p[j].x - ox;
+                    Y[j] = p[j].y - oy;
+                    const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                    const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                    const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+                    const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+                    Mx[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
+                    if constexpr (KIND == K_SOO) Mn[j] = fminf(fminf(fminf(m0, m1), m2), m3);
+                }
+            }
+            for (int e = 4; e < n4; e += 4) {
+                const float4 c0 = S.coef[e + 0], c1 = S.coef[e + 1];
+                const float4 c2 = S.coef[e + 2], c3 = S.coef[e + 3];
+    #pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const float m0 = fmaf(c0.x, X[j], fmaf(c0.y, Y[j], c0.z));
+                    const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
+                    const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
+                    const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
+                    Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
                     if constexpr (KIND == K_SOO) {
-                        in = __ballot(Mx[j] < -E) | __ballot(Mn[j] > E);
-                        out = __ballot(Mx[j] > E) & __ballot(Mn[j] < -E);
-                    } else {
-                        in = __ballot(Mx[j] < -E);
-                        out = __ballot(Mx[j] > E);
+                        Mn[j] = fminf(fminf(Mn[j], m0), m1);
+                        Mn[j] = fminf(fminf(Mn[j], m2), m3);
                     }
+                }
+            }
+            // Voronoi: when |X| + |Y| <= RQ for every point of the chunk, the
+            // band's quadratic term is inside its linear constants and
+            // E = KS (|X| + |Y|) + KC with KS = max(KA, KB) (wave-uniform branch;
+            // a NaN sum is dropped by the max and gives a NaN band: undecided)
+            bool fold = false;
+            float sxy[kP32];
+            if constexpr (KIND == K_VORONOI) {
+                float acc = 0.0f;
+    #pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    sxy[j] = fabsf(X[j]) + fabsf(Y[j]);
+                    acc = fmaxf(acc, sxy[j]);
+                }
+                fold = __ballot(acc > RQ) == 0;
+            }
+            if (fold) {
+    #pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    const float E = fmaf(KS, sxy[j], KC);
+                    const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
                     inm[j] = in;
                     unc[j] = ~(in | out);
+                }
+            } else {
+    #pragma unroll
+                for (int j = 0; j < kP32; ++j) {
+                    if constexpr (KIND == K_PLAIN) {
+                        inm[j] = __ballot(Mx[j] <= 0.0f);
+                        unc[j] = 0;
+                    } else {
+                        const float r2 = fmaf(X[j], X[j], Y[j] * Y[j]);
+                        const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
+                        uint64_t in, out;
+                        if constexpr (KIND == K_SOO) {
+                            in = __ballot(Mx[j] < -E) | __ballot(Mn[j] > E);
+                            out = __ballot(Mx[j] > E) & __ballot(Mn[j] < -E);
+                        } else {
+                            in = __ballot(Mx[j] < -E);
+                            out = __ballot(Mx[j] > E);
+                        }
+                        inm[j] = in;
+                        unc[j] = ~(in | out);
+                    }
                 }
             }
         }
@@ -470,107 +532,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
         if (qcount > 0)
             flush_queue32<KIND>(S, queue_c[wv], queue_x[wv], queue_y[wv], qcount, labels, lane,
                                 c0, stride);
-    }
-}
-
-// ----------------------------------------------------------------------------
-// Ray crossing (Section 2.1, Algorithm 1) for float32 points, in binary64
-// with exactly the plain algorithm's comparisons and products (so its labels
-// are the oracle's without a band): the vertex-above flags and each point's
-// crossing parity are kept as wave masks (one bit per lane, in scalar
-// registers), so that per edge and point the vector units run the vertex
-// comparison, the two products and the difference of the line test and one
-// comparison; the rest is scalar mask logic.  A float32 pre-screen of the
-// line test would not be cheaper here: binary64 vector operations issue at
-// the unpacked float32 rate on this device, and the screen needs as many.
-// 512-point chunks, non-temporal loads, the next chunk in flight.
-__global__ __launch_bounds__(kBlock) void k_ray32(const double* __restrict__ V, int n,
-                                                 const float2* __restrict__ Q, int64_t m,
-                                                 uint32_t* __restrict__ labels,
-                                                 int32_t* __restrict__ status) {
-    __shared__ PolyLds S;
-    const int tid = threadIdx.x;
-    const int lane = tid & (kWave - 1);
-    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
-    const int64_t nfull = m / kChunk32;
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    int64_t chunk = (int64_t)blockIdx.x * kWavesPerBlock + wv;
-
-    double2 vt = make_double2(0.0, 0.0);
-    if (tid < n) vt = make_double2(V[2 * tid], V[2 * tid + 1]);
-    float2 pa[kP32], pb[kP32];
-    if (nfull > 0) load_full32(Q, chunk < nfull ? chunk : nfull - 1, lane, pa);
-    if (tid < n) S.vtx[tid] = vt;
-    if (tid == 0) S.n = n;
-    __syncthreads();
-    if (wv == 0) prepare_polygon(S, K_RAY, lane);
-    __syncthreads();
-    if (status && blockIdx.x == 0 && tid == 0) *status = S.status;
-    const int nv = __builtin_amdgcn_readfirstlane(S.n);
-    const double ylast = S.vtx[nv - 1].y;  // start vertex of edge 0
-
-    auto process = [&](const float2(&p)[kP32], int64_t ch, int rem) {
-        double x[kP32], y[kP32];
-        uint64_t above[kP32], cross[kP32];
-#pragma unroll
-        for (int j = 0; j < kP32; ++j) {
-            x[j] = (double)p[j].x;
-            y[j] = (double)p[j].y;
-            above[j] = __ballot(ylast > y[j]);
-            cross[j] = 0;
-        }
-        for (int e = 0; e < nv; ++e) {
-            const double4 r = S.ray[e];  // (V'_y, V_y, dV_x, dV_y): edge V' -> V
-            const double R = S.rhs[e];
-            if (r.y > r.x) {  // going up: on the left when LHS > RHS
-#pragma unroll
-                for (int j = 0; j < kP32; ++j) {
-                    const uint64_t ab = __ballot(r.y > y[j]);
-                    const double L = y[j] * r.z - x[j] * r.w;
-                    cross[j] ^= (ab ^ above[j]) & __ballot(L > R);
-                    above[j] = ab;
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < kP32; ++j) {
-                    const uint64_t ab = __ballot(r.y > y[j]);
-                    const double L = y[j] * r.z - x[j] * r.w;
-                    cross[j] ^= (ab ^ above[j]) & __ballot(L < R);
-                    above[j] = ab;
-                }
-            }
-        }
-        uint64_t inm[kP32];
-#pragma unroll
-        for (int j = 0; j < kP32; ++j) {
-            const bool ok = lane + kWave * j < rem && isfinite(x[j]) && isfinite(y[j]);
-            inm[j] = cross[j] & __ballot(ok);
-        }
-        const uint32_t w = chunk_word32(inm);
-        const int nw = (rem + 31) / 32;
-        if (lane < nw) labels[ch * kWords32 + lane] = w;
-    };
-
-    for (;;) {
-        if (chunk >= nfull) break;
-        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pb);
-        process(pa, chunk, kChunk32);
-        chunk += stride;
-        if (chunk >= nfull) break;
-        load_full32(Q, chunk + stride < nfull ? chunk + stride : chunk, lane, pa);
-        process(pb, chunk, kChunk32);
-        chunk += stride;
-    }
-    if (chunk == nfull && nfull * kChunk32 < m) {  // the partial chunk
-        const int64_t base = nfull * kChunk32;
-        const int rem = (int)(m - base);
-        float2 pt[kP32];
-#pragma unroll
-        for (int j = 0; j < kP32; ++j) {
-            const int r = lane + kWave * j;
-            pt[j] = Q[base + (r < rem ? r : rem - 1)];
-        }
-        process(pt, chunk, rem);
     }
 }
 
@@ -871,16 +832,6 @@ hipError_t launch_stream32_t(const StreamLaunch& L) {
     return hipGetLastError();
 }
 
-hipError_t launch_ray32(const StreamLaunch& L) {
-    const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
-    const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
-    int grid = (int)(want < L.max_blocks ? want : L.max_blocks);
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_ray32, dim3(grid), dim3(kBlock), 0, L.stream, L.V, L.n,
-                       static_cast<const float2*>(L.Q), L.m, L.labels, L.status);
-    return hipGetLastError();
-}
-
 hipError_t launch_stream32_radial(const StreamLaunch& L) {
     const int64_t nchunks = (L.m + kChunk32 - 1) / kChunk32;
     const int64_t want = (nchunks + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -916,7 +867,7 @@ hipError_t launch_stream(const StreamLaunch& L) {
         case K_SOO:
             return f64 ? launch_stream_t<K_SOO, double>(L) : launch_stream32_t<K_SOO>(L);
         case K_RAY:
-            return f64 ? launch_stream_t<K_RAY, double>(L) : launch_ray32(L);
+            return f64 ? launch_stream_t<K_RAY, double>(L) : launch_stream32_t<K_RAY>(L);
         case K_PLAIN:
             return f64 ? launch_stream_t<K_PLAIN, double>(L) : launch_stream32_t<K_PLAIN>(L);
         case K_MARGIN:
@@ -944,7 +895,7 @@ hipError_t stream_max_blocks_per_cu(int kind, int qdt, int* out) {
     switch (kind) {
         case K_VORONOI: f = f64 ? (const void*)k_stream<K_VORONOI, double> : (const void*)k_stream32<K_VORONOI>; break;
         case K_SOO: f = f64 ? (const void*)k_stream<K_SOO, double> : (const void*)k_stream32<K_SOO>; break;
-        case K_RAY: f = f64 ? (const void*)k_stream<K_RAY, double> : (const void*)k_ray32; break;
+        case K_RAY: f = f64 ? (const void*)k_stream<K_RAY, double> : (const void*)k_stream32<K_RAY>; break;
         case K_PLAIN: f = f64 ? (const void*)k_stream<K_PLAIN, double> : (const void*)k_stream32<K_PLAIN>; break;
         case K_MARGIN: f = f64 ? (const void*)k_stream<K_MARGIN, double> : (const void*)k_stream<K_MARGIN, float>; break;
         default: return hipErrorInvalidValue;

@@ -80,6 +80,8 @@ __device__ inline void flush_queue32(const PolyLds& S, const uint32_t* qc, const
         bool in;
         if constexpr (KIND == K_VORONOI)
             in = voronoi64(x, y, S.gen, S.n);
+        else if constexpr (KIND == K_RAY)
+            in = ray_crossing64(x, y, S.ray, S.rhs, S.n);
         else
             in = sign_of_offset64(x, y, S.vtx, S.n);
         if (in) or_label_bit(labels, idx >> 5, (uint32_t)(idx & 31));
