@@ -643,6 +643,58 @@ pip_status pip_plan_create_cost(pip_ctx ctx, int32_t backward, const float *foot
                                 float *cost, const float *grad_cost, float *grad_pose,
                                 float *grad_footprint, float *residual, pip_plan *out);
 
+/* One creator for every plan kind (the plan interface of the boundary as a
+ * single call): `desc` points to the descriptor of `kind` and holds exactly
+ * the arguments of the typed creator, which it calls:
+ *   PIP_PLAN_BATCHED   pip_batched_desc   -> pip_plan_create_batched
+ *   PIP_PLAN_ALLPAIRS  pip_allpairs_desc  -> pip_plan_create_allpairs
+ *   PIP_PLAN_COST_FWD  pip_cost_desc      -> pip_plan_create_cost (backward 0)
+ *   PIP_PLAN_COST_BWD  pip_cost_desc      -> pip_plan_create_cost (backward 1)
+ * The descriptor is read during the call only; the buffers it names are
+ * bound to the plan as by the typed creator.  Errors: PIP_EINVAL for a
+ * NULL ctx, desc or out or an unknown kind, else the typed creator's. */
+typedef enum {
+    PIP_PLAN_BATCHED = 0,
+    PIP_PLAN_ALLPAIRS = 1,
+    PIP_PLAN_COST_FWD = 2,
+    PIP_PLAN_COST_BWD = 3
+} pip_plan_kind;
+typedef struct {
+    int32_t P;
+    const int64_t *vtx_off;       /* [P+1] */
+    const double *V;              /* [total_vertices][2] */
+    int64_t total_vertices;
+    const int64_t *pt_off;        /* [P+1] */
+    const float *Q;               /* [total_points][2] */
+    int64_t total_points;
+    const int64_t *lbl_word_off;  /* [P+1] */
+    uint32_t *labels;
+    int32_t *status;              /* [P], optional */
+} pip_batched_desc;
+typedef struct {
+    int32_t P, n;
+    const double *V;              /* [P][n][2] */
+    const float *Q;               /* [m][2] */
+    int64_t m;
+    uint32_t *labels;             /* [P][ceil(m/32)] */
+    int32_t *counts;              /* [P] */
+    int32_t *status;              /* [P], optional */
+} pip_allpairs_desc;
+typedef struct {
+    const float *footprint;       /* [n][2] */
+    int32_t n;
+    const float *pose;            /* [K][3] */
+    int64_t K;
+    const float *Q;               /* [m][2] */
+    int64_t m;
+    float *cost;                  /* forward: [K] */
+    const float *grad_cost;       /* backward: [K] */
+    float *grad_pose;             /* backward: [K][3] */
+    float *grad_footprint;        /* backward: [n][2] */
+    float *residual;              /* backward: optional */
+} pip_cost_desc;
+pip_status pip_plan_create(pip_ctx ctx, pip_plan_kind kind, const void *desc, pip_plan *out);
+
 #ifdef __cplusplus
 }
 #endif

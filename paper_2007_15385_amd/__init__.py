@@ -14,8 +14,9 @@ The functions carry the C names: :func:`polygon_to_generators`,
 from __future__ import annotations
 
 from ._lib import (PIP_BATCHED_SCRATCH_BYTES, PIP_F32, PIP_F64, PIP_OPT_ALLPAIRS_CULL, PIP_OPT_ALLPAIRS_PAIR, PIP_OPT_COST_CULL, PIP_OPT_COST_PAIR, PIP_OPT_MFMA_MIN_EDGES, PIP_OPT_RADIAL_MIN_EDGES, PIP_OPT_EARLY_EXIT, PipError, lib_path, load_library,
-                   num_label_words, status_name)
-from .api import get_option, set_option
+                   num_label_words, status_name, PIP_PLAN_BATCHED, PIP_PLAN_ALLPAIRS,
+                   PIP_PLAN_COST_FWD, PIP_PLAN_COST_BWD, BatchedDesc, AllpairsDesc, CostDesc)
+from .api import get_option, set_option, pip_plan_create
 from .api import (AllpairsPlan, BatchedPlan, LocateIndex, allpairs_workspace_bytes, batched_workspace_bytes,
                   convex_decompose, pieces_workspace_bytes, pip_voronoi_pieces,
                   allpairs_csr_workspace_bytes, pip_voronoi_allpairs_csr, pip_mfma_margin_probe, label_word_offsets, pip_poses_to_polygons,
@@ -36,4 +37,6 @@ __all__ = [
     "pip_voronoi_pieces", "allpairs_csr_workspace_bytes", "pip_voronoi_allpairs_csr", "pip_mfma_margin_probe",
     "pip_poses_to_polygons", "pip_voronoi_allpairs", "allpairs_workspace_bytes", "pip_cost_fwd", "pip_cost_bwd",
     "CollisionCost", "CostPlan", "collision_cost", "PIP_OPT_MFMA_MIN_EDGES", "PIP_OPT_ALLPAIRS_CULL", "PIP_OPT_ALLPAIRS_PAIR", "PIP_OPT_COST_CULL", "PIP_OPT_COST_PAIR", "PIP_OPT_RADIAL_MIN_EDGES", "PIP_OPT_EARLY_EXIT", "set_option", "get_option",
+    "pip_plan_create", "PIP_PLAN_BATCHED", "PIP_PLAN_ALLPAIRS", "PIP_PLAN_COST_FWD",
+    "PIP_PLAN_COST_BWD", "BatchedDesc", "AllpairsDesc", "CostDesc",
 ]

@@ -91,6 +91,7 @@ SIGNATURES = {
     "pip_plan_variant": (_int, [_vp, _vp, _c.POINTER(_c.c_float)]),
     "pip_plan_create_cost": (_int, [_vp, _i32, _vp, _i32, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _vp,
                                     _vp, _c.POINTER(_vp)]),
+    "pip_plan_create": (_int, [_vp, _i32, _vp, _c.POINTER(_vp)]),
     "pip_plan_set_variant": (_int, [_vp, _vp]),
     "pip_plan_destroy": (None, [_vp]),
     "pip_poses_to_polygons": (_int, [_vp, _vp, _i32, _vp, _vp, _i64, _vp, _vp]),
@@ -113,6 +114,35 @@ class BatchedConfig(ctypes.Structure):
 
 class VariantConfig(ctypes.Structure):
     _fields_ = [("cull", ctypes.c_int32), ("pair", ctypes.c_int32)]
+
+
+# pip_plan_create: kinds and descriptors (the typed creators' arguments)
+PIP_PLAN_BATCHED = 0
+PIP_PLAN_ALLPAIRS = 1
+PIP_PLAN_COST_FWD = 2
+PIP_PLAN_COST_BWD = 3
+
+
+class BatchedDesc(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("vtx_off", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("total_vertices", ctypes.c_int64), ("pt_off", ctypes.c_void_p),
+                ("Q", ctypes.c_void_p), ("total_points", ctypes.c_int64),
+                ("lbl_word_off", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
+class AllpairsDesc(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("n", ctypes.c_int32), ("V", ctypes.c_void_p),
+                ("Q", ctypes.c_void_p), ("m", ctypes.c_int64), ("labels", ctypes.c_void_p),
+                ("counts", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class CostDesc(ctypes.Structure):
+    _fields_ = [("footprint", ctypes.c_void_p), ("n", ctypes.c_int32), ("pose", ctypes.c_void_p),
+                ("K", ctypes.c_int64), ("Q", ctypes.c_void_p), ("m", ctypes.c_int64),
+                ("cost", ctypes.c_void_p), ("grad_cost", ctypes.c_void_p),
+                ("grad_pose", ctypes.c_void_p), ("grad_footprint", ctypes.c_void_p),
+                ("residual", ctypes.c_void_p)]
 
 _lock = threading.Lock()
 _lib = None

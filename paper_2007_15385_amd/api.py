@@ -306,6 +306,16 @@ def pip_voronoi_batched_noalloc(vtx_off, V, pt_off, Q, lbl_word_off=None, labels
     return a.labels, a.lbl, a.status
 
 
+def pip_plan_create(kind: int, desc, device: int = 0) -> int:
+    """The plan handle of pip_plan_create (kind PIP_PLAN_*, desc the kind's
+    descriptor structure from ._lib); destroy it with pip_plan_destroy."""
+    ctx = context(device)
+    h = ctypes.c_void_p()
+    s = _lib().pip_plan_create(ctx, int(kind), ctypes.byref(desc), ctypes.byref(h))
+    _check(s, "pip_plan_create", ctx)
+    return h.value
+
+
 class BatchedPlan:
     """Autotuned, graph-captured batched launch bound to fixed buffers."""
 

@@ -1513,6 +1513,32 @@ pip_status pip_set_option(pip_ctx ctx, pip_option opt, int64_t value) {
     return fail(PIP_EINVAL, "unknown option %d", (int)opt);
 }
 
+pip_status pip_plan_create(pip_ctx ctx, pip_plan_kind kind, const void* desc, pip_plan* out) {
+    if (!ctx) return fail(PIP_EINVAL, "ctx is NULL");
+    if (!desc || !out) return fail(PIP_EINVAL, "desc or out is NULL");
+    switch (kind) {
+        case PIP_PLAN_BATCHED: {
+            const pip_batched_desc& d = *static_cast<const pip_batched_desc*>(desc);
+            return pip_plan_create_batched(ctx, d.P, d.vtx_off, d.V, d.total_vertices, d.pt_off,
+                                           d.Q, d.total_points, d.lbl_word_off, d.labels,
+                                           d.status, out);
+        }
+        case PIP_PLAN_ALLPAIRS: {
+            const pip_allpairs_desc& d = *static_cast<const pip_allpairs_desc*>(desc);
+            return pip_plan_create_allpairs(ctx, d.P, d.n, d.V, d.Q, d.m, d.labels, d.counts,
+                                            d.status, out);
+        }
+        case PIP_PLAN_COST_FWD:
+        case PIP_PLAN_COST_BWD: {
+            const pip_cost_desc& d = *static_cast<const pip_cost_desc*>(desc);
+            return pip_plan_create_cost(ctx, kind == PIP_PLAN_COST_BWD ? 1 : 0, d.footprint, d.n,
+                                        d.pose, d.K, d.Q, d.m, d.cost, d.grad_cost, d.grad_pose,
+                                        d.grad_footprint, d.residual, out);
+        }
+    }
+    return fail(PIP_EINVAL, "unknown plan kind %d", (int)kind);
+}
+
 pip_status pip_get_option(pip_ctx ctx, pip_option opt, int64_t* value) {
     if (!ctx || !value) return fail(PIP_EINVAL, "ctx or value is NULL");
     switch (opt) {

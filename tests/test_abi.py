@@ -108,3 +108,11 @@ def test_library_has_no_cpu_fallback_symbols(lib):
     # the product library must not contain the oracle
     for name in ("oracle_voronoi", "oracle_generators", "oracle_cost"):
         assert not hasattr(lib, name)
+
+
+def test_plan_create_rejects_null_arguments(lib):
+    """pip_plan_create checks its pointers before it touches a context."""
+    import ctypes
+    h = ctypes.c_void_p()
+    desc = ctypes.create_string_buffer(128)
+    assert lib.pip_plan_create(None, 0, desc, ctypes.byref(h)) == 1
