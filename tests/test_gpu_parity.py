@@ -381,3 +381,82 @@ def test_ray_crossing_nonconvex(P, oracle, qdt):
         area = 0.5 * abs(np.dot(x, np.roll(y, -1)) - np.dot(y, np.roll(x, -1)))
         frac = want[:200_000].mean()
         assert abs(frac - area / np.prod(hi - lo)) < 0.01, (frac, area / np.prod(hi - lo))
+
+
+def random_convex(rng, n):
+    """A random convex polygon with exactly n vertices, CCW, float64: n random
+    x and n random y values, each sorted range split at random into two
+    monotone chains whose successive differences (summing to zero) are
+    paired at random and laid end to end in order of angle.  Irregular
+    shapes: short and long edges, sharp and nearly flat vertices."""
+    for _ in range(100):
+        def steps(k):
+            v = np.sort(rng.random(k))
+            lo, hi = v[0], v[-1]
+            a, b = lo, lo
+            out = []
+            for x in v[1:-1]:
+                if rng.random() < 0.5:
+                    out.append(x - a)
+                    a = x
+                else:
+                    out.append(b - x)
+                    b = x
+            out += [hi - a, b - hi]
+            return np.array(out)
+        dx, dy = steps(n), rng.permutation(steps(n))
+        ang = np.arctan2(dy, dx)
+        o = np.argsort(ang)
+        E = np.stack([dx[o], dy[o]], 1)
+        V = np.cumsum(E, 0)
+        V -= V.mean(0)
+        x, y = V[:, 0], V[:, 1]
+        nxt = np.roll(V, -1, 0) - V
+        prv = V - np.roll(V, 1, 0)
+        turn = prv[:, 0] * nxt[:, 1] - prv[:, 1] * nxt[:, 0]
+        if np.all(turn > 1e-9 * np.abs(V).max() ** 2) and np.all(np.hypot(*prv.T) > 1e-6):
+            return V
+    raise AssertionError("no strictly convex polygon drawn")
+
+
+@pytest.mark.parametrize("test", list(TESTS))
+@pytest.mark.parametrize("qdt", ["f32", "f64"])
+def test_irregular_polygons(P, oracle, test, qdt):
+    """Irregular convex polygons (random edge lengths and turning angles, 3 to
+    64 vertices), stretched up to 10^4:1, rotated, at sizes 10^-4..10^4 and
+    centres up to 10^5 from the origin, in both orientations: uniform points
+    over the bounding box, points at 0..10^-5 of the size from the edges,
+    the vertices and their float32 neighbours.  Labels bit-identical to the
+    oracle's; valid polygons report status 0."""
+    rng = np.random.default_rng(61)
+    fn, otest = TESTS[test]
+    for n in (3, 4, 5, 7, 12, 20, 33, 48, 64):
+        for stretch, size, centre in ((1.0, 1.0, 0.0), (1e2, 1e-3, 1e3), (1e4, 1e4, -1e5),
+                                      (30.0, 1e-4, 0.5)):
+            V = random_convex(rng, n)
+            V[:, 0] *= stretch
+            th = rng.uniform(0, 2 * np.pi)
+            R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+            V = V @ R.T
+            V *= size / np.abs(V).max()
+            V += np.array([centre, -0.7 * centre])
+            if rng.random() < 0.5:
+                V = V[::-1].copy()
+            lo, hi = V.min(0), V.max(0)
+            span = hi - lo
+            Q = rng.uniform(lo - 0.25 * span, hi + 0.25 * span, size=(6000, 2))
+            scale = float(np.abs(V).max())
+            offs = [0.0, 1e-12 * scale, -1e-12 * scale, 1e-9 * size, -1e-9 * size, 1e-7 * size,
+                    -1e-7 * size, 1e-5 * size, -1e-5 * size]
+            Qe = near_edge(rng, V, 400, offs)
+            fv = V.astype(np.float32)
+            nb = np.concatenate([np.stack([np.nextafter(fv[:, 0], np.float32(s)), fv[:, 1]], 1)
+                                 for s in (-np.inf, np.inf)]).astype(np.float64)
+            Q = np.concatenate([Q, Qe, nb]).astype(np.float32 if qdt == "f32" else np.float64)
+            say(f"[case] {test} {qdt} irregular n={n} stretch={stretch:g} size={size:g} "
+                f"centre={centre:g}")
+            st = []
+            got = run_gpu(P, fn, V, Q, status=st)
+            assert st == [0], (n, stretch, size, centre, st)
+            assert_same(got, expect(oracle, otest, V, Q), len(Q),
+                        f"{test} n={n} stretch={stretch:g} size={size:g}")
