@@ -450,3 +450,39 @@ def test_allpairs_csr_full_size(P, oracle):
         want = oracle.voronoi(polys[k], Qh)
         bad += int((unpack_bits(lab[k], len(Q))[:4096] != want).sum())
     assert bad == 0
+
+
+def test_allpairs_csr_irregular(P, oracle, allpairs_variant):
+    """40 irregular convex polygons (random edge lengths and turns, 3 to 64
+    vertices, stretched up to 10^3:1, sizes 0.05..5, either orientation)
+    spread over one cloud: uniform points plus points on and within
+    10^-9..10^-5 of every polygon's edges, labels and counts exact."""
+    from oracle import pack_bits
+    from shapes import placed_convex
+    rng = np.random.default_rng(401)
+    polys = []
+    for k in range(40):
+        n = int(rng.integers(3, 65))
+        V = placed_convex(rng, n, float(10.0 ** rng.uniform(0, 3)),
+                          float(10.0 ** rng.uniform(np.log10(0.05), np.log10(5.0))), 0.0)
+        polys.append(V + rng.uniform(-6, 6, 2))
+    pts = [rng.uniform(-8, 8, size=(6000, 2))]
+    for Vk in polys:
+        Wr = np.roll(Vk, 1, 0)
+        e = Vk - Wr
+        L = np.hypot(e[:, 0], e[:, 1])
+        for off in (0.0, 1e-9, -1e-9, 1e-7, -1e-5):
+            i = rng.integers(len(Vk), size=20)
+            t = rng.random(20)
+            pts.append(np.stack([Wr[i, 0] + t * e[i, 0] + off * e[i, 1] / L[i],
+                                 Wr[i, 1] + t * e[i, 1] - off * e[i, 0] / L[i]], 1))
+        pts.append(Vk)
+    Q = np.concatenate(pts).astype(np.float32)
+    vtx_off = np.concatenate([[0], np.cumsum([len(v) for v in polys])]).astype(np.int64)
+    V = np.concatenate(polys)
+    lab, cnt, st = run_csr(P, vtx_off, V, Q)
+    assert (st == 0).all(), st
+    for k, Vk in enumerate(polys):
+        want = oracle.voronoi(Vk, Q.astype(np.float64))
+        assert np.array_equal(lab[k], pack_bits(want)), k
+        assert int(cnt[k]) == int(want.sum()), k

@@ -204,3 +204,44 @@ def test_uneven_batch_full_size(P, oracle):
     assert bad == 0
     assert (plan.status.cpu().numpy() == 0).all()
     plan.close()
+
+
+def test_batched_irregular(P, oracle):
+    """A batch of 72 irregular convex polygons (random edge lengths and
+    turns, 3 to 64 vertices, stretched up to 10^4:1, sizes 10^-4..10^4,
+    centres up to 10^5, either orientation), each with uniform points over
+    its bounding box and points at 0..10^-5 of its size from its edges."""
+    from shapes import placed_convex
+    rng = np.random.default_rng(71)
+    polys, Qs = [], []
+    for k in range(72):
+        n = int(rng.integers(3, 65))
+        stretch, size, centre = [(1.0, 1.0, 0.0), (1e2, 1e-3, 1e3), (1e4, 1e4, -1e5),
+                                 (30.0, 1e-4, 0.5)][k % 4]
+        V = placed_convex(rng, n, stretch, size, centre)
+        lo, hi = V.min(0), V.max(0)
+        span = hi - lo
+        s = int(rng.integers(1, 4000))
+        q = rng.uniform(lo - 0.25 * span, hi + 0.25 * span, size=(s, 2))
+        m = s // 4
+        if m:
+            Wv = np.roll(V, 1, 0)
+            e = V - Wv
+            i = rng.integers(n, size=m)
+            t = rng.random(m)
+            L = np.hypot(e[i, 0], e[i, 1])
+            off = rng.choice([0.0, 1e-9 * size, -1e-9 * size, 1e-7 * size, -1e-5 * size], size=m)
+            q[:m, 0] = Wv[i, 0] + t * e[i, 0] + off * e[i, 1] / L
+            q[:m, 1] = Wv[i, 1] + t * e[i, 1] - off * e[i, 0] / L
+        polys.append(V)
+        Qs.append(q.astype(np.float32))
+    vtx_off = np.concatenate([[0], np.cumsum([len(v) for v in polys])]).astype(np.int64)
+    pt_off = np.concatenate([[0], np.cumsum([len(q) for q in Qs])]).astype(np.int64)
+    B = W.Batch(vtx_off, np.concatenate(polys), pt_off, np.concatenate(Qs),
+                W.label_word_offsets(pt_off))
+    vo, V, po, Q, lo = to_dev(B)
+    say(f"[case] batched irregular polygons, {int(pt_off[-1])} points")
+    labels, _, status = P.pip_voronoi_batched(vo, V, po, Q, lo)
+    torch.cuda.synchronize()
+    check_batch(oracle, B, labels)
+    assert (status.cpu().numpy() == 0).all()

@@ -13,6 +13,7 @@ import pytest
 
 import workloads as W
 from oracle import pack_bits, unpack_bits
+from shapes import placed_convex
 
 pytestmark = pytest.mark.gpu
 
@@ -383,42 +384,6 @@ def test_ray_crossing_nonconvex(P, oracle, qdt):
         assert abs(frac - area / np.prod(hi - lo)) < 0.01, (frac, area / np.prod(hi - lo))
 
 
-def random_convex(rng, n):
-    """A random convex polygon with exactly n vertices, CCW, float64: n random
-    x and n random y values, each sorted range split at random into two
-    monotone chains whose successive differences (summing to zero) are
-    paired at random and laid end to end in order of angle.  Irregular
-    shapes: short and long edges, sharp and nearly flat vertices."""
-    for _ in range(100):
-        def steps(k):
-            v = np.sort(rng.random(k))
-            lo, hi = v[0], v[-1]
-            a, b = lo, lo
-            out = []
-            for x in v[1:-1]:
-                if rng.random() < 0.5:
-                    out.append(x - a)
-                    a = x
-                else:
-                    out.append(b - x)
-                    b = x
-            out += [hi - a, b - hi]
-            return np.array(out)
-        dx, dy = steps(n), rng.permutation(steps(n))
-        ang = np.arctan2(dy, dx)
-        o = np.argsort(ang)
-        E = np.stack([dx[o], dy[o]], 1)
-        V = np.cumsum(E, 0)
-        V -= V.mean(0)
-        x, y = V[:, 0], V[:, 1]
-        nxt = np.roll(V, -1, 0) - V
-        prv = V - np.roll(V, 1, 0)
-        turn = prv[:, 0] * nxt[:, 1] - prv[:, 1] * nxt[:, 0]
-        if np.all(turn > 1e-9 * np.abs(V).max() ** 2) and np.all(np.hypot(*prv.T) > 1e-6):
-            return V
-    raise AssertionError("no strictly convex polygon drawn")
-
-
 @pytest.mark.parametrize("test", list(TESTS))
 @pytest.mark.parametrize("qdt", ["f32", "f64"])
 def test_irregular_polygons(P, oracle, test, qdt):
@@ -433,15 +398,7 @@ def test_irregular_polygons(P, oracle, test, qdt):
     for n in (3, 4, 5, 7, 12, 20, 33, 48, 64):
         for stretch, size, centre in ((1.0, 1.0, 0.0), (1e2, 1e-3, 1e3), (1e4, 1e4, -1e5),
                                       (30.0, 1e-4, 0.5)):
-            V = random_convex(rng, n)
-            V[:, 0] *= stretch
-            th = rng.uniform(0, 2 * np.pi)
-            R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
-            V = V @ R.T
-            V *= size / np.abs(V).max()
-            V += np.array([centre, -0.7 * centre])
-            if rng.random() < 0.5:
-                V = V[::-1].copy()
+            V = placed_convex(rng, n, stretch, size, centre)
             lo, hi = V.min(0), V.max(0)
             span = hi - lo
             Q = rng.uniform(lo - 0.25 * span, hi + 0.25 * span, size=(6000, 2))
