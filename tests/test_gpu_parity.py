@@ -417,3 +417,25 @@ def test_irregular_polygons(P, oracle, test, qdt):
             assert st == [0], (n, stretch, size, centre, st)
             assert_same(got, expect(oracle, otest, V, Q), len(Q),
                         f"{test} n={n} stretch={stretch:g} size={size:g}")
+
+
+@pytest.mark.parametrize("test", list(TESTS))
+def test_ragged_tail_after_many_chunks(P, oracle, test):
+    """3 x 5120 x 512 + 333 float32 points (every wave of the persistent
+    screens walks three or four full chunks before one wave takes the
+    333-point tail), 1% of them within 1e-7 of an edge so that the recheck
+    queues hold codes of later chunks; every label checked."""
+    rng = np.random.default_rng(77)
+    fn, otest = TESTS[test]
+    m = 3 * 5120 * 512 + 333
+    for n in (8, 33):
+        V = W.circle_polygon(n, 1.0, (0.02, -0.01), rng)
+        Q = rng.uniform(-1.5, 1.5, size=(m, 2))
+        k = m // 100
+        sel = rng.choice(m, size=k, replace=False)
+        Q[sel] = near_edge(rng, V, k, [1e-7, -1e-7])[2 * len(V):][rng.permutation(2 * k)[:k]]
+        Q = Q.astype(np.float32)
+        say(f"[case] {test} ragged tail n={n} m={m}")
+        got = run_gpu(P, fn, V, Q)
+        assert got.size == (m + 31) // 32
+        assert_same(got, expect(oracle, otest, V, Q), m, f"{test} n={n} m={m}")
