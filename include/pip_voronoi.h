@@ -218,12 +218,18 @@ pip_status pip_voronoi_radial_bounds(pip_ctx ctx, const double *V, int32_t n, fl
  *        out[0..12) = o_x, o_y (the local origin, fl32(p_0)), KQ, KA, KB, KC
  *        (the band E = KQ (X^2 + Y^2) + KA |X| + KB |Y| + KC, X, Y the
  *        point's float32 local coordinates), n4, the polygon's pip_status,
- *        RQ (Voronoi: where |X| + |Y| <= RQ for every point of a screened
- *        chunk, the vector screens use E = max(KA, KB) (|X| + |Y|) + KC),
- *        then three zeros; then n4 rows (A_i, B_i, -C_i, 0) with margin
+ *        RQ (where |X| + |Y| <= RQ for every point of a screened chunk, the
+ *        vector screens use E = max(KA, KB) (|X| + |Y|) + KC), SO (sign of
+ *        offset: for fl32(|X| + |Y|) < SO some edge's offset is known to
+ *        clear the band on the inner side, so one edge cleared on the outer
+ *        side decides "outside"; 0 for Voronoi and for unusable polygons),
+ *        then two zeros; then n4 rows (A_i, B_i, -C_i, 0) with margin
  *        m_i = A_i X + B_i Y - C_i (Voronoi; rows past n repeat edge 0) or
- *        (-dV_y, dV_x, -R_i, 0) (sign of offset).  A point is decided in
- *        float32 only when its largest margin clears the band.
+ *        sg (-dV_y, dV_x, -R_i, 0) (sign of offset, Algorithm 2's offset
+ *        LHS - RHS in the local frame, sg = -1 for a clockwise polygon so
+ *        that the inner side is positive).  A point is decided in float32
+ *        only when its largest margin (sign of offset: its smallest
+ *        offset) clears the band.
  * Asynchronous on `stream`; allocates nothing.  Errors: PIP_EINVAL for a bad
  * argument, PIP_EUNSUPPORTED for n > PIP_MAX_EDGES.
  */

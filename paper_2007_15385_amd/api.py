@@ -144,10 +144,12 @@ def pip_voronoi_radial_bounds(V):
 
 def pip_screen_table(V, test: int = 0, matrix: int = 0):
     """The float32 screen table (float32 tensor [12 + 4 n4]): o_x, o_y, KQ,
-    KA, KB, KC, n4, status, RQ (the band's fold radius), 0, 0, 0, then n4
-    rows (A, B, -C, 0) for the Voronoi test (test 0) or the sign-of-offset
-    rows (test 1), as the vector (matrix 0) or matrix-core (matrix 1) screen
-    derives them."""
+    KA, KB, KC, n4, status, RQ (the band's fold radius), SO (sign of offset:
+    the one-sided screen's bound on fl32(|X| + |Y|); 0 for Voronoi), 0, 0,
+    then n4 rows (A, B, -C, 0) for the Voronoi test (test 0) or the
+    sign-of-offset rows, oriented so that the inner side is positive (test
+    1), as the vector (matrix 0) or matrix-core (matrix 1) screen derives
+    them."""
     V = _polygon(V)
     d = _dev(V)
     n4 = (V.shape[0] + 3) // 4 * 4

@@ -66,6 +66,7 @@ struct alignas(32) PolyLds {
     float ox, oy;                    // float32 local origin
     float KQ, KA, KB, KC;            // band E = KQ (X^2 + Y^2) + KA |X| + KB |Y| + KC
     float RQ;                        // for |X|, |Y| <= RQ, E = KA |X| + KB |Y| + KC suffices
+    float SO;                        // sign of offset: fl32(|X| + |Y|) < SO proves an inner edge (0: never)
     int n, n4, status;
 };
 
@@ -98,6 +99,36 @@ __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
     return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// largest float32 <= d for d >= 0 (at most FLT_MAX); 0 for NaN
+__device__ __forceinline__ float round_down_f32(double d) {
+    if (!(d > 0.0)) return 0.0f;
+    if (d >= 3.4028234663852886e38) return 3.4028234663852886e38f;
+    float f = (float)d;
+    if ((double)f > d) f = __uint_as_float(__float_as_uint(f) - 1u);
+    return f;
+}
+
+// Fold of the quadratic band term into the linear ones near the polygon: for
+// |X|, |Y| <= RQ, KQ (X^2 + Y^2) <= KQ RQ (|X| + |Y|).  RQ is the largest
+// power of two with KQ RQ <= 2^-8 min(KA, KB) (at most 2^60), so the linear
+// constants grow by at most 2^-8 of themselves.  Returns RQ (0: no fold).
+__device__ inline double fold_band(double KQ, double& KA, double& KB) {
+    const double kmin = fmin(KA, KB);
+    if (!(kmin > 0.0 && kmin < 1e300)) return 0.0;
+    int e = 0;
+    (void)frexp(kmin * 0.00390625 / KQ, &e);  // value in [2^(e-1), 2^e)
+    const double RQ = ldexp(1.0, e - 1 < 60 ? e - 1 : 60);
+    KA += KQ * RQ;
+    KB += KQ * RQ;
+    return RQ;
 }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
@@ -221,15 +252,24 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
     if (lane < n) S.gen[1 + lane] = make_double2(gx, gy);
     if (lane == 0) S.gen[0] = make_double2(g0x, g0y);
 
-    // Local frame o = fl32(p_0), or the global frame (o = 0, so X = p_x
-    // exactly); the band below holds for either.
-    const float ox = given_frame ? gox : global_frame ? 0.0f : (float)g0x;
-    const float oy = given_frame ? goy : global_frame ? 0.0f : (float)g0y;
+    // Local frame o = fl32(p_0) (Voronoi), fl32 of the vertex mean (sign of
+    // offset and ray crossing, whose offsets do not involve p_0: the binary64
+    // centroid of a polygon that is tiny against its distance from the
+    // origin can lie far from it, the vertex mean cannot), or the global
+    // frame (o = 0, so X = p_x exactly); the bands below hold for any frame.
+    double fx = g0x, fy = g0y;
+    if (kind == K_SOO || kind == K_RAY32) {
+        fx = wave_sum(lane < n ? S.vtx[lane].x : 0.0) / (double)n;
+        fy = wave_sum(lane < n ? S.vtx[lane].y : 0.0) / (double)n;
+    }
+    const float ox = given_frame ? gox : global_frame ? 0.0f : (float)fx;
+    const float oy = given_frame ? goy : global_frame ? 0.0f : (float)fy;
     const double dox = (double)ox, doy = (double)oy;
     const int i = lane < n ? lane : 0;
     const double d2x = g0x - dox, d2y = g0y - doy;
     const double d2 = d2x * d2x + d2y * d2y;
     double qa = 0.0, qb = 0.0, qc = 0.0, KA = 0.0, KB = 0.0, KC = 0.0, KQ = 0.0, RQ = 0.0;
+    double soL = 0.0, soMx = 0.0, soMy = 0.0;  // sign of offset: the one-sided screen's sums
     bool finite_ok = true;
     if (kind == K_VORONOI || kind == K_MARGIN) {
         const double hx = gx - g0x, hy = gy - g0y;
@@ -252,18 +292,7 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         KC = (f32_factor * kU32 * gam + 4.1 * kU64 * (G2 + d2) +
               4.0001 * kU64 * (6.0 * d2 + 2.0 * H2) + kEpsAbs * (1.0 + alpha + beta)) * infl;
         KQ = 24.01 * kU64 * infl;
-        // Fold of the quadratic term into the linear ones near the polygon:
-        // for |X|, |Y| <= RQ, KQ (X^2 + Y^2) <= KQ RQ (|X| + |Y|).  RQ is the
-        // largest power of two with KQ RQ <= 2^-8 min(KA, KB) (at most 2^60),
-        // so the linear constants grow by at most 2^-8 of themselves.
-        const double kmin = fmin(KA, KB);
-        if (kmin > 0.0 && kmin < 1e300) {
-            int e = 0;
-            (void)frexp(kmin * 0.00390625 / KQ, &e);  // value in [2^(e-1), 2^e)
-            RQ = ldexp(1.0, e - 1 < 60 ? e - 1 : 60);
-            KA += KQ * RQ;
-            KB += KQ * RQ;
-        }
+        RQ = fold_band(KQ, KA, KB);
         (void)qa; (void)qb; (void)qc;
     } else if (kind == K_SOO || kind == K_RAY32) {
         const int j = prev_edge(i, n);
@@ -276,11 +305,15 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         // every edge (negation is exact); and the height of the edge's end
         // vertex rounded up to float32, c: for a float32 Q_y, V_y > Q_y
         // exactly when c > Q_y
+        // sign of offset: every row negated for a clockwise polygon, so that
+        // the inner side of every edge is s > 0 (the labels do not change:
+        // the test accepts either orientation)
         if (kind == K_RAY32) {
             const float sg = v.y > w.y ? 1.0f : -1.0f;
             S.coef[lane] = make_float4(sg * p, sg * q, -(sg * r), ceil_f32(v.y));
         } else {
-            S.coef[lane] = make_float4(p, q, -r, 0.0f);
+            const float sg = area < 0.0 ? -1.0f : 1.0f;
+            S.coef[lane] = make_float4(sg * p, sg * q, -(sg * r), 0.0f);
         }
         finite_ok = isfinite(p) && isfinite(q) && isfinite(r) && fabs((double)p) < kCoefLimit &&
                     fabs((double)q) < kCoefLimit && fabs((double)r) < kCoefLimit;
@@ -300,6 +333,29 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         KC = (f32_factor * kU32 * rm + 3.1 * kU64 * kR + 2.0001 * kU64 * k64 +
               kEpsAbs * (1.0 + pm + qm)) * infl;
         KQ = kEpsAbs;  // no quadratic term; keeps X^2 overflow -> E = +inf
+        if (kind == K_SOO) {
+            RQ = fold_band(KQ, KA, KB);
+            // One-sided screen.  With the rounded edge vectors (dV_x, dV_y)
+            // of Algorithm 2, the exact offsets s_i = LHS_i - RHS_i of a point
+            // Q sum to C + Q_y sum(dV_x) - Q_x sum(dV_y), C = -sum(V'_y dV_x -
+            // V'_x dV_y) (twice the signed area when the edge vectors close
+            // up exactly).  With the rows oriented by sg, some edge has
+            // sg s_i >= (sg C - |sum dV_x| |Q_y| - |sum dV_y| |Q_x|) / n; when
+            // that exceeds the band, that edge's binary64 comparison falls on
+            // the inner side, and a point certified on the outer side of one
+            // edge is certified outside.  The sums are bounded for any
+            // summation order by 80 v of the sums of absolute values
+            // (>= gamma_{n+2} for n <= 64); SO below turns the condition into
+            // one float32 comparison per point.
+            const bool act = lane < n;
+            const double sg = area < 0.0 ? -1.0 : 1.0;
+            const double g = 80.0 * kU64;
+            const double Cs = -wave_sum(act ? w.y * dVx - w.x * dVy : 0.0);
+            const double Ca = wave_sum(act ? fabs(w.y * dVx) + fabs(w.x * dVy) : 0.0);
+            soL = sg * Cs - g * Ca;  // <= sg C
+            soMx = fabs(wave_sum(act ? dVx : 0.0)) + g * wave_sum(act ? fabs(dVx) : 0.0);
+            soMy = fabs(wave_sum(act ? dVy : 0.0)) + g * wave_sum(act ? fabs(dVy) : 0.0);
+        }
     }
     if (kind == K_RAY || kind == K_RAY32) {
         const int j = prev_edge(i, n);
@@ -311,6 +367,25 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         }
     }
     const uint64_t bad = __ballot(!finite_ok);
+    // Sign of offset: |Q_x| <= |o_x| + |X| / (1 - u) (X = fl32(Q_x - o_x)),
+    // |X| + |Y| <= fl32(|X| + |Y|) / (1 - u), and the folded band
+    // E <= KS (|X| + |Y|) + KC with KS = max(KA, KB) for |X|, |Y| <= RQ
+    // (stored, rounded-up constants).  The one-sided condition above then
+    // holds whenever fl32(|X| + |Y|) < SO with
+    //   SO <= (1 - u) T / (n KS + max(Mx, My) / (1 - u)),
+    //   T = L - Mx |o_y| - My |o_x| - n KC,
+    // L <= sg C, Mx >= |sum dV_x|, My >= |sum dV_y|; the factors 1 +- 2^-40
+    // and 1 - 2^-20 cover the binary64 evaluation here, and SO <= RQ / 2
+    // keeps |X|, |Y| <= RQ.  Unusable polygons get SO = 0 (never).
+    float SO = 0.0f;
+    if (kind == K_SOO) {
+        const double KSs = fmax((double)round_up_f32(KA), (double)round_up_f32(KB));
+        const double KCs = (double)round_up_f32(KC);
+        const double T = soL - (soMx * fabs(doy) + soMy * fabs(dox) + (double)n * KCs) * (1.0 + 0x1p-40);
+        const double den = (double)n * KSs * (1.0 + 0x1p-40) + fmax(soMx, soMy) * (1.0 + 0x1p-20);
+        SO = fminf(round_down_f32(T * (1.0 - 0x1p-20) / den), (float)(0.5 * RQ));
+        if (status != ST_OK || bad) SO = 0.0f;
+    }
     if (lane == 0) {
         S.ox = ox;
         S.oy = oy;
@@ -319,6 +394,7 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         S.KB = round_up_f32(KB);
         S.KC = bad ? __builtin_huge_valf() : round_up_f32(KC);
         S.RQ = (float)RQ;  // a power of two (or 0), exact in float32
+        S.SO = SO;
         S.n4 = (n + 3) & ~3;
         S.status = status;
     }

@@ -69,21 +69,6 @@ __device__ __forceinline__ double wave_min(double v) {
     return v;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-
-// largest float32 <= d for d >= 0 (at most FLT_MAX); 0 for NaN
-__device__ __forceinline__ float round_down_f32(double d) {
-    if (!(d > 0.0)) return 0.0f;
-    if (d >= 3.4028234663852886e38) return 3.4028234663852886e38f;
-    float f = (float)d;
-    if ((double)f > d) f = __uint_as_float(__float_as_uint(f) - 1u);
-    return f;
-}
-
 // Octant o as the closed arc from e0 to e1 (counter-clockwise, pi/4 wide).
 __device__ __forceinline__ void octant_arc(int o, double2* e0, double2* e1) {
     const double s = 0.70710678118654752440;

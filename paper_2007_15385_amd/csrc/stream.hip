@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_stream(const double* __restrict__ V,
 }
 
 template <int KIND>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == K_SOO ? 4 : 5))) void k_stream32(const double* __restrict__ V, int n,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_stream32(const double* __restrict__ V, int n,
                                                     const float2* __restrict__ Q, int64_t m,
                                                     uint32_t* __restrict__ labels,
                                                     int32_t* __restrict__ status) {
@@ -322,6 +322,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
 
     const float ox = S.ox, oy = S.oy;
     const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC, RQ = S.RQ, KS = fmaxf(KA, KB);
+    const float SO = S.SO;
     const int n4 = __builtin_amdgcn_readfirstlane(S.n4);
     const int nv = __builtin_amdgcn_readfirstlane(S.n);
     int qcount = 0;
@@ -391,7 +392,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
                 }
             }
         } else {
-            float X[kP32], Y[kP32], Mx[kP32], Mn[kP32];
+            // Voronoi: the largest margin; sign of offset (rows oriented so
+            // that the inner side is s > 0): the smallest offset only
+            float X[kP32], Y[kP32], Mx[kP32];
             {  // edges 0-3 (n4 >= 4) start the max / min
                 const float4 c0 = S.coef[0], c1 = S.coef[1], c2 = S.coef[2], c3 = S.coef[3];
     #pragma unroll
@@ -402,8 +405,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
                     const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
                     const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
                     const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
-                    Mx[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
-                    if constexpr (KIND == K_SOO) Mn[j] = fminf(fminf(fminf(m0, m1), m2), m3);
+                    if constexpr (KIND == K_SOO)
+                        Mx[j] = fminf(fminf(fminf(m0, m1), m2), m3);
+                    else
+                        Mx[j] = fmaxf(fmaxf(fmaxf(m0, m1), m2), m3);
                 }
             }
             for (int e = 4; e < n4; e += 4) {
@@ -415,21 +420,22 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
                     const float m1 = fmaf(c1.x, X[j], fmaf(c1.y, Y[j], c1.z));
                     const float m2 = fmaf(c2.x, X[j], fmaf(c2.y, Y[j], c2.z));
                     const float m3 = fmaf(c3.x, X[j], fmaf(c3.y, Y[j], c3.z));
-                    Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
-                    Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
                     if constexpr (KIND == K_SOO) {
-                        Mn[j] = fminf(fminf(Mn[j], m0), m1);
-                        Mn[j] = fminf(fminf(Mn[j], m2), m3);
+                        Mx[j] = fminf(fminf(Mx[j], m0), m1);
+                        Mx[j] = fminf(fminf(Mx[j], m2), m3);
+                    } else {
+                        Mx[j] = fmaxf(fmaxf(Mx[j], m0), m1);
+                        Mx[j] = fmaxf(fmaxf(Mx[j], m2), m3);
                     }
                 }
             }
-            // Voronoi: when |X| + |Y| <= RQ for every point of the chunk, the
-            // band's quadratic term is inside its linear constants and
+            // When |X| + |Y| <= RQ for every point of the chunk, the band's
+            // quadratic term is inside its linear constants and
             // E = KS (|X| + |Y|) + KC with KS = max(KA, KB) (wave-uniform branch;
             // a NaN sum is dropped by the max and gives a NaN band: undecided)
             bool fold = false;
             float sxy[kP32];
-            if constexpr (KIND == K_VORONOI) {
+            if constexpr (KIND == K_VORONOI || KIND == K_SOO) {
                 float acc = 0.0f;
     #pragma unroll
                 for (int j = 0; j < kP32; ++j) {
@@ -442,7 +448,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
     #pragma unroll
                 for (int j = 0; j < kP32; ++j) {
                     const float E = fmaf(KS, sxy[j], KC);
-                    const uint64_t in = __ballot(Mx[j] < -E), out = __ballot(Mx[j] > E);
+                    uint64_t in, out;
+                    if constexpr (KIND == K_SOO) {
+                        // inside: every offset on the inner side; outside: one
+                        // on the outer side, and fl32(|X| + |Y|) < SO proves
+                        // one on the inner side
+                        in = __ballot(Mx[j] > E);
+                        out = __ballot(Mx[j] < -E) & __ballot(sxy[j] < SO);
+                    } else {
+                        in = __ballot(Mx[j] < -E);
+                        out = __ballot(Mx[j] > E);
+                    }
                     inm[j] = in;
                     unc[j] = ~(in | out);
                 }
@@ -457,8 +473,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(KIND == 
                         const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X[j]), fmaf(KB, fabsf(Y[j]), KC)));
                         uint64_t in, out;
                         if constexpr (KIND == K_SOO) {
-                            in = __ballot(Mx[j] < -E) | __ballot(Mn[j] > E);
-                            out = __ballot(Mx[j] > E) & __ballot(Mn[j] < -E);
+                            in = __ballot(Mx[j] > E);
+                            out = __ballot(Mx[j] < -E) & __ballot(sxy[j] < SO);
                         } else {
                             in = __ballot(Mx[j] < -E);
                             out = __ballot(Mx[j] > E);
@@ -793,7 +809,8 @@ __global__ __launch_bounds__(kWave) void k_screen_table(const double* __restrict
         out[6] = (float)S.n4;
         out[7] = (float)S.status;
         out[8] = S.RQ;
-        out[9] = out[10] = out[11] = 0.0f;
+        out[9] = S.SO;
+        out[10] = out[11] = 0.0f;
     }
     for (int r = lane; r < S.n4; r += kWave) {
         const float4 c = S.coef[r];

@@ -63,6 +63,11 @@ __device__ __forceinline__ float reg_min(const floatx16& d) {
     for (int i = 3; i < R; i += 2) r = fminf(fminf(r, d[i]), d[i + 1 < R ? i + 1 : 0]);
     return r;
 }
+__device__ __forceinline__ float reg_min_cont(float r, const floatx16& d) {
+#pragma unroll
+    for (int i = 0; i < 16; i += 2) r = fminf(fminf(r, d[i]), d[i + 1]);
+    return r;
+}
 
 // lane l < 32: (a[l], a[l + 32]); lane l >= 32: (b[l - 32], b[l])
 __device__ __forceinline__ void swap_halves(float a, float b, float& lo, float& hi) {
@@ -129,7 +134,7 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
         }
     }
     const float ox = S.ox, oy = S.oy;
-    const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC;
+    const float KQ = S.KQ, KA = S.KA, KB = S.KB, KC = S.KC, SO = S.SO;
     int qcount = 0;
 
     // Screen the 8 slots of 64 points of chunk `ch` (this wave's k-th); rem
@@ -143,19 +148,21 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
             // the band first: X and Y are then free for the operand swap
             const float r2 = fmaf(X, X, Y * Y);
             const float E = fmaf(KQ, r2, fmaf(KA, fabsf(X), fmaf(KB, fabsf(Y), KC)));
+            const float sxy = fabsf(X) + fabsf(Y);  // sign of offset's one-sided test
             float bA, bB;  // operands of groups A and B
             swap_halves(X, Y, bA, bB);
-            float xA, xB, nA = 0.f, nB = 0.f;
+            float xA = 0.f, xB = 0.f, nA = 0.f, nB = 0.f;
             if constexpr (NB == 1) {
                 floatx16 dA = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[0], bA, c_op[0], 0, 0, 0);
                 floatx16 dB = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[0], bB, c_op[0], 0, 0, 0);
                 // both products in flight before the reductions start
                 __builtin_amdgcn_sched_barrier(0);
-                xA = reg_max<RR>(dA);
-                xB = reg_max<RR>(dB);
                 if constexpr (KIND == K_SOO) {
                     nA = reg_min<RR>(dA);
                     nB = reg_min<RR>(dB);
+                } else {
+                    xA = reg_max<RR>(dA);
+                    xB = reg_max<RR>(dB);
                 }
                 if constexpr (kDup && RR < 16) {  // keep every product register live
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -171,33 +178,39 @@ void k_stream_mfma(const double* __restrict__ V, int n, const float2* __restrict
                     const floatx16 d1 =
                         __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[1], bop, c_op[1], 0, 0, 0);
                     __builtin_amdgcn_sched_barrier(0);
-                    mx = reg_max_cont(reg_max<RR>(d0), d1);
-                    if constexpr (KIND == K_SOO) {
-                        const float n0 = reg_min<RR>(d0), n1 = reg_min<RR>(d1);
-                        mn = n0 < n1 ? n0 : n1;
-                    }
+                    if constexpr (KIND == K_SOO)
+                        mn = reg_min_cont(reg_min<RR>(d0), d1);
+                    else
+                        mx = reg_max_cont(reg_max<RR>(d0), d1);
                 };
                 group(bA, xA, nA);
                 group(bB, xB, nB);
             }
-            // max (min) over all edges of this lane's own point
-            float mx, mn = 0.f;
+            // max over all edges of this lane's own point (sign of offset,
+            // rows oriented so that the inner side is s > 0: the min)
+            float mx = 0.f, mn = 0.f;
             if constexpr (kDup) {
-                mx = half ? xB : xA;
-                if constexpr (KIND == K_SOO) mn = half ? nB : nA;
+                if constexpr (KIND == K_SOO)
+                    mn = half ? nB : nA;
+                else
+                    mx = half ? xB : xA;
             } else {
                 float u, w;
-                swap_halves(xA, xB, u, w);
-                mx = u > w ? u : w;
                 if constexpr (KIND == K_SOO) {
                     swap_halves(nA, nB, u, w);
                     mn = u < w ? u : w;
+                } else {
+                    swap_halves(xA, xB, u, w);
+                    mx = u > w ? u : w;
                 }
             }
             uint64_t in, out;
             if constexpr (KIND == K_SOO) {
-                in = __ballot(mx < -E) | __ballot(mn > E);
-                out = __ballot(mx > E) & __ballot(mn < -E);
+                // inside: every offset on the inner side; outside: one on the
+                // outer side, and fl32(|X| + |Y|) < SO proves one on the inner
+                // side (the bound of the polygon's preparation)
+                in = __ballot(mn > E);
+                out = __ballot(mn < -E) & __ballot(sxy < SO);
             } else {
                 in = __ballot(mx < -E);
                 out = __ballot(mx > E);
