@@ -466,8 +466,9 @@ __device__ __forceinline__ int64_t gen_base(const int64_t* vtx_off, int64_t k) {
 
 // ----------------------------------------------------------------------------
 // The float32 screen of one chunk (kPPL points per lane) against n4 padded
-// edges whose coefficients are in LDS.  Voronoi: Mx = max margin.  Sign of
-// offset: Mx, Mn = max and min offsets.  Classification against the band E:
+// edges whose coefficients are in LDS (binary64 points).  Voronoi: Mx = max
+// margin.  Sign of offset: Mx, Mn = max and min offsets (both extremes, so
+// the orientation of the rows does not matter).  Classification against the band E:
 // see prepare_polygon.  valid[j] false -> neither inside nor undecided.
 // ----------------------------------------------------------------------------
 template <int KIND>

@@ -6,8 +6,9 @@
 // is exactly v_mfma_f32_32x32x2f32 with A = [A_i, B_i] (32 x 2), B = [X_j; Y_j]
 // (2 x 32) and the accumulator input preset to -C_i; polygons of up to 64
 // edges take two such products per 32 points.  The vector units then only
-// reduce each point's margins (max over edges; max and min for sign of
-// offset), evaluate the band and pack the labels.
+// reduce each point's margins (max over edges; for sign of offset, whose rows
+// are oriented so that the inner side is positive, the min), evaluate the
+// band and pack the labels.
 //
 // Operand layout (gfx950, verified on the device): lane l supplies A[l%32][l/32]
 // and B[l/32][l%32]; accumulator register r of lane l holds row
