@@ -774,7 +774,13 @@ def main() -> int:
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
-    soo = {n: time_fn(P.pip_sign_of_offset, n) for n in NS}
+    # sign of offset and Voronoi timed back to back per polygon size, so that
+    # both meet the same clock (under sustained load the part lowers its
+    # clock within milliseconds; these launches follow the timed sweep)
+    soo, vor_beside = {}, {}
+    for n in NS:
+        soo[n] = time_fn(P.pip_sign_of_offset, n)
+        vor_beside[n] = time_fn(P.pip_voronoi, n)
     plain = {n: time_fn(P.pip_voronoi_fp32_plain, n) for n in NS}
     ray = {n: time_fn(P.pip_ray_crossing, n, reps=1) for n in NS}
     # the radial pre-screen (a culling layer in front of the test: points
@@ -799,6 +805,9 @@ def main() -> int:
         "voronoi_radial_prescreen": radial,
         "sign_of_offset_gtests_per_s": round(tests_per_step / (sum(soo.values()) * 1e-3) / 1e9, 2),
         "sign_of_offset_ms": {str(n): round(v, 4) for n, v in soo.items()},
+        "voronoi_beside_sign_of_offset_gtests_per_s":
+            round(tests_per_step / (sum(vor_beside.values()) * 1e-3) / 1e9, 2),
+        "voronoi_beside_sign_of_offset_ms": {str(n): round(v, 4) for n, v in vor_beside.items()},
         "fp32_plain_gtests_per_s": round(tests_per_step / (sum(plain.values()) * 1e-3) / 1e9, 2),
         "fp32_plain_ms": {str(n): round(v, 4) for n, v in plain.items()},
         "ray_crossing_gtests_per_s": round(tests_per_step / (sum(ray.values()) * 1e-3) / 1e9, 2),
