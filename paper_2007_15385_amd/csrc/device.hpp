@@ -307,12 +307,17 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
         // exactly when c > Q_y
         // sign of offset: every row negated for a clockwise polygon, so that
         // the inner side of every edge is s > 0 (the labels do not change:
-        // the test accepts either orientation)
+        // the test accepts either orientation).  The orientation is the sign
+        // of C = -sum(V'_y dV_x - V'_x dV_y) (below), formed from the edge
+        // vectors and so accurate where the shoelace sum of a tiny polygon
+        // far from the origin (the centroid's area) is not.
+        const bool act = lane < n;
+        const double soC = kind == K_SOO ? -wave_sum(act ? w.y * dVx - w.x * dVy : 0.0) : 0.0;
         if (kind == K_RAY32) {
             const float sg = v.y > w.y ? 1.0f : -1.0f;
             S.coef[lane] = make_float4(sg * p, sg * q, -(sg * r), ceil_f32(v.y));
         } else {
-            const float sg = area < 0.0 ? -1.0f : 1.0f;
+            const float sg = soC < 0.0 ? -1.0f : 1.0f;
             S.coef[lane] = make_float4(sg * p, sg * q, -(sg * r), 0.0f);
         }
         finite_ok = isfinite(p) && isfinite(q) && isfinite(r) && fabs((double)p) < kCoefLimit &&
@@ -347,12 +352,10 @@ __device__ inline void prepare_polygon(PolyLds& S, int kind, int lane, bool glob
             // summation order by 80 v of the sums of absolute values
             // (>= gamma_{n+2} for n <= 64); SO below turns the condition into
             // one float32 comparison per point.
-            const bool act = lane < n;
-            const double sg = area < 0.0 ? -1.0 : 1.0;
+            const double sg = soC < 0.0 ? -1.0 : 1.0;
             const double g = 80.0 * kU64;
-            const double Cs = -wave_sum(act ? w.y * dVx - w.x * dVy : 0.0);
             const double Ca = wave_sum(act ? fabs(w.y * dVx) + fabs(w.x * dVy) : 0.0);
-            soL = sg * Cs - g * Ca;  // <= sg C
+            soL = sg * soC - g * Ca;  // <= sg C
             soMx = fabs(wave_sum(act ? dVx : 0.0)) + g * wave_sum(act ? fabs(dVx) : 0.0);
             soMy = fabs(wave_sum(act ? dVy : 0.0)) + g * wave_sum(act ? fabs(dVy) : 0.0);
         }

@@ -51,22 +51,25 @@ def polygons():
            ("sliver", np.array([[0.0, 0.0], [1.0, 0.0], [0.5, 1e-7]])),
            ("sliver cw far", np.array([[1e4, 3e3], [1e4 + 0.5, 3e3 + 1e-6], [1e4 + 1.0, 3e3]])),
            ("tiny far", W.circle_polygon(8, 1e-4, (1e4, -2e4), rng)),
-           ("needle", placed_convex(rng, 12, 1e4, 10.0, 0.0))]
+           ("needle", placed_convex(rng, 12, 1e4, 10.0, 0.0)),
+           ("tiny very far", W.circle_polygon(16, 1e-3, (3e6, -1e6), rng)),
+           ("far needle", placed_convex(rng, 24, 1e3, 1e-2, 1e6))]
     for n in (3, 5, 16, 33, 64):
         out.append((f"circle {n}", W.circle_polygon(n, 1.0, (0.03, -0.02), rng)))
         out.append((f"irregular {n}", placed_convex(rng, n, 30.0, 100.0, 1e3)))
     return out
 
 
-def binary64_area_sign(V):
-    """Sign of the signed area as the polygon's preparation sums it (binary64,
-    edges in order)."""
-    S = 0.0
-    n = len(V)
-    for i in range(n):
-        j = i - 1
-        S = S + (V[j, 0] * V[i, 1] - V[i, 0] * V[j, 1])
-    return -1 if 0.5 * S < 0.0 else 1
+def orientation(V):
+    """Sign of C = -sum(V'_y dV_x - V'_x dV_y) over the binary64 rounded edge
+    vectors of Algorithm 2, exactly (twice the signed area when the edge
+    vectors close up); wherever the bound SO is positive, the preparation's
+    binary64 value of C has this sign."""
+    Vp = np.roll(V, 1, 0)
+    d = V - Vp
+    C = -sum(Fr(float(Vp[i, 1])) * Fr(float(d[i, 0])) - Fr(float(Vp[i, 0])) * Fr(float(d[i, 1]))
+             for i in range(len(V)))
+    return -1 if C < 0 else 1
 
 
 def f32(x):
@@ -82,7 +85,7 @@ def test_outside_bound_is_sound(P, matrix):
         assert int(t[7]) == 0, name
         assert 0.0 < SO <= 0.5 * RQ, (name, SO, RQ)
         KS = max(KA, KB)
-        sg = binary64_area_sign(V)
+        sg = orientation(V)
         n = len(V)
         Vp = np.roll(V, 1, 0)
         d = V - Vp  # binary64 rounded edge vectors of Algorithm 2
